@@ -1,0 +1,119 @@
+"""Oracle pins from free-electron closed forms (P1, P2, P3)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import lindhard
+from oracle.lattice import response_basis
+
+
+def _run(w, iq, st=None):
+    st = oracle.build_states(w) if st is None else st
+    return st, oracle.run_q(w, st, iq)
+
+
+@pytest.mark.parametrize("iq", [0, 1, 2])
+def test_p1_ksampled_lindhard_all_bands(iq):
+    """chi0_GG of the full oracle (eigensolver, G-shift maps, pair densities,
+    BLAS contraction) equals the plane-wave Lindhard sum written directly."""
+    w = workloads.feg_tiny()
+    st, r = _run(w, iq)
+    om = r.omegas
+    for g in {r.iG0, 0, len(r.basis) - 1}:
+        ref, mu = lindhard.ksampled_chi0(w.cell, w.kgrid, w.ecut_wf, w.n_bands,
+                                         w.qs[iq], tuple(r.basis[g]), om, w.eta,
+                                         w.temperatures[iq], w.n_electrons,
+                                         w.f_trans_thr)
+        got = r.chi0[:, g, g]
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref)) + 1e-300
+        assert abs(mu - st.mu) < 1e-13
+    off = r.chi0 - np.einsum("wgg->wg", r.chi0)[:, :, None] * np.eye(len(r.basis))
+    assert np.max(np.abs(off)) <= 1e-14 * np.max(np.abs(r.chi0))
+
+
+def test_p1_truncated_band_set_snaps_multiplets():
+    w = workloads.feg_tiny().with_(n_bands=12, f_trunc=1.0)
+    st, r = _run(w, 1)
+    nbs = {len(e) for e in st.eps}
+    assert min(nbs) > 12                            # snapping moved the cut
+    ref, _ = lindhard.ksampled_chi0(w.cell, w.kgrid, w.ecut_wf, w.n_bands, w.qs[1],
+                                    (0, 0, 0), r.omegas, w.eta, w.temperatures[1],
+                                    w.n_electrons, w.f_trans_thr)
+    got = r.chi0[:, r.iG0, r.iG0]
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_p3_rpa_dyson_scalar_for_free_electrons():
+    """V = 0: chi0 is diagonal, so chi_00 = chi0_00 / (1 - v_0 chi0_00)."""
+    w = workloads.feg_tiny()
+    st, r = _run(w, 0)
+    c = r.chi0[:, r.iG0, r.iG0]
+    v0 = r.K[r.iG0, r.iG0].real
+    ref = c / (1.0 - v0 * c)
+    assert np.max(np.abs(r.chi00 - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("q,w", [(0.9, 0.3), (0.9, 1.2), (0.3, 0.05), (2.0, 2.5)])
+def test_p2_continuum_closed_form_vs_quadrature(q, w):
+    """eta -> 0 closed form of Im chi0 against the log-integral at tiny eta."""
+    n = workloads.paper_h_density()
+    T = lindhard.fermi_energy(n)
+    mu = lindhard.continuum_mu(n, T)
+    quad = lindhard.continuum_chi0(q, w, 1e-9, T, mu)
+    closed = lindhard.continuum_im_chi0(q, w, T, mu)
+    assert abs(quad.imag - closed) <= 1e-6 * abs(closed) + 1e-12
+
+
+def test_continuum_mu_limits():
+    """Sommerfeld (T << E_F) and classical (T >> E_F) limits of mu(n, T)."""
+    n = workloads.paper_h_density()
+    ef = lindhard.fermi_energy(n)
+    T = 0.01 * ef
+    mu = lindhard.continuum_mu(n, T)
+    assert abs(mu - (ef - math.pi ** 2 * T ** 2 / (12 * ef))) < 1e-6 * ef
+    T = 200 * ef
+    lam3 = (2 * math.pi / T) ** 1.5
+    mu = lindhard.continuum_mu(n, T)
+    assert abs(mu / T - math.log(n * lam3 / 2)) < 1e-3
+
+
+def test_continuum_density_integral():
+    """n = 2 int d^3k/(2pi)^3 f reproduces the input density at theta = 1."""
+    n = workloads.paper_h_density()
+    T = lindhard.fermi_energy(n)
+    mu = lindhard.continuum_mu(n, T)
+    from scipy import integrate
+    val, _ = integrate.quad(lambda k: k * k / (1 + math.exp(min((0.5 * k * k - mu) / T, 700))),
+                            0, 20, limit=400, epsabs=1e-15)
+    assert abs(val / math.pi ** 2 - n) < 1e-10 * n
+
+
+@pytest.mark.slow
+def test_p2_ksampled_itcf_approaches_continuum():
+    """The k-grid noise that dominates S(q, w) at small eta is largely
+    averaged out in F(q, tau) (the premise of the paper's Sec. 2).
+
+    On a 6^3 grid with eta = 0.01 Ha the pointwise S error against the
+    continuum is tens of percent while F(q, tau) agrees to a few percent.
+    """
+    w = workloads.feg_c1().with_(kgrid=(6, 6, 6), ecut_wf=6.0, n_bands=56,
+                                 qs=((6, 0, 0),))
+    st = oracle.build_states(w)
+    r = oracle.run_q(w, st, 0)
+    n = r.density
+    T = w.temperatures[0]
+    mu = lindhard.continuum_mu(n, T)
+    q = 2 * math.pi / 7.0
+    om = r.omegas
+    c0 = np.array([lindhard.continuum_chi0(q, x, w.eta, T, mu) for x in om])
+    v = 4 * math.pi / q ** 2
+    chi = c0 / (1 - v * c0)
+    S = oracle.dsf(chi, om, r.beta, n)
+    F = oracle.itcf(S, om, r.beta, r.taus)
+    s_err = np.max(np.abs(r.S - S)) / np.max(S)
+    f_err = np.max(np.abs(r.F - F) / F)
+    assert s_err > 3 * f_err
+    assert f_err < 0.05
