@@ -1,0 +1,274 @@
+/*
+ * tdx.h -- C ABI of the MI355X (gfx950) library for the linear-response
+ * TDDFT route to the dynamic structure factor and the imaginary-time
+ * correlation function of arXiv 2510.01875:
+ *
+ *   Kohn-Sham states -> transitions -> pair densities -> chi0 (Adler-Wiser)
+ *   -> Dyson with K = v + f_xc -> S(q,w) (Eq. 8, detailed balance)
+ *   -> F(q,tau) (Eq. 1).
+ *
+ * Units: Hartree atomic units throughout.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: TDX_OK (0) or a negative TDX_ERR_* code.  On error the
+ *    outputs are left unchanged unless stated otherwise and tdx_last_error()
+ *    returns a message for the calling thread.  Nothing throws or aborts
+ *    across this boundary.
+ *  - "device" pointers are HIP device allocations owned by the caller; the
+ *    library never frees them.  "host" pointers are read (or written)
+ *    before the call returns.  Workspaces are owned by the context.
+ *  - Work is enqueued on the given HIP stream (NULL = default stream) in a
+ *    fixed order; results are bitwise reproducible run to run.  Calls that
+ *    must read a count or a status back to the host synchronise the stream;
+ *    their descriptions say so.
+ *  - Arrays are row-major.  Complex numbers are stored as interleaved
+ *    (re, im) pairs of the stated real type.
+ *  - Miller triples m give G = m1 b1 + m2 b2 + m3 b3 (b_i reciprocal rows).
+ *  - k-points form the Monkhorst-Pack grid
+ *      k_r = sum_i (2 r_i + 1 - N_i) / (2 N_i) b_i,  r_i = 0..N_i-1,
+ *    flattened with r_3 fastest.  A momentum transfer is given by an integer
+ *    triple qj: q = sum_i qj_i / N_i b_i, so that k + q = k' + G_s exactly.
+ */
+#ifndef TDX_H
+#define TDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TDX_ABI_VERSION 1
+
+enum {
+  TDX_OK = 0,
+  TDX_ERR_INVALID_ARG = -1, /* null pointer, bad enum, non-finite input   */
+  TDX_ERR_SHAPE = -2,       /* sizes inconsistent or capacity too small    */
+  TDX_ERR_ALLOC = -3,       /* workspace above the context limit / OOM     */
+  TDX_ERR_HIP = -4,         /* a HIP / rocSOLVER call failed               */
+  TDX_ERR_NUMERIC = -5,     /* singular Dyson matrix, NaN, no mu bracket   */
+  TDX_ERR_UNSUPPORTED = -6  /* device is not gfx950                        */
+};
+
+/* Arithmetic of the chi0 contraction.  Weights, states, Dyson and S/F are
+ * always FP64. */
+enum {
+  TDX_PREC_FP64 = 0,   /* FP64 products, FP64 accumulation (MFMA f64)     */
+  TDX_PREC_FP32 = 1,   /* FP32 products, FP32 accumulation per K-chunk,   */
+                       /* FP64 across chunks                               */
+  TDX_PREC_BF16X3 = 2  /* x = hi + lo (bf16, round-to-nearest-even),       */
+                       /* hi*hi + hi*lo + lo*hi in FP32 per K-chunk, FP64  */
+                       /* across chunks                                    */
+};
+
+enum { TDX_XC_RPA = 0, TDX_XC_ALDA = 1 };
+
+typedef struct tdx_ctx tdx_ctx;
+typedef void *tdx_stream; /* hipStream_t */
+
+/* ------------------------------------------------------------------ */
+/* Context                                                              */
+/* ------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  Fails with UNSUPPORTED if the
+ * device is not gfx950.  *out receives the context (host). */
+int tdx_create(int device, tdx_ctx **out);
+int tdx_destroy(tdx_ctx *ctx);
+/* Message of the last failed call on this thread ("" if none). */
+const char *tdx_last_error(void);
+int tdx_abi_version(void);
+/* Cap on the library-owned workspace (bytes, 0 = no cap).  A call whose
+ * workspace would exceed the cap fails with TDX_ERR_ALLOC before it writes
+ * any output. */
+int tdx_set_workspace_limit(tdx_ctx *ctx, size_t bytes);
+
+/* ------------------------------------------------------------------ */
+/* Model and Kohn-Sham states (FP64)                                   */
+/* ------------------------------------------------------------------ */
+
+/* Local pseudopotential V(G) = v(|G|) sum_I exp(-i G.R_I), V(0) = 0.
+ * v on the shells |G|^2 = shell_unit^2 * shell_n2[j] is shell_v[j]; off
+ * those shells v = 0, or, if gauss != 0, the Gaussian-regularised Coulomb
+ * form factor -4 pi Z exp(-sigma^2 G^2/2) / (Omega G^2).  The model is
+ * non-self-consistent (the paper's states are self-consistent DFT,
+ * Sec. A.1). */
+typedef struct {
+  double cell[9];          /* rows a1, a2, a3 (bohr)                       */
+  int kgrid[3];            /* Monkhorst-Pack sizes                         */
+  double ecut_wf;          /* plane waves with 1/2|k+G|^2 <= ecut_wf       */
+  int n_bands;             /* bands kept, moved up to the end of a         */
+                           /* multiplet (gap < 1e-6 Ha); 0 = all           */
+  double n_electrons;      /* electrons per cell (spin-unpolarised)        */
+  double f_trunc;          /* the highest kept band must have f < f_trunc  */
+  int n_atoms;             /* ions                                         */
+  const double *positions; /* host [n_atoms][3] cartesian bohr             */
+  double shell_unit;       /* bohr^-1                                      */
+  int n_shells;
+  const int *shell_n2;     /* host [n_shells]                              */
+  const double *shell_v;   /* host [n_shells] Ha                           */
+  int gauss;               /* 0/1                                          */
+  double z_ion, sigma;
+} tdx_model;
+
+typedef struct {
+  int n_k;      /* prod(kgrid)                                             */
+  int npw_max;  /* largest plane-wave basis over the grid                  */
+  int nb_max;   /* band capacity: n_bands + 64 (or npw_max if all)         */
+} tdx_states_dims;
+
+/* Host-only: sizes needed by tdx_build_states. */
+int tdx_states_query(const tdx_model *model, tdx_states_dims *out);
+
+/* Device-resident states.  The caller allocates every buffer with the
+ * sizes from tdx_states_query and fills in the pointers and dims. */
+typedef struct {
+  int n_k, npw_max, nb_max;
+  int *npw;       /* device [n_k]                                          */
+  int *nb;        /* device [n_k] kept band count                          */
+  int *miller;    /* device [n_k][npw_max][3], basis of each k             */
+  double *eps;    /* device [n_k][nb_max] eigenvalues, ascending           */
+  double *occ;    /* device [n_k][nb_max] Fermi-Dirac occupations          */
+  double *coef;   /* device complex128 [n_k][nb_max][npw_max], band rows,  */
+                  /* zero beyond npw[k]                                    */
+  int kgrid[3];       /* out (host): Monkhorst-Pack sizes                  */
+  int mmax[3];        /* out (host): largest |Miller index| per axis       */
+  double cell[9];     /* out (host): rows a1, a2, a3                       */
+  double bvec[9];     /* out (host): reciprocal rows b1, b2, b3            */
+  double mu;          /* out (host): chemical potential                    */
+  double temperature; /* out (host)                                        */
+  double omega_cell;  /* out (host): cell volume                           */
+} tdx_states;
+
+/* Plane-wave Hamiltonian H_GG'(k) = 1/2|k+G|^2 delta + V(G-G') on every
+ * k of the grid, dense FP64 eigensolve, band count snapped to a multiplet
+ * end, chemical potential by bisection on (2/N_k) sum f = N_e, Fermi-Dirac
+ * occupations at `temperature`.  Synchronises the stream.
+ * Errors: SHAPE if the snapped band count exceeds nb_max, NUMERIC if the
+ * top kept band has f >= f_trunc or the electron count cannot be met. */
+int tdx_build_states(tdx_ctx *ctx, const tdx_model *model, double temperature,
+                     tdx_states *st, tdx_stream stream);
+
+/* Occupations and mu of existing states at another temperature (same
+ * orbitals: the model is non-self-consistent).  Synchronises. */
+int tdx_occupations(tdx_ctx *ctx, tdx_states *st, double temperature,
+                    double n_electrons, double f_trunc, tdx_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Response basis (host geometry)                                      */
+/* ------------------------------------------------------------------ */
+
+/* B(q) = {G : 1/2|q+G|^2 <= ecut_chi, q+G != 0}, sorted by |q+G|^2 then
+ * Miller triple.  Writes up to `capacity` triples to miller_out (host,
+ * [capacity][3]), the count to *n_out and the index of G = 0 (the
+ * reported q+G = q element) to *i_g0.  SHAPE if capacity is too small
+ * (*n_out still set); INVALID_ARG if G = 0 is outside the basis. */
+int tdx_response_basis(const double cell[9], const int kgrid[3], const int qj[3],
+                       double ecut_chi, int *miller_out, int capacity, int *n_out,
+                       int *i_g0);
+
+/* ------------------------------------------------------------------ */
+/* Transitions                                                          */
+/* ------------------------------------------------------------------ */
+
+/* T(q) = {(k,n,m): |f_nk - f_m,k+q| > thr}, ordered by k, then n, then m.
+ * Device arrays of capacity `capacity` entries (caller-owned):
+ *   k[T] int32, n[T] int32, m[T] int32,
+ *   delta[T] = eps_m(k+q) - eps_n(k) (FP64), df[T] = f_n - f_m (FP64),
+ *   k_offsets[n_k + 1] int64 (CSR by k).
+ * The count is always written to *count (host).  With capacity < count
+ * nothing else is written and SHAPE is returned: call once with
+ * capacity 0 to size the buffers.  Synchronises. */
+typedef struct {
+  int64_t capacity;
+  int *k, *n, *m;
+  double *delta, *df;
+  int64_t *k_offsets;
+} tdx_translist;
+
+int tdx_transitions(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
+                    double thr, tdx_translist *tl, int64_t *count,
+                    tdx_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Pair densities                                                       */
+/* ------------------------------------------------------------------ */
+
+/* rho_t(G) = <n k| e^{-i(q+G).r} |m k+q> = sum_G1 c*_nk(G1) c_m,k'(G1+G+G_s)
+ * for every transition t and response vector G (basis from
+ * tdx_response_basis, copied to device: gbasis [n_g][3] int32).
+ * Computed in FP64; stored per `prec`, row stride ld = n_g rounded up to a
+ * multiple of 16 (zero-padded):
+ *   FP64:   complex128 P[T][ld]
+ *   FP32:   complex64  P[T][ld]
+ *   BF16X3: bf16 quads [T][ld][4] = (re_hi, im_hi, re_lo, im_lo), with
+ *           x32 = fp32(x), hi = RNE_bf16(x32), lo = RNE_bf16(x32 - hi).
+ * P must hold tdx_pair_density_bytes(...) bytes. */
+size_t tdx_pair_density_bytes(int64_t n_trans, int n_g, int prec);
+int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
+                     const tdx_translist *tl, int64_t n_trans,
+                     const int *gbasis, int n_g, int prec, void *P,
+                     tdx_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* chi0 (Adler-Wiser), the MFMA contraction                             */
+/* ------------------------------------------------------------------ */
+
+/* chi0_GG'(q,w) = pref * sum_t df_t / (w - delta_t + i eta) rho_t(G) rho_t(G')*
+ * with pref = 2 / (N_k Omega) supplied by the caller.  The weights are
+ * formed in FP64 in-kernel; the products run in `prec` (see TDX_PREC_*).
+ * omega: device [n_w] FP64.  chi0: device complex128 [n_w][n_g][n_g].
+ * The sum over t is split into fixed chunks reduced in a fixed order. */
+int tdx_chi0(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans,
+             const void *P, int n_g, int prec, const double *omega, int n_w,
+             double eta, double pref, double *chi0, tdx_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* Kernel K = v + f_xc and the Dyson solve (FP64)                      */
+/* ------------------------------------------------------------------ */
+
+/* K_GG' = 4 pi / |q+G|^2 delta_GG' + f_xc(G - G').  For TDX_XC_ALDA,
+ * f_xc(G) = (1/N_r) sum_j f_xc(n(r_j)) e^{-i G.r_j} on the real-space
+ * grid r_j = sum_i (j_i/N_i) a_i (dens_grid[3]), with
+ * n(r_j) = 2/(N_k Omega) sum_kn f_nk |sum_G c_nk(G) e^{i G.r_j}|^2 and
+ * f_xc = d^2(n eps_xc)/dn^2 for Slater exchange + PW92 correlation (the
+ * local form of the paper's adiabatic kernel, Sec. A.1).  States with
+ * f_nk < 1e-20 are skipped (their weight is below FP64 resolution).
+ * K: device complex128 [n_g][n_g].  SHAPE if a grid side is smaller than
+ * the span of a wavefunction basis.  Synchronises for ALDA. */
+int tdx_kernel_matrix(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
+                      const int *gbasis, int n_g, int xc, const int dens_grid[3],
+                      double *K, tdx_stream stream);
+
+/* chi_{00}(w) for every w: solve (1 - chi0(w) K) x = chi0(w) e_{i_g0} by LU
+ * with partial pivoting and return x_{i_g0}.  chi0: device complex128
+ * [n_w][n_g][n_g]; K: device complex128 [n_g][n_g]; chi00 out: device
+ * complex128 [n_w].  Synchronises to check pivots: NUMERIC if a pivot is
+ * zero or not finite (outputs then undefined for that w only). */
+int tdx_dyson(tdx_ctx *ctx, const double *chi0, const double *K, int n_g,
+              int n_w, int i_g0, double *chi00, tdx_stream stream);
+
+/* ------------------------------------------------------------------ */
+/* S(q,w) and F(q,tau) (FP64)                                          */
+/* ------------------------------------------------------------------ */
+
+/* Fluctuation-dissipation theorem (Eq. 8) in the normalisation
+ * S = -Im chi / (pi n (1 - e^{-beta w})), valid for either sign of w; at
+ * w = 0 exactly S = -Im chi(w1) / (pi n beta w1) from the next point.
+ * chi00: device complex128 [n_w]; omega, S: device FP64 [n_w]. */
+int tdx_dsf(tdx_ctx *ctx, const double *chi00, const double *omega, int n_w,
+            double beta, double density, double *S, tdx_stream stream);
+
+/* Two-sided Laplace transform (Eq. 1) on the w >= 0 grid with the negative
+ * half from detailed balance S(-w) = e^{-beta w} S(w):
+ * F(tau) = sum_j c_j S_j (e^{-tau w_j} + e^{-(beta - tau) w_j}), c_j the
+ * composite-trapezoid weights.  S, omega: device [n_w]; tau, F: device
+ * [n_tau]. */
+int tdx_itcf(tdx_ctx *ctx, const double *S, const double *omega, int n_w,
+             double beta, const double *tau, int n_tau, double *F,
+             tdx_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDX_H */

@@ -1,0 +1,424 @@
+"""Python binding of the tdx HIP library (libtdx.so, gfx950).
+
+Argument marshalling only: every step of the chi0 -> Dyson -> S -> F path
+runs in the library's HIP kernels.  PyTorch supplies device memory and the
+HIP stream.  Names follow the C ABI in include/tdx.h.
+
+The library is built in-tree by ``paper_2510_01875_amd.build``; importing
+this package without it raises immediately (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtdx.so")
+
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+XC = {"rpa": 0, "alda": 1}
+
+OK, ERR_INVALID_ARG, ERR_SHAPE, ERR_ALLOC, ERR_HIP, ERR_NUMERIC, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+
+
+class TdxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tdx error {code}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2510_01875_amd.build` (no CPU fallback exists)")
+    return C.CDLL(LIB_PATH)
+
+
+_lib = _load()
+
+c_int_p = C.POINTER(C.c_int)
+c_dbl_p = C.POINTER(C.c_double)
+
+
+class Model(C.Structure):
+    _fields_ = [("cell", C.c_double * 9), ("kgrid", C.c_int * 3), ("ecut_wf", C.c_double),
+                ("n_bands", C.c_int), ("n_electrons", C.c_double), ("f_trunc", C.c_double),
+                ("n_atoms", C.c_int), ("positions", c_dbl_p), ("shell_unit", C.c_double),
+                ("n_shells", C.c_int), ("shell_n2", c_int_p), ("shell_v", c_dbl_p),
+                ("gauss", C.c_int), ("z_ion", C.c_double), ("sigma", C.c_double)]
+
+
+class StatesDims(C.Structure):
+    _fields_ = [("n_k", C.c_int), ("npw_max", C.c_int), ("nb_max", C.c_int)]
+
+
+class StatesC(C.Structure):
+    _fields_ = [("n_k", C.c_int), ("npw_max", C.c_int), ("nb_max", C.c_int),
+                ("npw", C.c_void_p), ("nb", C.c_void_p), ("miller", C.c_void_p),
+                ("eps", C.c_void_p), ("occ", C.c_void_p), ("coef", C.c_void_p),
+                ("kgrid", C.c_int * 3), ("mmax", C.c_int * 3), ("cell", C.c_double * 9),
+                ("bvec", C.c_double * 9), ("mu", C.c_double), ("temperature", C.c_double),
+                ("omega_cell", C.c_double)]
+
+
+class TransC(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("k", C.c_void_p), ("n", C.c_void_p),
+                ("m", C.c_void_p), ("delta", C.c_void_p), ("df", C.c_void_p),
+                ("k_offsets", C.c_void_p)]
+
+
+def _sig(name, args):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = C.c_int
+    return f
+
+
+_lib.tdx_last_error.restype = C.c_char_p
+_lib.tdx_last_error.argtypes = []
+_lib.tdx_pair_density_bytes.restype = C.c_size_t
+_lib.tdx_pair_density_bytes.argtypes = [C.c_int64, C.c_int, C.c_int]
+_create = _sig("tdx_create", [C.c_int, C.POINTER(C.c_void_p)])
+_destroy = _sig("tdx_destroy", [C.c_void_p])
+_set_limit = _sig("tdx_set_workspace_limit", [C.c_void_p, C.c_size_t])
+_abi = _sig("tdx_abi_version", [])
+_query = _sig("tdx_states_query", [C.POINTER(Model), C.POINTER(StatesDims)])
+_build = _sig("tdx_build_states", [C.c_void_p, C.POINTER(Model), C.c_double,
+                                   C.POINTER(StatesC), C.c_void_p])
+_occ = _sig("tdx_occupations", [C.c_void_p, C.POINTER(StatesC), C.c_double, C.c_double,
+                                C.c_double, C.c_void_p])
+_basis = _sig("tdx_response_basis", [C.c_double * 9, C.c_int * 3, C.c_int * 3, C.c_double,
+                                     c_int_p, C.c_int, c_int_p, c_int_p])
+_trans = _sig("tdx_transitions", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3, C.c_double,
+                                  C.POINTER(TransC), C.POINTER(C.c_int64), C.c_void_p])
+_pair = _sig("tdx_pair_density", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
+                                  C.POINTER(TransC), C.c_int64, C.c_void_p, C.c_int, C.c_int,
+                                  C.c_void_p, C.c_void_p])
+_chi0 = _sig("tdx_chi0", [C.c_void_p, C.POINTER(TransC), C.c_int64, C.c_void_p, C.c_int,
+                          C.c_int, C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_void_p,
+                          C.c_void_p])
+_kmat = _sig("tdx_kernel_matrix", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3, C.c_void_p,
+                                   C.c_int, C.c_int, C.c_int * 3, C.c_void_p, C.c_void_p])
+_dyson = _sig("tdx_dyson", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                            C.c_void_p, C.c_void_p])
+_dsf = _sig("tdx_dsf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double,
+                        C.c_void_p, C.c_void_p])
+_itcf = _sig("tdx_itcf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_void_p,
+                          C.c_int, C.c_void_p, C.c_void_p])
+
+EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
+            "tdx_set_workspace_limit", "tdx_states_query", "tdx_build_states",
+            "tdx_occupations", "tdx_response_basis", "tdx_transitions",
+            "tdx_pair_density_bytes", "tdx_pair_density", "tdx_chi0", "tdx_kernel_matrix",
+            "tdx_dyson", "tdx_dsf", "tdx_itcf"]
+
+
+def check(code):
+    if code != OK:
+        raise TdxError(code, _lib.tdx_last_error().decode())
+    return code
+
+
+def abi_version():
+    return _abi()
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    assert t.is_cuda and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- context
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        check(_create(device, C.byref(h)))
+        self.handle = h
+
+    def set_workspace_limit(self, nbytes: int):
+        check(_set_limit(self.handle, nbytes))
+
+    def close(self):
+        if self.handle:
+            _destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------- states
+def make_model(w, keep=None) -> Model:
+    """tdx_model from a workload definition; `keep` holds the host arrays."""
+    p = w.potential
+    pos = np.ascontiguousarray(np.asarray(p.positions, dtype=np.float64).reshape(-1))
+    sn = np.ascontiguousarray(np.asarray(p.shell_n2, dtype=np.int32))
+    sv = np.ascontiguousarray(np.asarray(p.shell_v, dtype=np.float64))
+    if keep is not None:
+        keep.extend([pos, sn, sv])
+    m = Model()
+    m.cell[:] = list(np.asarray(w.cell, dtype=np.float64).reshape(-1))
+    m.kgrid[:] = list(w.kgrid)
+    m.ecut_wf = w.ecut_wf
+    m.n_bands = w.n_bands
+    m.n_electrons = w.n_electrons
+    m.f_trunc = w.f_trunc
+    m.n_atoms = len(p.positions)
+    m.positions = pos.ctypes.data_as(c_dbl_p)
+    m.shell_unit = p.shell_unit
+    m.n_shells = len(p.shell_n2)
+    m.shell_n2 = sn.ctypes.data_as(c_int_p)
+    m.shell_v = sv.ctypes.data_as(c_dbl_p)
+    m.gauss = int(p.gauss)
+    m.z_ion = p.z_ion
+    m.sigma = p.sigma
+    return m
+
+
+class States:
+    """Device-resident Kohn-Sham states (tensors own the memory)."""
+
+    def __init__(self, dims: StatesDims, device):
+        dev = torch.device("cuda", device)
+        self.npw = torch.zeros(dims.n_k, dtype=torch.int32, device=dev)
+        self.nb = torch.zeros(dims.n_k, dtype=torch.int32, device=dev)
+        self.miller = torch.zeros((dims.n_k, dims.npw_max, 3), dtype=torch.int32, device=dev)
+        self.eps = torch.zeros((dims.n_k, dims.nb_max), dtype=torch.float64, device=dev)
+        self.occ = torch.zeros((dims.n_k, dims.nb_max), dtype=torch.float64, device=dev)
+        self.coef = torch.zeros((dims.n_k, dims.nb_max, dims.npw_max), dtype=torch.complex128,
+                                device=dev)
+        c = StatesC()
+        c.n_k, c.npw_max, c.nb_max = dims.n_k, dims.npw_max, dims.nb_max
+        c.npw, c.nb, c.miller = self.npw.data_ptr(), self.nb.data_ptr(), self.miller.data_ptr()
+        c.eps, c.occ, c.coef = self.eps.data_ptr(), self.occ.data_ptr(), self.coef.data_ptr()
+        self.c = c
+
+    @property
+    def mu(self):
+        return self.c.mu
+
+    @property
+    def temperature(self):
+        return self.c.temperature
+
+    @property
+    def omega_cell(self):
+        return self.c.omega_cell
+
+    @property
+    def n_k(self):
+        return self.c.n_k
+
+
+def states_query(w) -> StatesDims:
+    keep = []
+    d = StatesDims()
+    check(_query(C.byref(make_model(w, keep)), C.byref(d)))
+    return d
+
+
+def build_states(ctx: Context, w, temperature: Optional[float] = None, stream=None) -> States:
+    keep = []
+    m = make_model(w, keep)
+    d = StatesDims()
+    check(_query(C.byref(m), C.byref(d)))
+    st = States(d, ctx.device)
+    T = w.temperatures[0] if temperature is None else temperature
+    check(_build(ctx.handle, C.byref(m), T, C.byref(st.c), _stream(stream)))
+    return st
+
+
+def occupations(ctx: Context, st: States, temperature: float, n_electrons: float,
+                f_trunc: float = 1e-5, stream=None):
+    check(_occ(ctx.handle, C.byref(st.c), temperature, n_electrons, f_trunc, _stream(stream)))
+
+
+# ---------------------------------------------------------- response basis
+def response_basis(cell, kgrid, qj, ecut_chi):
+    """(Miller int32 [N_G,3] host array, index of G = 0)."""
+    cellc = (C.c_double * 9)(*np.asarray(cell, dtype=np.float64).reshape(-1))
+    kg = (C.c_int * 3)(*kgrid)
+    q = (C.c_int * 3)(*qj)
+    n = C.c_int()
+    g0 = C.c_int()
+    code = _basis(cellc, kg, q, ecut_chi, None, 0, C.byref(n), C.byref(g0))
+    if code not in (OK, ERR_SHAPE):
+        check(code)
+    out = np.zeros((max(n.value, 1), 3), dtype=np.int32)
+    check(_basis(cellc, kg, q, ecut_chi, out.ctypes.data_as(c_int_p), n.value, C.byref(n),
+                 C.byref(g0)))
+    return out[: n.value], g0.value
+
+
+# ------------------------------------------------------------- transitions
+class Transitions:
+    def __init__(self, count, device):
+        dev = torch.device("cuda", device)
+        cap = max(int(count), 1)
+        self.count = int(count)
+        self.k = torch.zeros(cap, dtype=torch.int32, device=dev)
+        self.n = torch.zeros(cap, dtype=torch.int32, device=dev)
+        self.m = torch.zeros(cap, dtype=torch.int32, device=dev)
+        self.delta = torch.zeros(cap, dtype=torch.float64, device=dev)
+        self.df = torch.zeros(cap, dtype=torch.float64, device=dev)
+        self.k_offsets = None
+        c = TransC()
+        c.capacity = self.count
+        c.k, c.n, c.m = self.k.data_ptr(), self.n.data_ptr(), self.m.data_ptr()
+        c.delta, c.df = self.delta.data_ptr(), self.df.data_ptr()
+        self.c = c
+
+    def __len__(self):
+        return self.count
+
+
+def transitions(ctx: Context, st: States, qj, thr: float, stream=None) -> Transitions:
+    q = (C.c_int * 3)(*qj)
+    probe = TransC()
+    probe.capacity = 0
+    cnt = C.c_int64()
+    code = _trans(ctx.handle, C.byref(st.c), q, thr, C.byref(probe), C.byref(cnt), _stream(stream))
+    if code not in (OK, ERR_SHAPE):
+        check(code)
+    tr = Transitions(cnt.value, ctx.device)
+    tr.k_offsets = torch.zeros(st.n_k + 1, dtype=torch.int64, device=st.eps.device)
+    tr.c.k_offsets = tr.k_offsets.data_ptr()
+    check(_trans(ctx.handle, C.byref(st.c), q, thr, C.byref(tr.c), C.byref(cnt), _stream(stream)))
+    return tr
+
+
+# ---------------------------------------------------------- pair densities
+def pair_density_bytes(n_trans, n_g, prec):
+    return _lib.tdx_pair_density_bytes(n_trans, n_g, PREC[prec])
+
+
+def pair_density(ctx: Context, st: States, qj, tr: Transitions, gbasis: torch.Tensor,
+                 prec: str = "fp64", stream=None) -> torch.Tensor:
+    """P as a flat uint8 device buffer in the layout tdx.h documents."""
+    n_g = gbasis.shape[0]
+    nbytes = pair_density_bytes(len(tr), n_g, prec)
+    P = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=st.eps.device)
+    q = (C.c_int * 3)(*qj)
+    check(_pair(ctx.handle, C.byref(st.c), q, C.byref(tr.c), len(tr), _ptr(gbasis), n_g,
+                PREC[prec], _ptr(P), _stream(stream)))
+    return P
+
+
+def pair_density_view(P: torch.Tensor, n_trans: int, n_g: int, prec: str) -> torch.Tensor:
+    """complex view [T, N_G] of an FP64/FP32 pair-density buffer."""
+    ld = (n_g + 15) // 16 * 16
+    if prec == "fp64":
+        v = P[: n_trans * ld * 16].view(torch.complex128)
+    elif prec == "fp32":
+        v = P[: n_trans * ld * 8].view(torch.complex64)
+    else:
+        raise ValueError("bf16x3 quads have no complex view")
+    return v.view(n_trans, ld)[:, :n_g]
+
+
+# ------------------------------------------------------------------ chi0
+def chi0(ctx: Context, tr: Transitions, P: torch.Tensor, n_g: int, prec: str,
+         omega: torch.Tensor, eta: float, pref: float, out: Optional[torch.Tensor] = None,
+         stream=None) -> torch.Tensor:
+    n_w = omega.shape[0]
+    if out is None:
+        out = torch.empty((n_w, n_g, n_g), dtype=torch.complex128, device=omega.device)
+    check(_chi0(ctx.handle, C.byref(tr.c), len(tr), _ptr(P), n_g, PREC[prec], _ptr(omega), n_w,
+                eta, pref, _ptr(out), _stream(stream)))
+    return out
+
+
+def kernel_matrix(ctx: Context, st: States, qj, gbasis: torch.Tensor, xc: str,
+                  dens_grid=(0, 0, 0), stream=None) -> torch.Tensor:
+    n_g = gbasis.shape[0]
+    K = torch.empty((n_g, n_g), dtype=torch.complex128, device=gbasis.device)
+    q = (C.c_int * 3)(*qj)
+    dg = (C.c_int * 3)(*dens_grid)
+    check(_kmat(ctx.handle, C.byref(st.c), q, _ptr(gbasis), n_g, XC[xc], dg, _ptr(K),
+                _stream(stream)))
+    return K
+
+
+def dyson(ctx: Context, chi0_t: torch.Tensor, K: torch.Tensor, i_g0: int,
+          stream=None) -> torch.Tensor:
+    n_w, n_g, _ = chi0_t.shape
+    out = torch.empty(n_w, dtype=torch.complex128, device=chi0_t.device)
+    check(_dyson(ctx.handle, _ptr(chi0_t), _ptr(K), n_g, n_w, i_g0, _ptr(out), _stream(stream)))
+    return out
+
+
+def dsf(ctx: Context, chi00: torch.Tensor, omega: torch.Tensor, beta: float, density: float,
+        stream=None) -> torch.Tensor:
+    S = torch.empty(omega.shape[0], dtype=torch.float64, device=omega.device)
+    check(_dsf(ctx.handle, _ptr(chi00), _ptr(omega), omega.shape[0], beta, density, _ptr(S),
+               _stream(stream)))
+    return S
+
+
+def itcf(ctx: Context, S: torch.Tensor, omega: torch.Tensor, beta: float, tau: torch.Tensor,
+         stream=None) -> torch.Tensor:
+    F = torch.empty(tau.shape[0], dtype=torch.float64, device=tau.device)
+    check(_itcf(ctx.handle, _ptr(S), _ptr(omega), omega.shape[0], beta, _ptr(tau),
+                tau.shape[0], _ptr(F), _stream(stream)))
+    return F
+
+
+# --------------------------------------------------------------- pipeline
+@dataclass
+class QOut:
+    qj: tuple
+    basis: np.ndarray
+    i_g0: int
+    n_trans: int
+    omega: torch.Tensor
+    chi0: Optional[torch.Tensor]
+    K: torch.Tensor
+    chi00: torch.Tensor
+    S: torch.Tensor
+    tau: torch.Tensor
+    F: torch.Tensor
+    beta: float
+    density: float
+
+
+def run_q(ctx: Context, w, st: States, iq: int, prec: str = "fp64", omega=None,
+          keep_chi0: bool = True, stream=None) -> QOut:
+    """transitions -> pair densities -> chi0 -> K -> Dyson -> S -> F for one q."""
+    dev = st.eps.device
+    qj = tuple(w.qs[iq])
+    T = w.temperatures[iq]
+    if abs(st.temperature - T) > 0:
+        occupations(ctx, st, T, w.n_electrons, w.f_trunc, stream)
+    basis, i_g0 = response_basis(w.cell, w.kgrid, qj, w.ecut_chi[iq])
+    gb = torch.from_numpy(basis).to(dev)
+    tr = transitions(ctx, st, qj, w.f_trans_thr, stream)
+    P = pair_density(ctx, st, qj, tr, gb, prec, stream)
+    om = torch.as_tensor(w.omega_grid(iq) if omega is None else np.asarray(omega, dtype=np.float64),
+                         device=dev)
+    pref = 2.0 / (st.n_k * st.omega_cell)
+    c0 = chi0(ctx, tr, P, len(basis), prec, om, w.eta, pref, stream=stream)
+    del P
+    K = kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid, stream)
+    c00 = dyson(ctx, c0, K, i_g0, stream)
+    beta = 1.0 / T
+    n = w.n_electrons / st.omega_cell
+    S = dsf(ctx, c00, om, beta, n, stream)
+    tau = torch.as_tensor(w.tau_grid(iq), device=dev)
+    F = itcf(ctx, S, om, beta, tau, stream)
+    return QOut(qj, basis, i_g0, len(tr), om, c0 if keep_chi0 else None, K, c00, S, tau, F,
+                beta, n)

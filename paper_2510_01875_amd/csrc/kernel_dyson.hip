@@ -1,0 +1,439 @@
+// Interaction kernel K = v + f_xc and the Dyson solve, both FP64.
+//
+// K_GG' = 4 pi / |q+G|^2 delta_GG' + f_xc(G - G').  The ALDA part uses the
+// density on the real-space grid r_j = sum_i (j_i/N_i) a_i,
+//   n(r_j) = 2/(N_k Omega) sum_kn f_nk |sum_G c_nk(G) e^{i G.r_j}|^2,
+// the local kernel f_xc(n) = d^2(n eps_xc)/dn^2 (Slater exchange + PW92
+// correlation, Phys. Rev. B 45, 13244 (1992)), and
+//   f_xc(G) = (1/N_r) sum_j f_xc(r_j) e^{-i G.r_j}.
+// Both transforms are separable DFTs (three passes of 1D pencil sums with a
+// twiddle table) on a box held in LDS.
+//
+// Dyson: chi = chi0 + chi0 K chi, column G0 by LU with partial pivoting of
+// (1 - chi0 K), one workgroup per frequency.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace tdx {
+namespace {
+
+constexpr int kMaxSide = 32;
+constexpr double kOccSkip = 1e-20;
+
+// One pass of 1D DFTs along `axis` of an N0 x N1 x N2 box in LDS (in place:
+// each thread owns whole pencils).  sign = +1: sum_m x_m e^{+2 pi i m j/N}.
+__device__ void dft_pass(double2 *box, const double2 *tw, int N0, int N1, int N2, int axis,
+                         double sign) {
+  const int Na = axis == 0 ? N0 : (axis == 1 ? N1 : N2);
+  const int npen = N0 * N1 * N2 / Na;
+  const int stride = axis == 0 ? N1 * N2 : (axis == 1 ? N2 : 1);
+  for (int p = threadIdx.x; p < npen; p += blockDim.x) {
+    int base;
+    if (axis == 0) {
+      base = p;  // p = i1 * N2 + i2
+    } else if (axis == 1) {
+      base = (p / N2) * N1 * N2 + (p % N2);
+    } else {
+      base = p * N2;
+    }
+    double2 v[kMaxSide];
+    for (int m = 0; m < Na; ++m) v[m] = box[base + m * stride];
+    for (int j = 0; j < Na; ++j) {
+      double re = 0.0, im = 0.0;
+      int idx = 0;  // (m * j) mod Na
+      for (int m = 0; m < Na; ++m) {
+        const double2 t = tw[idx];
+        const double ti = sign * t.y;
+        re = fma(v[m].x, t.x, fma(-v[m].y, ti, re));
+        im = fma(v[m].x, ti, fma(v[m].y, t.x, im));
+        idx += j;
+        if (idx >= Na) idx -= Na;
+      }
+      box[base + j * stride] = make_double2(re, im);
+    }
+  }
+}
+
+// Twiddle tables for the three axes: tw + off[a], e^{2 pi i t / N_a}.
+__device__ void make_twiddles(double2 *tw, int N0, int N1, int N2) {
+  const int Ns[3] = {N0, N1, N2};
+  int off = 0;
+  for (int a = 0; a < 3; ++a) {
+    for (int t = threadIdx.x; t < Ns[a]; t += blockDim.x) {
+      double s, c;
+      sincospi(2.0 * t / Ns[a], &s, &c);
+      tw[off + t] = make_double2(c, s);
+    }
+    off += Ns[a];
+  }
+}
+
+// Per-k density partial: dens[k][j] = sum_n f_nk |u_nk(r_j)|^2.
+__global__ void __launch_bounds__(256)
+    k_density(const double2 *coef, const double *occ, const int *nb, const int *npw,
+              const int *miller, int nb_max, int npw_max, int N0, int N1, int N2,
+              double *dens) {
+  extern __shared__ double2 sm[];
+  const int Nr = N0 * N1 * N2;
+  double2 *box = sm;
+  double2 *tw = sm + Nr;
+  const int k = blockIdx.x;
+  make_twiddles(tw, N0, N1, N2);
+  double *out = dens + (size_t)k * Nr;
+  for (int j = threadIdx.x; j < Nr; j += blockDim.x) out[j] = 0.0;
+  const int nbk = nb[k], np = npw[k];
+  const int *mk = miller + (size_t)k * npw_max * 3;
+  for (int n = 0; n < nbk; ++n) {
+    const double f = occ[(size_t)k * nb_max + n];
+    if (!(f >= kOccSkip)) continue;
+    __syncthreads();
+    for (int j = threadIdx.x; j < Nr; j += blockDim.x) box[j] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const double2 *c = coef + ((size_t)k * nb_max + n) * npw_max;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+      const int a = ((mk[3 * i] % N0) + N0) % N0;
+      const int b = ((mk[3 * i + 1] % N1) + N1) % N1;
+      const int d = ((mk[3 * i + 2] % N2) + N2) % N2;
+      box[(a * N1 + b) * N2 + d] = c[i];
+    }
+    __syncthreads();
+    dft_pass(box, tw + N0 + N1, N0, N1, N2, 2, 1.0);
+    __syncthreads();
+    dft_pass(box, tw + N0, N0, N1, N2, 1, 1.0);
+    __syncthreads();
+    dft_pass(box, tw, N0, N1, N2, 0, 1.0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < Nr; j += blockDim.x) {
+      const double2 u = box[j];
+      out[j] = fma(f, u.x * u.x + u.y * u.y, out[j]);
+    }
+  }
+}
+
+__device__ void pw92(double rs, double *e, double *e1, double *e2) {
+  const double A = 0.031091, a1 = 0.21370;
+  const double b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
+  const double s = sqrt(rs);
+  const double Q = 2 * A * (b1 * s + b2 * rs + b3 * rs * s + b4 * rs * rs);
+  const double Q1 = 2 * A * (0.5 * b1 / s + b2 + 1.5 * b3 * s + 2 * b4 * rs);
+  const double Q2 = 2 * A * (-0.25 * b1 / (rs * s) + 0.75 * b3 / s + 2 * b4);
+  const double L = log1p(1.0 / Q);
+  const double D = Q + Q * Q;
+  const double L1 = -Q1 / D;
+  const double L2 = -Q2 / D + Q1 * Q1 * (1 + 2 * Q) / (D * D);
+  const double g = -2 * A * (1 + a1 * rs);
+  *e = g * L;
+  *e1 = -2 * A * a1 * L + g * L1;
+  *e2 = -4 * A * a1 * L1 + g * L2;
+}
+
+// Sum the per-k partials in k order, scale, apply f_xc(n) pointwise.
+__global__ void k_fxc_real(const double *dens, int nk, int Nr, double scale, double2 *fx) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Nr) return;
+  double s = 0.0;
+  for (int k = 0; k < nk; ++k) s += dens[(size_t)k * Nr + j];
+  const double n = s * scale;
+  const double fxv = -(1.0 / 3.0) * cbrt(3.0 / M_PI) * pow(n, -2.0 / 3.0);
+  const double rs = cbrt(3.0 / (4.0 * M_PI * n));
+  double e, e1, e2;
+  pw92(rs, &e, &e1, &e2);
+  const double fcv = (rs * rs * e2 - 2.0 * rs * e1) / (9.0 * n);
+  fx[j] = make_double2(fxv + fcv, 0.0);
+}
+
+// Forward transform of f_xc on the box (one workgroup), scaled by 1/N_r.
+__global__ void __launch_bounds__(256)
+    k_fxc_forward(double2 *fx, int N0, int N1, int N2) {
+  extern __shared__ double2 sm[];
+  const int Nr = N0 * N1 * N2;
+  double2 *box = sm, *tw = sm + Nr;
+  make_twiddles(tw, N0, N1, N2);
+  for (int j = threadIdx.x; j < Nr; j += blockDim.x) box[j] = fx[j];
+  __syncthreads();
+  dft_pass(box, tw + N0 + N1, N0, N1, N2, 2, -1.0);
+  __syncthreads();
+  dft_pass(box, tw + N0, N0, N1, N2, 1, -1.0);
+  __syncthreads();
+  dft_pass(box, tw, N0, N1, N2, 0, -1.0);
+  __syncthreads();
+  const double inv = 1.0 / Nr;
+  for (int j = threadIdx.x; j < Nr; j += blockDim.x)
+    fx[j] = make_double2(box[j].x * inv, box[j].y * inv);
+}
+
+__global__ void k_assemble_k(const int *gb, int n_g, double3 q, double3 b0, double3 b1,
+                             double3 b2, const double2 *fxg, int N0, int N1, int N2, int alda,
+                             double2 *K) {
+  const int i = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_g || j >= n_g) return;
+  double2 v = make_double2(0.0, 0.0);
+  if (alda) {
+    const int a = (((gb[3 * i] - gb[3 * j]) % N0) + N0) % N0;
+    const int b = (((gb[3 * i + 1] - gb[3 * j + 1]) % N1) + N1) % N1;
+    const int c = (((gb[3 * i + 2] - gb[3 * j + 2]) % N2) + N2) % N2;
+    v = fxg[(a * N1 + b) * N2 + c];
+  }
+  if (i == j) {
+    const int *m = gb + 3 * i;
+    const double px = q.x + m[0] * b0.x + m[1] * b1.x + m[2] * b2.x;
+    const double py = q.y + m[0] * b0.y + m[1] * b1.y + m[2] * b2.y;
+    const double pz = q.z + m[0] * b0.z + m[1] * b1.z + m[2] * b2.z;
+    v.x += 4.0 * M_PI / (px * px + py * py + pz * pz);
+  }
+  K[(size_t)i * n_g + j] = v;
+}
+
+// ------------------------------------------------------------------ Dyson
+constexpr int kT = 16;
+
+// A_w = I - chi0_w K (row-major), batched over w.
+__global__ void k_one_minus(const double2 *chi0, const double2 *K, int n, double2 *A) {
+  __shared__ double2 sa[kT][kT + 1], sb[kT][kT + 1];
+  const int w = blockIdx.z;
+  const int i = blockIdx.y * kT + threadIdx.y, j = blockIdx.x * kT + threadIdx.x;
+  const double2 *C = chi0 + (size_t)w * n * n;
+  double re = 0.0, im = 0.0;
+  for (int l0 = 0; l0 < n; l0 += kT) {
+    const int la = l0 + threadIdx.x, lb = l0 + threadIdx.y;
+    sa[threadIdx.y][threadIdx.x] = (i < n && la < n) ? C[(size_t)i * n + la] : make_double2(0, 0);
+    sb[threadIdx.y][threadIdx.x] = (lb < n && j < n) ? K[(size_t)lb * n + j] : make_double2(0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int l = 0; l < kT; ++l) {
+      const double2 a = sa[threadIdx.y][l], b = sb[l][threadIdx.x];
+      re = fma(a.x, b.x, fma(-a.y, b.y, re));
+      im = fma(a.x, b.y, fma(a.y, b.x, im));
+    }
+    __syncthreads();
+  }
+  if (i < n && j < n)
+    A[(size_t)w * n * n + (size_t)i * n + j] = make_double2((i == j ? 1.0 : 0.0) - re, -im);
+}
+
+constexpr int kLuThreads = 256;
+
+__device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
+
+__device__ inline double2 cdiv(double2 a, double2 b) {
+  // Smith's algorithm
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  }
+  const double r = b.x / b.y, d = b.y + b.x * r;
+  return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+
+// LU with partial pivoting (largest |re|+|im|, lowest index on ties) of A_w,
+// right-hand side chi0_w[:, g0]; writes x[g0] and a status per frequency.
+__global__ void __launch_bounds__(kLuThreads)
+    k_lu_solve(double2 *Aall, const double2 *chi0, int n, int g0, double2 *out, int *info) {
+  extern __shared__ double2 sm[];
+  double2 *b = sm;              // [n]
+  double2 *l = sm + n;          // [n] multipliers
+  __shared__ double pv[kLuThreads];
+  __shared__ int pi[kLuThreads];
+  __shared__ int fail;
+  const int w = blockIdx.x, t = threadIdx.x;
+  double2 *A = Aall + (size_t)w * n * n;
+  const double2 *C = chi0 + (size_t)w * n * n;
+  for (int i = t; i < n; i += kLuThreads) b[i] = C[(size_t)i * n + g0];
+  if (t == 0) fail = 0;
+  __syncthreads();
+  for (int c = 0; c < n; ++c) {
+    double best = -1.0;
+    int arg = n;
+    for (int r = c + t; r < n; r += kLuThreads) {
+      const double v = cabs1(A[(size_t)r * n + c]);
+      if (v > best) {
+        best = v;
+        arg = r;
+      }
+    }
+    pv[t] = best;
+    pi[t] = arg;
+    __syncthreads();
+    for (int s = kLuThreads / 2; s > 0; s >>= 1) {
+      if (t < s) {
+        if (pv[t + s] > pv[t] || (pv[t + s] == pv[t] && pi[t + s] < pi[t])) {
+          pv[t] = pv[t + s];
+          pi[t] = pi[t + s];
+        }
+      }
+      __syncthreads();
+    }
+    const int p = pi[0];
+    const double pmax = pv[0];
+    if (!(pmax > 0.0) || !isfinite(pmax)) {
+      if (t == 0) fail = c + 1;
+      __syncthreads();
+      break;
+    }
+    if (p != c) {
+      for (int j = c + t; j < n; j += kLuThreads) {
+        const double2 x = A[(size_t)c * n + j];
+        A[(size_t)c * n + j] = A[(size_t)p * n + j];
+        A[(size_t)p * n + j] = x;
+      }
+      if (t == 0) {
+        const double2 x = b[c];
+        b[c] = b[p];
+        b[p] = x;
+      }
+    }
+    __syncthreads();
+    const double2 piv = A[(size_t)c * n + c];
+    for (int r = c + 1 + t; r < n; r += kLuThreads) l[r] = cdiv(A[(size_t)r * n + c], piv);
+    __syncthreads();
+    const int m = n - c - 1;
+    for (long e = t; e < (long)m * (m + 1); e += kLuThreads) {
+      const int r = c + 1 + (int)(e / (m + 1));
+      const int j = c + 1 + (int)(e % (m + 1));  // j == n stands for the right-hand side
+      const double2 lr = l[r];
+      if (j < n) {
+        const double2 u = A[(size_t)c * n + j];
+        double2 &a = A[(size_t)r * n + j];
+        a.x = fma(-lr.x, u.x, fma(lr.y, u.y, a.x));
+        a.y = fma(-lr.x, u.y, fma(-lr.y, u.x, a.y));
+      } else {
+        const double2 u = b[c];
+        double2 &a = b[r];
+        a.x = fma(-lr.x, u.x, fma(lr.y, u.y, a.x));
+        a.y = fma(-lr.x, u.y, fma(-lr.y, u.x, a.y));
+      }
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (t == 0) {
+      info[w] = fail;
+      out[w] = make_double2(NAN, NAN);
+    }
+    return;
+  }
+  // back substitution, x overwrites b
+  __shared__ double sr[kLuThreads], si[kLuThreads];
+  for (int r = n - 1; r >= 0; --r) {
+    double re = 0.0, im = 0.0;
+    for (int j = r + 1 + t; j < n; j += kLuThreads) {
+      const double2 a = A[(size_t)r * n + j], x = b[j];
+      re = fma(a.x, x.x, fma(-a.y, x.y, re));
+      im = fma(a.x, x.y, fma(a.y, x.x, im));
+    }
+    sr[t] = re;
+    si[t] = im;
+    __syncthreads();
+    for (int s = kLuThreads / 2; s > 0; s >>= 1) {
+      if (t < s) {
+        sr[t] += sr[t + s];
+        si[t] += si[t + s];
+      }
+      __syncthreads();
+    }
+    if (t == 0) b[r] = cdiv(make_double2(b[r].x - sr[0], b[r].y - si[0]), A[(size_t)r * n + r]);
+    __syncthreads();
+  }
+  if (t == 0) {
+    info[w] = 0;
+    out[w] = b[g0];
+  }
+}
+
+}  // namespace
+}  // namespace tdx
+
+using namespace tdx;
+
+extern "C" {
+
+int tdx_kernel_matrix(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const int *gbasis,
+                      int n_g, int xc, const int dens_grid[3], double *K, tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && st && qj && gbasis && K, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(xc == TDX_XC_RPA || xc == TDX_XC_ALDA, TDX_ERR_INVALID_ARG, "bad xc");
+  TDX_REQUIRE(n_g > 0, TDX_ERR_SHAPE, "n_g must be positive");
+  TDX_TRY(check_device(ctx));
+  hipStream_t s = as_stream(stream);
+  const double *B = st->bvec;
+  const double3 b0 = make_double3(B[0], B[1], B[2]), b1 = make_double3(B[3], B[4], B[5]),
+                b2 = make_double3(B[6], B[7], B[8]);
+  double qr[3];
+  for (int i = 0; i < 3; ++i) qr[i] = (double)qj[i] / st->kgrid[i];
+  const double3 q = make_double3(qr[0] * B[0] + qr[1] * B[3] + qr[2] * B[6],
+                                 qr[0] * B[1] + qr[1] * B[4] + qr[2] * B[7],
+                                 qr[0] * B[2] + qr[1] * B[5] + qr[2] * B[8]);
+  int N0 = 1, N1 = 1, N2 = 1;
+  double2 *fxg = nullptr;
+  if (xc == TDX_XC_ALDA) {
+    TDX_REQUIRE(dens_grid, TDX_ERR_INVALID_ARG, "ALDA needs a density grid");
+    N0 = dens_grid[0];
+    N1 = dens_grid[1];
+    N2 = dens_grid[2];
+    for (int i = 0; i < 3; ++i)
+      TDX_REQUIRE(dens_grid[i] >= 2 * st->mmax[i] + 1 && dens_grid[i] <= kMaxSide, TDX_ERR_SHAPE,
+                  "density grid side %d must lie in [%d, %d]", dens_grid[i],
+                  2 * st->mmax[i] + 1, kMaxSide);
+    const int Nr = N0 * N1 * N2;
+    const size_t lds = sizeof(double2) * (Nr + N0 + N1 + N2);
+    TDX_REQUIRE(lds <= 160 * 1024, TDX_ERR_SHAPE, "density grid of %d points exceeds LDS", Nr);
+    void *w;
+    const size_t dens_bytes = sizeof(double) * (size_t)st->n_k * Nr;
+    TDX_TRY(ws_get(ctx, WS_DENS, dens_bytes + sizeof(double2) * Nr, &w));
+    double *dens = (double *)w;
+    fxg = (double2 *)((char *)w + dens_bytes);
+    TDX_HIP(hipFuncSetAttribute((const void *)k_density, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    TDX_HIP(hipFuncSetAttribute((const void *)k_fxc_forward,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(k_density, dim3(st->n_k), dim3(256), lds, s, (const double2 *)st->coef,
+                       st->occ, st->nb, st->npw, st->miller, st->nb_max, st->npw_max, N0, N1, N2,
+                       dens);
+    TDX_HIP(hipGetLastError());
+    const double scale = 2.0 / (st->n_k * st->omega_cell);
+    hipLaunchKernelGGL(k_fxc_real, dim3((Nr + 255) / 256), dim3(256), 0, s, dens, st->n_k, Nr,
+                       scale, fxg);
+    TDX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_fxc_forward, dim3(1), dim3(256), lds, s, fxg, N0, N1, N2);
+    TDX_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_assemble_k, dim3((n_g + 63) / 64, n_g), dim3(64), 0, s, gbasis, n_g, q, b0,
+                     b1, b2, fxg, N0, N1, N2, xc == TDX_XC_ALDA ? 1 : 0, (double2 *)K);
+  TDX_HIP(hipGetLastError());
+  if (xc == TDX_XC_ALDA) TDX_HIP(hipStreamSynchronize(s));
+  return TDX_OK;
+}
+
+int tdx_dyson(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w, int i_g0,
+              double *chi00, tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && chi0 && K && chi00, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(n_g > 0 && n_w > 0 && i_g0 >= 0 && i_g0 < n_g, TDX_ERR_SHAPE, "bad sizes");
+  TDX_REQUIRE((size_t)n_g * 2 * sizeof(double2) <= 64 * 1024, TDX_ERR_SHAPE,
+              "n_g %d too large for the LU kernel", n_g);
+  TDX_TRY(check_device(ctx));
+  hipStream_t s = as_stream(stream);
+  void *w;
+  const size_t abytes = sizeof(double2) * (size_t)n_w * n_g * n_g;
+  TDX_TRY(ws_get(ctx, WS_DYSON, abytes + sizeof(int) * n_w, &w));
+  double2 *A = (double2 *)w;
+  int *info = (int *)((char *)w + abytes);
+  dim3 g((n_g + kT - 1) / kT, (n_g + kT - 1) / kT, n_w);
+  hipLaunchKernelGGL(k_one_minus, g, dim3(kT, kT), 0, s, (const double2 *)chi0,
+                     (const double2 *)K, n_g, A);
+  TDX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_lu_solve, dim3(n_w), dim3(kLuThreads), sizeof(double2) * 2 * n_g, s, A,
+                     (const double2 *)chi0, n_g, i_g0, (double2 *)chi00, info);
+  TDX_HIP(hipGetLastError());
+  std::vector<int> h(n_w);
+  TDX_HIP(hipMemcpyAsync(h.data(), info, sizeof(int) * n_w, hipMemcpyDeviceToHost, s));
+  TDX_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < n_w; ++i)
+    TDX_REQUIRE(h[i] == 0, TDX_ERR_NUMERIC, "Dyson matrix singular at frequency %d (column %d)",
+                i, h[i] - 1);
+  return TDX_OK;
+}
+
+}  // extern "C"
