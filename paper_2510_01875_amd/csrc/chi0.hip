@@ -150,7 +150,8 @@ __global__ void __launch_bounds__(256)
         acci[i][j] += fi[i][j];
       }
   }
-  // D[row][col]: lane holds rows 4*(lane/16)+j, column lane%16
+  // D[row][col], column lane%16; element j is row 4*(lane/16)+j for the
+  // f32 16x16x4 MFMA and row lane/16 + 4j for the f64 one
   const int col = gbp * 16 + (lane & 15);
 #pragma unroll
   for (int i = 0; i < kWPerWave; ++i) {
@@ -158,7 +159,7 @@ __global__ void __launch_bounds__(256)
     if (w >= n_w) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int row = gb * 16 + 4 * (lane >> 4) + j;
+      const int row = gb * 16 + (PREC == TDX_PREC_FP64 ? (lane >> 4) + 4 * j : 4 * (lane >> 4) + j);
       if (row < n_g && col < n_g)
         part[(((size_t)blockIdx.z * n_w + w) * n_g + row) * n_g + col] =
             make_double2(accr[i][j], acci[i][j]);

@@ -103,52 +103,56 @@ __global__ void k_vtable(double2 *vt, int D0, int D1, int D2, double3 b0, double
   }
 }
 
-// Column-major Hamiltonians of a batch: A[kk][i + j*lda].
-__global__ void k_build_h(double2 *A, int lda, int k0, int nkb, const int *npw,
-                          const int *miller, int npw_max, const double *kcart,
-                          const double2 *vt, int D0, int D1, int D2, double3 b0,
-                          double3 b1, double3 b2, double pad) {
+// Column-major Hamiltonians of a batch of k-points sharing the basis size
+// n: A[kk][i + j*n] for k = klist[kk].
+__global__ void k_build_h(double2 *A, int n, const int *klist, int nkb, const int *miller,
+                          int npw_max, const double *kcart, const double2 *vt, int D0, int D1,
+                          int D2, double3 b0, double3 b1, double3 b2) {
   const int i = blockIdx.x * 16 + threadIdx.x;
   const int j = blockIdx.y * 16 + threadIdx.y;
   const int kk = blockIdx.z;
-  if (i >= lda || j >= lda || kk >= nkb) return;
-  const int k = k0 + kk;
-  const int n = npw[k];
-  double2 h = make_double2(0.0, 0.0);
-  if (i < n && j < n) {
-    const int *mi = miller + ((size_t)k * npw_max + i) * 3;
-    const int *mj = miller + ((size_t)k * npw_max + j) * 3;
-    const int d0 = mi[0] - mj[0], d1 = mi[1] - mj[1], d2 = mi[2] - mj[2];
-    const long idx = ((long)(d0 + D0) * (2 * D1 + 1) + (d1 + D1)) * (2 * D2 + 1) + (d2 + D2);
-    h = vt[idx];
-    if (i == j) {
-      const double *kc = kcart + 3 * k;
-      const double px = kc[0] + mi[0] * b0.x + mi[1] * b1.x + mi[2] * b2.x;
-      const double py = kc[1] + mi[0] * b0.y + mi[1] * b1.y + mi[2] * b2.y;
-      const double pz = kc[2] + mi[0] * b0.z + mi[1] * b1.z + mi[2] * b2.z;
-      h.x += 0.5 * (px * px + py * py + pz * pz);
-      h.y = 0.0;
-    }
-  } else if (i == j) {
-    h.x = pad;  // decoupled padding, above every physical eigenvalue
+  if (i >= n || j >= n || kk >= nkb) return;
+  const int k = klist[kk];
+  const int *mi = miller + ((size_t)k * npw_max + i) * 3;
+  const int *mj = miller + ((size_t)k * npw_max + j) * 3;
+  const int d0 = mi[0] - mj[0], d1 = mi[1] - mj[1], d2 = mi[2] - mj[2];
+  const long idx = ((long)(d0 + D0) * (2 * D1 + 1) + (d1 + D1)) * (2 * D2 + 1) + (d2 + D2);
+  double2 h = vt[idx];
+  if (i == j) {
+    const double *kc = kcart + 3 * k;
+    const double px = kc[0] + mi[0] * b0.x + mi[1] * b1.x + mi[2] * b2.x;
+    const double py = kc[1] + mi[0] * b0.y + mi[1] * b1.y + mi[2] * b2.y;
+    const double pz = kc[2] + mi[0] * b0.z + mi[1] * b1.z + mi[2] * b2.z;
+    h.x += 0.5 * (px * px + py * py + pz * pz);
+    h.y = 0.0;
   }
-  A[(size_t)kk * lda * lda + (size_t)j * lda + i] = h;
+  A[(size_t)kk * n * n + (size_t)j * n + i] = h;
 }
 
-// Copy eigenpairs of a batch out; band rows, zero beyond npw.
-__global__ void k_extract(const double2 *A, const double *D, int lda, int k0, int nkb,
-                          const int *npw, int nb_max, int npw_max, double *eps,
-                          double2 *coef) {
+// flag = 1 if any eigenvector entry of the batch is not finite
+__global__ void k_finite(const double2 *A, size_t count, int *flag) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(A[i].x) || !isfinite(A[i].y)) atomicOr(flag, 1);
+}
+
+// Copy eigenpairs of a batch out as band rows, zero beyond n.
+__global__ void k_extract(const double2 *A, const double *D, int n, const int *klist, int nkb,
+                          int nb_max, int npw_max, double *eps, double2 *coef) {
   const int kk = blockIdx.y;
   const int nband = blockIdx.x;
   if (kk >= nkb || nband >= nb_max) return;
-  const int k = k0 + kk;
-  const int n = npw[k];
-  const double2 *src = A + (size_t)kk * lda * lda + (size_t)nband * lda;
+  const int k = klist[kk];
   double2 *dst = coef + ((size_t)k * nb_max + nband) * npw_max;
+  if (nband >= n) {
+    for (int i = threadIdx.x; i < npw_max; i += blockDim.x) dst[i] = make_double2(0.0, 0.0);
+    if (threadIdx.x == 0) eps[(size_t)k * nb_max + nband] = INFINITY;
+    return;
+  }
+  const double2 *src = A + (size_t)kk * n * n + (size_t)nband * n;
   for (int i = threadIdx.x; i < npw_max; i += blockDim.x)
-    dst[i] = (i < n && nband < n) ? src[i] : make_double2(0.0, 0.0);
-  if (threadIdx.x == 0) eps[(size_t)k * nb_max + nband] = D[(size_t)kk * lda + nband];
+    dst[i] = i < n ? src[i] : make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) eps[(size_t)k * nb_max + nband] = D[(size_t)kk * n + nband];
 }
 
 // Band count per k: n_bands moved up past any multiplet; flag if the
@@ -362,11 +366,11 @@ int tdx_build_states(tdx_ctx *ctx, const tdx_model *md, double T, tdx_states *st
   TDX_HIP(hipMemcpyAsync(st->npw, npw.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
   TDX_HIP(hipMemcpyAsync(st->miller, mill.data(), sizeof(int) * mill.size(), hipMemcpyHostToDevice, s));
 
-  // V(G) on the difference box, Gershgorin bound for the padding value
+  // V(G) on the box of Miller differences
   const int D0 = 2 * hb.mmax[0], D1 = 2 * hb.mmax[1], D2 = 2 * hb.mmax[2];
   const size_t nvt = (size_t)(2 * D0 + 1) * (2 * D1 + 1) * (2 * D2 + 1);
   const size_t small_bytes = sizeof(double) * (3 * nk + 3 * std::max(md->n_atoms, 1) + 64) +
-                             sizeof(int) * 64;
+                             sizeof(int) * (64 + nk);
   void *tab;
   TDX_TRY(ws_get(ctx, WS_MISC2, nvt * sizeof(double2) + small_bytes, &tab));
   double2 *d_vt = (double2 *)tab;
@@ -374,6 +378,7 @@ int tdx_build_states(tdx_ctx *ctx, const tdx_model *md, double T, tdx_states *st
   double *d_pos = d_kc + 3 * nk;
   double *d_sv = d_pos + 3 * std::max(md->n_atoms, 1);
   int *d_sn = (int *)(d_sv + 64);
+  int *d_klist = d_sn + 64;
   TDX_HIP(hipMemcpyAsync(d_kc, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice, s));
   if (md->n_atoms)
     TDX_HIP(hipMemcpyAsync(d_pos, md->positions, sizeof(double) * 3 * md->n_atoms,
@@ -389,49 +394,68 @@ int tdx_build_states(tdx_ctx *ctx, const tdx_model *md, double T, tdx_states *st
                      0, s, d_vt, D0, D1, D2, b0, b1, b2, L.volume, d_pos, md->n_atoms, d_sn,
                      d_sv, md->n_shells, md->shell_unit, md->gauss, md->z_ion, md->sigma);
   TDX_HIP(hipGetLastError());
-  std::vector<double2> hvt(nvt);
-  TDX_HIP(hipMemcpyAsync(hvt.data(), d_vt, nvt * sizeof(double2), hipMemcpyDeviceToHost, s));
-  TDX_HIP(hipStreamSynchronize(s));
-  double gersh = 0.0;
-  for (const auto &v : hvt) gersh += std::sqrt(v.x * v.x + v.y * v.y);
-  const double pad = md->ecut_wf + gersh + 1.0;
 
-  // batched eigensolve
-  const int lda = npw_max;
-  const size_t per_k = (size_t)lda * lda * sizeof(double2);
-  int kb = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, ((size_t)4 << 30) / per_k));
+  // k-points grouped by basis size: one unpadded batched eigensolve per size
+  std::vector<int> order(nk);
+  for (int k = 0; k < nk; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return npw[a] < npw[b]; });
+  TDX_HIP(hipMemcpyAsync(d_klist, order.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
+  const size_t per_max = (size_t)npw_max * npw_max * sizeof(double2);
+  const int kb_max = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, ((size_t)4 << 30) / per_max));
   void *wa, *wb;
-  TDX_TRY(ws_get(ctx, WS_EIG, per_k * kb, &wa));
-  TDX_TRY(ws_get(ctx, WS_EIG_AUX, ((size_t)2 * lda * sizeof(double) + sizeof(int)) * kb + 256, &wb));
+  TDX_TRY(ws_get(ctx, WS_EIG, per_max * kb_max, &wa));
+  TDX_TRY(ws_get(ctx, WS_EIG_AUX, ((size_t)2 * npw_max * sizeof(double) + sizeof(int)) * kb_max + 256, &wb));
   double2 *dA = (double2 *)wa;
   double *dD = (double *)wb;
-  double *dE = dD + (size_t)lda * kb;
-  int *dinfo = (int *)(dE + (size_t)lda * kb);
+  double *dE = dD + (size_t)npw_max * kb_max;
+  int *dinfo = (int *)(dE + (size_t)npw_max * kb_max);
+  int *d_flag = dinfo + kb_max;
   TDX_REQUIRE(rocblas_set_stream(ctx->blas, s) == rocblas_status_success, TDX_ERR_HIP,
               "rocblas_set_stream failed");
-  std::vector<int> hinfo(kb);
-  for (int k0 = 0; k0 < nk; k0 += kb) {
-    const int nkb = std::min(kb, nk - k0);
-    dim3 g((lda + 15) / 16, (lda + 15) / 16, nkb);
-    hipLaunchKernelGGL(k_build_h, g, dim3(16, 16), 0, s, dA, lda, k0, nkb, st->npw, st->miller,
-                       npw_max, d_kc, d_vt, D0, D1, D2, b0, b1, b2, pad);
+  std::vector<int> hinfo(kb_max + 1);
+  for (int g0 = 0; g0 < nk;) {
+    const int n = npw[order[g0]];
+    int g1 = g0;
+    while (g1 < nk && npw[order[g1]] == n && g1 - g0 < kb_max) ++g1;
+    const int nkb = g1 - g0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      dim3 g((n + 15) / 16, (n + 15) / 16, nkb);
+      hipLaunchKernelGGL(k_build_h, g, dim3(16, 16), 0, s, dA, n, d_klist + g0, nkb, st->miller,
+                         npw_max, d_kc, d_vt, D0, D1, D2, b0, b1, b2);
+      TDX_HIP(hipGetLastError());
+      // divide and conquer first; QR iteration if it returns non-finite vectors
+      rocblas_status rs =
+          attempt == 0
+              ? rocsolver_zheevd_strided_batched(ctx->blas, rocblas_evect_original,
+                                                 rocblas_fill_upper, n,
+                                                 (rocblas_double_complex *)dA, n,
+                                                 (rocblas_stride)n * n, dD, n, dE, n, dinfo, nkb)
+              : rocsolver_zheev_strided_batched(ctx->blas, rocblas_evect_original,
+                                                rocblas_fill_upper, n,
+                                                (rocblas_double_complex *)dA, n,
+                                                (rocblas_stride)n * n, dD, n, dE, n, dinfo, nkb);
+      TDX_REQUIRE(rs == rocblas_status_success, TDX_ERR_HIP, "rocsolver eigensolver failed (%d)",
+                  (int)rs);
+      TDX_HIP(hipMemsetAsync(d_flag, 0, sizeof(int), s));
+      const size_t cnt = (size_t)nkb * n * n;
+      hipLaunchKernelGGL(k_finite, dim3((unsigned)std::min<size_t>((cnt + 255) / 256, 4096)),
+                         dim3(256), 0, s, dA, cnt, d_flag);
+      TDX_HIP(hipGetLastError());
+      TDX_HIP(hipMemcpyAsync(hinfo.data(), dinfo, sizeof(int) * nkb, hipMemcpyDeviceToHost, s));
+      TDX_HIP(hipMemcpyAsync(&hinfo[kb_max], d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+      TDX_HIP(hipStreamSynchronize(s));
+      bool ok = hinfo[kb_max] == 0;
+      for (int i = 0; i < nkb; ++i) ok = ok && hinfo[i] == 0;
+      if (ok) break;
+      TDX_REQUIRE(attempt == 0, TDX_ERR_NUMERIC, "eigensolver failed for basis size %d", n);
+    }
+    hipLaunchKernelGGL(k_extract, dim3(st->nb_max, nkb), dim3(256), 0, s, dA, dD, n,
+                       d_klist + g0, nkb, st->nb_max, npw_max, st->eps, (double2 *)st->coef);
     TDX_HIP(hipGetLastError());
-    rocblas_status rs = rocsolver_zheevd_strided_batched(
-        ctx->blas, rocblas_evect_original, rocblas_fill_upper, lda,
-        (rocblas_double_complex *)dA, lda, (rocblas_stride)lda * lda, dD, lda, dE, lda, dinfo,
-        nkb);
-    TDX_REQUIRE(rs == rocblas_status_success, TDX_ERR_HIP, "rocsolver_zheevd failed (%d)", (int)rs);
-    hipLaunchKernelGGL(k_extract, dim3(st->nb_max, nkb), dim3(256), 0, s, dA, dD, lda, k0, nkb,
-                       st->npw, st->nb_max, npw_max, st->eps, (double2 *)st->coef);
-    TDX_HIP(hipGetLastError());
-    TDX_HIP(hipMemcpyAsync(hinfo.data(), dinfo, sizeof(int) * nkb, hipMemcpyDeviceToHost, s));
-    TDX_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < nkb; ++i)
-      TDX_REQUIRE(hinfo[i] == 0, TDX_ERR_NUMERIC, "eigensolver did not converge at k=%d", k0 + i);
+    g0 = g1;
   }
 
   // band counts
-  int *d_flag = dinfo;  // reuse
   TDX_HIP(hipMemsetAsync(d_flag, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_snap, dim3((nk + 127) / 128), dim3(128), 0, s, st->eps, st->npw, nk,
                      st->nb_max, md->n_bands, st->nb, d_flag);
