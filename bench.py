@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark of the chi0 -> Dyson -> S(q,w) -> F(q,tau) path on one MI355X.
+
+One step = the whole hot path for every q of the workload with the states
+already resident in HBM: transitions, pair densities, chi0, K = v + f_xc,
+Dyson, S, F.  The headline value is the chi0 contraction's algorithmic
+throughput, F_alg = 8 N_w N_G^2 T(q) flops per launch, divided by the chi0
+launch time measured with HIP events on the launch stream.  Comparison legs
+run the FP64 and FP32 contractions on the first q and report the error of
+the chosen form's S and F against the FP64 path.  The CPU baseline times
+the FP64 oracle's chi0 step on a bounded sample of the same crystal.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"bf16x3": 2516.0, "fp32": 157.3, "fp64": 78.6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def f_alg(n_w, n_g, n_t):
+    return 8.0 * n_w * n_g * n_g * n_t
+
+
+def run_step(tdx, ctx, w, st, setup, prec, qs, torch, keep=False):
+    """One pass of the path over the q indices `qs`; chi0 bracketed by events."""
+    stream = torch.cuda.current_stream()
+    out = []
+    for iq in qs:
+        T = w.temperatures[iq]
+        if st.temperature != T:
+            tdx.occupations(ctx, st, T, w.n_electrons, w.f_trunc)
+        gb, i_g0, om, tau = setup[iq]
+        qj = tuple(w.qs[iq])
+        tr = tdx.transitions(ctx, st, qj, w.f_trans_thr)
+        P = tdx.pair_density(ctx, st, qj, tr, gb, prec)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        c0 = tdx.chi0(ctx, tr, P, gb.shape[0], prec, om, w.eta, 2.0 / (st.n_k * st.omega_cell))
+        e1.record(stream)
+        del P
+        K = tdx.kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid)
+        c00 = tdx.dyson(ctx, c0, K, i_g0)
+        beta = 1.0 / T
+        S = tdx.dsf(ctx, c00, om, beta, w.n_electrons / st.omega_cell)
+        F = tdx.itcf(ctx, S, om, beta, tau)
+        out.append(dict(iq=iq, n_t=len(tr), n_g=gb.shape[0], n_w=om.shape[0], ev=(e0, e1),
+                        S=S if keep else None, F=F if keep else None))
+        del c0
+    return out
+
+
+def errors(S, Sref, F, Fref):
+    S, Sref, F, Fref = (np.asarray(x) for x in (S, Sref, F, Fref))
+    norm = float(np.max(np.abs(S - Sref)) / np.max(np.abs(Sref)))
+    m = Sref > 1e-3 * Sref.max()
+    point = float(np.max(np.abs(S[m] - Sref[m]) / Sref[m]))
+    ferr = float(np.max(np.abs(F - Fref) / np.abs(Fref)))
+    return {"S_max_rel_normwise": norm, "S_max_rel_pointwise": point, "F_max_rel": ferr}
+
+
+def cpu_baseline(w, n_w_sample=50):
+    """FP64 oracle chi0 on a bounded sample: the same crystal and q on a 4^3
+    grid (the q vector is unchanged), every tenth frequency."""
+    import oracle
+    from oracle import response
+    from oracle.lattice import response_basis
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()
+                     if i.get("user_api") == "blas"] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    N = np.asarray(w.kgrid)
+    small = (4, 4, 4)
+    qj = tuple(int(x) for x in np.asarray(w.qs[0]) * np.asarray(small) // N)
+    ws = w.with_(kgrid=small, qs=(qj,))
+    st = oracle.build_states(ws)
+    qred = np.asarray(qj) / np.asarray(small)
+    basis, _ = response_basis(st.B, qred, ws.ecut_chi[0])
+    tr = response.transitions(st, qj, ws.f_trans_thr)
+    P = response.pair_densities(st, tr, qj, basis)
+    om = w.omega_grid(0)[:: max(1, w.n_omega // n_w_sample)]
+    t0 = time.perf_counter()
+    response.chi0(tr, P, om, ws.eta, st.n_k, st.omega)
+    dt = time.perf_counter() - t0
+    fl = f_alg(len(om), len(basis), len(tr))
+    return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"{w.name} crystal and q0 on a 4^3 k-grid (T={len(tr)} transitions, "
+                       f"N_G={len(basis)}), {len(om)} of {w.n_omega} frequencies; FP64 NumPy "
+                       f"chi0 step {dt:.2f} s"),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="fcc_c2")
+    ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
+    ap.add_argument("--compare", default="fp64,fp32",
+                    help="precisions timed on the first q for comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path's sharding "
+              "over q, frequency or transition blocks is described in DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2510_01875_amd as tdx
+    import workloads
+
+    w = workloads.get(args.workload)
+    ctx = tdx.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = tdx.build_states(ctx, w, w.temperatures[0])
+    torch.cuda.synchronize()
+    t_states = time.perf_counter() - t0
+    log(f"states: {st.n_k} k, {t_states:.2f} s")
+    setup = []
+    for iq in range(len(w.qs)):
+        b, g0 = tdx.response_basis(w.cell, w.kgrid, w.qs[iq], w.ecut_chi[iq])
+        setup.append((torch.from_numpy(b).cuda(), g0,
+                      torch.as_tensor(w.omega_grid(iq), device="cuda"),
+                      torch.as_tensor(w.tau_grid(iq), device="cuda")))
+    qs = list(range(len(w.qs)))
+
+    for i in range(args.warmup):
+        run_step(tdx, ctx, w, st, setup, args.prec, qs, torch)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = []
+    for i in range(args.steps):
+        recs += run_step(tdx, ctx, w, st, setup, args.prec, qs, torch, keep=(i == 0))
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+
+    chi0_ms = [r["ev"][0].elapsed_time(r["ev"][1]) for r in recs]
+    flops = [f_alg(r["n_w"], r["n_g"], r["n_t"]) for r in recs]
+    tflops = sum(flops) / (sum(chi0_ms) * 1e-3) / 1e12
+    n_eval = sum(r["n_w"] for r in recs)
+    main_q0 = next(r for r in recs if r["iq"] == 0 and r["S"] is not None)
+
+    legs = {}
+    for prec in [p for p in args.compare.split(",") if p and p != args.prec]:
+        torch.cuda.synchronize()
+        r = run_step(tdx, ctx, w, st, setup, prec, [0], torch, keep=True)[0]
+        torch.cuda.synchronize()
+        ms = r["ev"][0].elapsed_time(r["ev"][1])
+        legs[prec] = {"chi0_tflops": f_alg(r["n_w"], r["n_g"], r["n_t"]) / (ms * 1e-3) / 1e12,
+                      "chi0_ms_q0": ms, "S": r["S"].cpu().numpy(), "F": r["F"].cpu().numpy()}
+        log(f"leg {prec}: chi0 {ms:.1f} ms, {legs[prec]['chi0_tflops']:.2f} TFLOP/s")
+    err = None
+    if "fp64" in legs:
+        err = errors(main_q0["S"].cpu().numpy(), legs["fp64"]["S"], main_q0["F"].cpu().numpy(),
+                     legs["fp64"]["F"])
+        if "fp32" in legs:
+            err["fp32"] = errors(legs["fp32"]["S"], legs["fp64"]["S"], legs["fp32"]["F"],
+                                 legs["fp64"]["F"])
+
+    per_launch = sum(flops) / len(flops)
+    avg_ms = sum(chi0_ms) / len(chi0_ms)
+    line = {
+        "metric": "chi0 TFLOP/s + S(q,w) eval/s at stated error vs FP64, plain vs split-BF16",
+        "value": tflops,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_total / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic (seeded model crystal; no paper data)",
+        "config": {"workload": w.name, "kgrid": list(w.kgrid), "n_bands": w.n_bands,
+                   "n_q": len(w.qs), "n_omega": w.n_omega,
+                   "n_g": [int(s[0].shape[0]) for s in setup],
+                   "n_trans": [r["n_t"] for r in recs[: len(qs)]], "xc": w.xc},
+        "s_eval_per_s": n_eval / t_total,
+        "chi0_ms": chi0_ms,
+        "build_states_s": t_states,
+        "plain": {p: {"chi0_tflops": v["chi0_tflops"], "chi0_ms_q0": v["chi0_ms_q0"]}
+                  for p, v in legs.items()},
+        "error_vs_fp64": err,
+        "roofline": {"bound": "mfma", "achieved": per_launch / (avg_ms * 1e-3) / 1e12,
+                     "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
+                     "frac": per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],
+                     "traffic": None,
+                     "kernel": {"bf16x3": "k_chi0_bf16x3", "fp32": "k_chi0_mfma<1>",
+                                "fp64": "k_chi0_mfma<0>"}[args.prec],
+                     "issued_mfma_frac": (3.0 if args.prec == "bf16x3" else 1.0)
+                     * per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec]},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        line["cpu_baseline"] = cpu_baseline(w)
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
