@@ -224,6 +224,61 @@ int tdx_chi0(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans,
              double eta, double pref, double *chi0, tdx_stream stream);
 
 /* ------------------------------------------------------------------ */
+/* Ragged batches of q in one persistent launch, tile autotuning        */
+/* ------------------------------------------------------------------ */
+
+/* One q-vector of a batch (all pointers device, as for tdx_chi0). */
+typedef struct {
+  const tdx_translist *tl; /* host struct; its arrays are device            */
+  int64_t n_trans;
+  const void *P;           /* pair densities of this q in the plan's prec   */
+  int n_g;
+  const double *omega;     /* device [n_w]                                  */
+  int n_w;
+  double eta, pref;
+  double *chi0;            /* device complex128 [n_w][n_g][n_g], output     */
+} tdx_chi0_item;
+
+typedef struct tdx_chi0_plan tdx_chi0_plan;
+
+/* Build the work queue of a ragged batch: for TDX_PREC_BF16X3 every
+ * (q, frequency block, G block, G' block, transition slice) tile, ordered
+ * longest first, plus the slice-partial buffers, in one device allocation
+ * owned by the plan.  The tile shape is the configured one (see
+ * tdx_chi0_set_config / tdx_autotune_chi0) of the widest basis in the batch.
+ * Other precisions run their items one launch each.  Items must stay valid
+ * until the plan is destroyed. */
+int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, int prec,
+                         tdx_chi0_plan **out);
+/* Enqueue the plan: a counter reset kernel, ONE persistent kernel in which
+ * every workgroup takes tiles from the queue until it is empty, and one
+ * batched slice reduction.  No allocation, host synchronisation or memset:
+ * the launch can be captured into a HIP graph and replayed.  Results are
+ * independent of which workgroup ran which tile (fixed-order FP64 slice
+ * reduction). */
+int tdx_chi0_plan_launch(tdx_ctx *ctx, tdx_chi0_plan *plan, tdx_stream stream);
+int tdx_chi0_plan_destroy(tdx_chi0_plan *plan);
+/* create + launch + synchronise + destroy */
+int tdx_chi0_batched(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, int prec,
+                     tdx_stream stream);
+
+/* Number of tile variants of a precision (split-BF16: frequencies per wave
+ * x G' per workgroup x chunk). */
+int tdx_chi0_variants(int prec, int *count);
+/* Tile variant (-1 = default) and slice length 2^slice_log2 used for bases
+ * of n_g vectors (size classes of 16). */
+int tdx_chi0_set_config(tdx_ctx *ctx, int prec, int n_g, int variant, int slice_log2);
+int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slice_log2);
+/* Time every variant and slice length 2^{16,18,20} on the probe item (its
+ * first max_trans transitions; probe->chi0 is overwritten), keep the fastest
+ * for the probe's size class in the context and return it.  Synchronises. */
+int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_t max_trans,
+                      int *best_variant, int *best_slice_log2, double *best_ms);
+/* Tuning cache as JSON text keyed by the gfx arch. */
+int tdx_tune_save(tdx_ctx *ctx, const char *path);
+int tdx_tune_load(tdx_ctx *ctx, const char *path);
+
+/* ------------------------------------------------------------------ */
 /* Kernel K = v + f_xc and the Dyson solve (FP64)                      */
 /* ------------------------------------------------------------------ */
 
@@ -247,6 +302,14 @@ int tdx_kernel_matrix(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
  * zero or not finite (outputs then undefined for that w only). */
 int tdx_dyson(tdx_ctx *ctx, const double *chi0, const double *K, int n_g,
               int n_w, int i_g0, double *chi00, tdx_stream stream);
+
+/* tdx_dyson without allocation or synchronisation (graph-capturable):
+ * work is a caller-owned device buffer of tdx_dyson_work_bytes(n_g, n_w)
+ * bytes, info a device int [n_w] that receives 0 or the failing column + 1
+ * (chi00 is NaN for that frequency). */
+size_t tdx_dyson_work_bytes(int n_g, int n_w);
+int tdx_dyson_async(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w,
+                    int i_g0, double *chi00, void *work, int *info, tdx_stream stream);
 
 /* ------------------------------------------------------------------ */
 /* S(q,w) and F(q,tau) (FP64)                                          */

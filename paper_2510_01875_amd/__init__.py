@@ -109,6 +109,31 @@ _dyson = _sig("tdx_dyson", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int
                             C.c_void_p, C.c_void_p])
 _dsf = _sig("tdx_dsf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double,
                         C.c_void_p, C.c_void_p])
+class Chi0ItemC(C.Structure):
+    _fields_ = [("tl", C.POINTER(TransC)), ("n_trans", C.c_int64), ("P", C.c_void_p),
+                ("n_g", C.c_int), ("omega", C.c_void_p), ("n_w", C.c_int), ("eta", C.c_double),
+                ("pref", C.c_double), ("chi0", C.c_void_p)]
+
+
+_plan_create = _sig("tdx_chi0_plan_create", [C.c_void_p, C.POINTER(Chi0ItemC), C.c_int, C.c_int,
+                                             C.POINTER(C.c_void_p)])
+_plan_launch = _sig("tdx_chi0_plan_launch", [C.c_void_p, C.c_void_p, C.c_void_p])
+_plan_destroy = _sig("tdx_chi0_plan_destroy", [C.c_void_p])
+_batched = _sig("tdx_chi0_batched", [C.c_void_p, C.POINTER(Chi0ItemC), C.c_int, C.c_int,
+                                     C.c_void_p])
+_variants = _sig("tdx_chi0_variants", [C.c_int, C.POINTER(C.c_int)])
+_set_cfg = _sig("tdx_chi0_set_config", [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int])
+_get_cfg = _sig("tdx_chi0_get_config", [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int),
+                                        C.POINTER(C.c_int)])
+_autotune = _sig("tdx_autotune_chi0", [C.c_void_p, C.POINTER(Chi0ItemC), C.c_int, C.c_int64,
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_double)])
+_tune_save = _sig("tdx_tune_save", [C.c_void_p, C.c_char_p])
+_tune_load = _sig("tdx_tune_load", [C.c_void_p, C.c_char_p])
+_lib.tdx_dyson_work_bytes.restype = C.c_size_t
+_lib.tdx_dyson_work_bytes.argtypes = [C.c_int, C.c_int]
+_dyson_async = _sig("tdx_dyson_async", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                        C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
 _itcf = _sig("tdx_itcf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_void_p,
                           C.c_int, C.c_void_p, C.c_void_p])
 
@@ -116,7 +141,10 @@ EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_set_workspace_limit", "tdx_states_query", "tdx_build_states",
             "tdx_occupations", "tdx_response_basis", "tdx_transitions",
             "tdx_pair_density_bytes", "tdx_pair_density", "tdx_chi0", "tdx_kernel_matrix",
-            "tdx_dyson", "tdx_dsf", "tdx_itcf"]
+            "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
+            "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
+            "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_autotune_chi0", "tdx_tune_save",
+            "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async"]
 
 
 def check(code):
@@ -422,3 +450,108 @@ def run_q(ctx: Context, w, st: States, iq: int, prec: str = "fp64", omega=None,
     F = itcf(ctx, S, om, beta, tau, stream)
     return QOut(qj, basis, i_g0, len(tr), om, c0 if keep_chi0 else None, K, c00, S, tau, F,
                 beta, n)
+
+
+# ------------------------------------------------------ batches and tuning
+class Chi0Item:
+    """One q of a batch; keeps the tensors it points to alive."""
+
+    def __init__(self, tr: Transitions, P: torch.Tensor, n_g: int, omega: torch.Tensor,
+                 eta: float, pref: float, out: Optional[torch.Tensor] = None):
+        n_w = omega.shape[0]
+        self.tr, self.P, self.omega = tr, P, omega
+        self.out = out if out is not None else torch.empty(
+            (n_w, n_g, n_g), dtype=torch.complex128, device=omega.device)
+        c = Chi0ItemC()
+        c.tl = C.pointer(tr.c)
+        c.n_trans = len(tr)
+        c.P = P.data_ptr()
+        c.n_g = n_g
+        c.omega = omega.data_ptr()
+        c.n_w = n_w
+        c.eta = eta
+        c.pref = pref
+        c.chi0 = self.out.data_ptr()
+        self.c = c
+
+
+def _item_array(items):
+    arr = (Chi0ItemC * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it.c
+    return arr
+
+
+class Chi0Plan:
+    """Work queue of a ragged batch; launch() is one persistent kernel
+    (split-BF16) and can be captured in a HIP graph."""
+
+    def __init__(self, ctx: Context, items, prec: str = "bf16x3"):
+        self.ctx, self.items = ctx, list(items)
+        self._arr = _item_array(self.items)
+        h = C.c_void_p()
+        check(_plan_create(ctx.handle, self._arr, len(self.items), PREC[prec], C.byref(h)))
+        self.handle = h
+
+    def launch(self, stream=None):
+        check(_plan_launch(self.ctx.handle, self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            _plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def chi0_batched(ctx: Context, items, prec: str = "bf16x3", stream=None):
+    arr = _item_array(items)
+    check(_batched(ctx.handle, arr, len(items), PREC[prec], _stream(stream)))
+    return [it.out for it in items]
+
+
+def chi0_variants(prec: str = "bf16x3") -> int:
+    n = C.c_int()
+    check(_variants(PREC[prec], C.byref(n)))
+    return n.value
+
+
+def chi0_set_config(ctx: Context, n_g: int, variant: int, slice_log2: int, prec: str = "bf16x3"):
+    check(_set_cfg(ctx.handle, PREC[prec], n_g, variant, slice_log2))
+
+
+def chi0_get_config(ctx: Context, n_g: int, prec: str = "bf16x3"):
+    v, s = C.c_int(), C.c_int()
+    check(_get_cfg(ctx.handle, PREC[prec], n_g, C.byref(v), C.byref(s)))
+    return v.value, s.value
+
+
+def autotune_chi0(ctx: Context, probe: Chi0Item, max_trans: int = 1 << 21,
+                  prec: str = "bf16x3"):
+    v, s, ms = C.c_int(), C.c_int(), C.c_double()
+    check(_autotune(ctx.handle, C.byref(probe.c), PREC[prec], max_trans, C.byref(v),
+                    C.byref(s), C.byref(ms)))
+    return v.value, s.value, ms.value
+
+
+def tune_save(ctx: Context, path: str):
+    check(_tune_save(ctx.handle, path.encode()))
+
+
+def tune_load(ctx: Context, path: str):
+    check(_tune_load(ctx.handle, path.encode()))
+
+
+def dyson_work_bytes(n_g: int, n_w: int) -> int:
+    return _lib.tdx_dyson_work_bytes(n_g, n_w)
+
+
+def dyson_async(ctx: Context, chi0_t: torch.Tensor, K: torch.Tensor, i_g0: int,
+                chi00: torch.Tensor, work: torch.Tensor, info: torch.Tensor, stream=None):
+    n_w, n_g, _ = chi0_t.shape
+    check(_dyson_async(ctx.handle, _ptr(chi0_t), _ptr(K), n_g, n_w, i_g0, _ptr(chi00),
+                       _ptr(work), _ptr(info), _stream(stream)))

@@ -1,0 +1,416 @@
+// Split-BF16 chi0 drivers: single q (grid launch), ragged batches of q in
+// one persistent launch (a plan whose launch is free of allocation, host
+// synchronisation and memset, so it can be captured in a HIP graph), the
+// slice reduction, and the tile/slice autotuner with its on-disk cache.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "chi0_batch.h"
+#include "internal.h"
+
+namespace tdx {
+namespace {
+
+constexpr int kChunkAlign = 32;   // slice lengths are multiples of every variant's chunk
+constexpr int kMinTiles = 2048;   // fill the chip: 256 CUs x 2 workgroups x 4
+
+__global__ void k_reduce_slices(const double2 *part, int n_slices, size_t per_slice, double pref,
+                                double2 *out) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per_slice;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < n_slices; ++s) {
+      const double2 v = part[(size_t)s * per_slice + i];
+      re += v.x;
+      im += v.y;
+    }
+    out[i] = make_double2(pref * re, pref * im);
+  }
+}
+
+struct ReduceItem {
+  const double2 *part;
+  int n_slices;
+  size_t per_slice;
+  double pref;
+  double2 *out;
+};
+
+// Slice reduction of every item of a batch (blockIdx.y = item).
+__global__ void k_reduce_batch(const ReduceItem *items) {
+  const ReduceItem it = items[blockIdx.y];
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < it.per_slice;
+       i += (size_t)gridDim.x * blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int s = 0; s < it.n_slices; ++s) {
+      const double2 v = it.part[(size_t)s * it.per_slice + i];
+      re += v.x;
+      im += v.y;
+    }
+    it.out[i] = make_double2(it.pref * re, it.pref * im);
+  }
+}
+
+__global__ void k_zero_int(int *p) { *p = 0; }
+
+int bucket_of(int ld) { return std::min(ld / 16, 63); }
+
+void pick(const tdx_ctx *ctx, int ld, int *variant, int *slice_log2) {
+  const tdx_chi0_tune &t = ctx->tune[bucket_of(ld)];
+  *variant = t.variant >= 0 ? t.variant : 0;
+  *slice_log2 = t.slice_log2;
+}
+
+// Slices of a transition list: about 2^slice_log2 transitions each, enough
+// of them that the tile count fills the chip, a multiple of the chunk.
+void slicing(long long n_trans, int slice_log2, long long tiles_per_slice, long long *slice_len,
+             int *slices) {
+  long long ns = std::max<long long>((n_trans + (1LL << slice_log2) - 1) >> slice_log2,
+                                     (kMinTiles + tiles_per_slice - 1) / tiles_per_slice);
+  ns = std::max<long long>(1, std::min<long long>(ns, (n_trans + kChunkAlign - 1) / kChunkAlign));
+  ns = std::min<long long>(ns, 8192);
+  long long len = (n_trans + ns - 1) / ns;
+  len = (len + kChunkAlign - 1) / kChunkAlign * kChunkAlign;
+  *slice_len = len;
+  *slices = (int)((n_trans + len - 1) / len);
+}
+
+long long tiles_per_slice(int v, int n_w, int ld) {
+  int wb, cols;
+  bf16x3_variant_shape(v, &wb, &cols);
+  return (long long)((n_w + wb - 1) / wb) * (ld / 16) * ((ld + cols - 1) / cols);
+}
+
+}  // namespace
+
+int chi0_bf16x3_with(tdx_ctx *ctx, int v, int slice_log2, const void *P, int ld,
+                     const double *delta, const double *df, long long n_trans,
+                     const double *omega, int n_w, double eta, int n_g, double pref,
+                     double2 *chi0, hipStream_t s) {
+  long long slice_len;
+  int slices;
+  slicing(n_trans, slice_log2, tiles_per_slice(v, n_w, ld), &slice_len, &slices);
+  const size_t out_elems = (size_t)n_w * n_g * n_g;
+  void *w;
+  TDX_TRY(ws_get(ctx, WS_PARTIAL, sizeof(double2) * out_elems * slices, &w));
+  double2 *part = (double2 *)w;
+  TDX_TRY(bf16x3_launch_grid(v, P, ld, delta, df, n_trans, slice_len, slices, omega, n_w, eta,
+                             n_g, part, s));
+  const unsigned rb = (unsigned)std::min<size_t>((out_elems + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_reduce_slices, dim3(rb), dim3(256), 0, s, part, slices, out_elems, pref,
+                     chi0);
+  TDX_HIP(hipGetLastError());
+  return TDX_OK;
+}
+
+int chi0_bf16x3(tdx_ctx *ctx, const void *P, int ld, const double *delta, const double *df,
+                long long n_trans, const double *omega, int n_w, double eta, int n_g,
+                double pref, double2 *chi0, hipStream_t s) {
+  int v, sl;
+  pick(ctx, ld, &v, &sl);
+  return chi0_bf16x3_with(ctx, v, sl, P, ld, delta, df, n_trans, omega, n_w, eta, n_g, pref,
+                          chi0, s);
+}
+
+}  // namespace tdx
+
+// ------------------------------------------------------------------ plans
+struct tdx_chi0_plan {
+  int device = 0;
+  int prec = 0;
+  int variant = 0;
+  int n_items = 0, n_tiles = 0, n_blocks = 0;
+  void *mem = nullptr;  // one device allocation for everything below
+  tdx::BatchItem *items = nullptr;
+  tdx::BatchTile *tiles = nullptr;
+  tdx::ReduceItem *reduce = nullptr;
+  int *counter = nullptr;
+  size_t max_per_slice = 0;
+  std::vector<tdx_chi0_item> host_items;  // for the non-persistent precisions
+};
+
+using namespace tdx;
+
+extern "C" {
+
+int tdx_chi0_variants(int prec, int *count) {
+  clear_error();
+  TDX_REQUIRE(count, TDX_ERR_INVALID_ARG, "count is null");
+  *count = prec == TDX_PREC_BF16X3 ? bf16x3_variant_count() : 1;
+  return TDX_OK;
+}
+
+int tdx_chi0_set_config(tdx_ctx *ctx, int prec, int n_g, int variant, int slice_log2) {
+  clear_error();
+  TDX_REQUIRE(ctx, TDX_ERR_INVALID_ARG, "ctx is null");
+  TDX_REQUIRE(prec == TDX_PREC_BF16X3, TDX_ERR_UNSUPPORTED, "only split-BF16 has variants");
+  TDX_REQUIRE(variant >= -1 && variant < bf16x3_variant_count(), TDX_ERR_INVALID_ARG,
+              "bad variant %d", variant);
+  TDX_REQUIRE(slice_log2 >= 10 && slice_log2 <= 30, TDX_ERR_INVALID_ARG, "bad slice_log2");
+  TDX_REQUIRE(n_g > 0, TDX_ERR_INVALID_ARG, "bad n_g");
+  tdx_chi0_tune &t = ctx->tune[bucket_of((n_g + 15) / 16 * 16)];
+  t.variant = variant;
+  t.slice_log2 = slice_log2;
+  return TDX_OK;
+}
+
+int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slice_log2) {
+  clear_error();
+  TDX_REQUIRE(ctx && variant && slice_log2, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(prec == TDX_PREC_BF16X3, TDX_ERR_UNSUPPORTED, "only split-BF16 has variants");
+  pick(ctx, (n_g + 15) / 16 * 16, variant, slice_log2);
+  return TDX_OK;
+}
+
+int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, int prec,
+                         tdx_chi0_plan **out) {
+  clear_error();
+  TDX_REQUIRE(ctx && items && out && n_items > 0, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(prec >= TDX_PREC_FP64 && prec <= TDX_PREC_BF16X3, TDX_ERR_INVALID_ARG, "bad prec");
+  for (int i = 0; i < n_items; ++i) {
+    const tdx_chi0_item &it = items[i];
+    TDX_REQUIRE(it.tl && it.P && it.omega && it.chi0, TDX_ERR_INVALID_ARG,
+                "item %d has a null pointer", i);
+    TDX_REQUIRE(it.n_g > 0 && it.n_w > 0 && it.n_trans > 0 && it.n_trans <= it.tl->capacity,
+                TDX_ERR_SHAPE, "item %d has bad sizes", i);
+    TDX_REQUIRE(std::isfinite(it.eta) && it.eta > 0 && std::isfinite(it.pref),
+                TDX_ERR_INVALID_ARG, "item %d has a bad eta or prefactor", i);
+  }
+  TDX_TRY(check_device(ctx));
+  tdx_chi0_plan *p = new tdx_chi0_plan();
+  p->device = ctx->device;
+  p->prec = prec;
+  p->n_items = n_items;
+  p->host_items.assign(items, items + n_items);
+  if (prec != TDX_PREC_BF16X3) {
+    *out = p;
+    return TDX_OK;
+  }
+  // one tile variant for the whole launch: the configuration of the widest basis
+  int ld_max = 0;
+  for (int i = 0; i < n_items; ++i) ld_max = std::max(ld_max, (items[i].n_g + 15) / 16 * 16);
+  int v, sl_default;
+  pick(ctx, ld_max, &v, &sl_default);
+  p->variant = v;
+  int wb, cols;
+  bf16x3_variant_shape(v, &wb, &cols);
+  std::vector<BatchItem> bi(n_items);
+  std::vector<ReduceItem> ri(n_items);
+  std::vector<BatchTile> tiles;
+  size_t part_bytes = 0;
+  std::vector<size_t> part_off(n_items);
+  for (int i = 0; i < n_items; ++i) {
+    const tdx_chi0_item &it = items[i];
+    const int ld = (it.n_g + 15) / 16 * 16;
+    int vi, sl;
+    pick(ctx, ld, &vi, &sl);
+    long long slice_len;
+    int slices;
+    slicing(it.n_trans, sl, tiles_per_slice(v, it.n_w, ld), &slice_len, &slices);
+    const size_t per = (size_t)it.n_w * it.n_g * it.n_g;
+    part_off[i] = part_bytes;
+    part_bytes += per * slices * sizeof(double2);
+    p->max_per_slice = std::max(p->max_per_slice, per);
+    bi[i] = BatchItem{it.P, ld, it.tl->delta, it.tl->df, (long long)it.n_trans, slice_len,
+                      it.omega, it.n_w, it.eta, it.n_g, nullptr};
+    ri[i] = ReduceItem{nullptr, slices, per, it.pref, (double2 *)it.chi0};
+    const int nwb = (it.n_w + wb - 1) / wb, ngb = ld / 16, ncb = (ld + cols - 1) / cols;
+    for (int s = 0; s < slices; ++s)
+      for (int a = 0; a < nwb; ++a)
+        for (int g = 0; g < ngb; ++g)
+          for (int c = 0; c < ncb; ++c) tiles.push_back(BatchTile{i, a, g, c, s});
+  }
+  // longest tiles first (the last slice of an item is shorter)
+  std::stable_sort(tiles.begin(), tiles.end(), [&](const BatchTile &a, const BatchTile &b) {
+    auto len = [&](const BatchTile &t) {
+      const BatchItem &x = bi[t.item];
+      return std::min(x.slice_len, x.n_trans - t.slice * x.slice_len);
+    };
+    return len(a) > len(b);
+  });
+  TDX_REQUIRE(tiles.size() < (size_t)1 << 30, TDX_ERR_SHAPE, "too many tiles");
+  const size_t off_items = (part_bytes + 255) / 256 * 256;
+  const size_t off_reduce = off_items + (sizeof(BatchItem) * n_items + 255) / 256 * 256;
+  const size_t off_tiles = off_reduce + (sizeof(ReduceItem) * n_items + 255) / 256 * 256;
+  const size_t off_counter = off_tiles + (sizeof(BatchTile) * tiles.size() + 255) / 256 * 256;
+  const size_t total = off_counter + 256;
+  hipError_t e = hipMalloc(&p->mem, total);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(TDX_ERR_ALLOC, "plan allocation of %zu bytes failed", total);
+  }
+  char *base = (char *)p->mem;
+  for (int i = 0; i < n_items; ++i) {
+    bi[i].part = (double2 *)(base + part_off[i]);
+    ri[i].part = bi[i].part;
+  }
+  p->items = (BatchItem *)(base + off_items);
+  p->reduce = (ReduceItem *)(base + off_reduce);
+  p->tiles = (BatchTile *)(base + off_tiles);
+  p->counter = (int *)(base + off_counter);
+  p->n_tiles = (int)tiles.size();
+  p->n_blocks = std::max(1, std::min(p->n_tiles, 2 * std::max(ctx->n_cu, 1)));
+  int rc = TDX_OK;
+  if (hipMemcpy(p->items, bi.data(), sizeof(BatchItem) * n_items, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(p->reduce, ri.data(), sizeof(ReduceItem) * n_items, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(p->tiles, tiles.data(), sizeof(BatchTile) * tiles.size(),
+                hipMemcpyHostToDevice) != hipSuccess)
+    rc = fail(TDX_ERR_HIP, "plan upload failed");
+  if (rc != TDX_OK) {
+    hipFree(p->mem);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return TDX_OK;
+}
+
+int tdx_chi0_plan_launch(tdx_ctx *ctx, tdx_chi0_plan *p, tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && p, TDX_ERR_INVALID_ARG, "null argument");
+  hipStream_t s = as_stream(stream);
+  if (p->prec != TDX_PREC_BF16X3) {
+    for (const tdx_chi0_item &it : p->host_items)
+      TDX_TRY(tdx_chi0(ctx, it.tl, it.n_trans, it.P, it.n_g, p->prec, it.omega, it.n_w, it.eta,
+                       it.pref, it.chi0, stream));
+    return TDX_OK;
+  }
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, p->counter);
+  TDX_HIP(hipGetLastError());
+  TDX_TRY(bf16x3_launch_persistent(p->variant, p->items, p->tiles, p->n_tiles, p->counter,
+                                   p->n_blocks, s));
+  const unsigned rb = (unsigned)std::min<size_t>((p->max_per_slice + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_reduce_batch, dim3(rb, p->n_items), dim3(256), 0, s, p->reduce);
+  TDX_HIP(hipGetLastError());
+  return TDX_OK;
+}
+
+int tdx_chi0_plan_destroy(tdx_chi0_plan *p) {
+  clear_error();
+  if (!p) return TDX_OK;
+  if (p->mem) {
+    hipSetDevice(p->device);
+    hipDeviceSynchronize();
+    hipFree(p->mem);
+  }
+  delete p;
+  return TDX_OK;
+}
+
+int tdx_chi0_batched(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, int prec,
+                     tdx_stream stream) {
+  tdx_chi0_plan *p = nullptr;
+  TDX_TRY(tdx_chi0_plan_create(ctx, items, n_items, prec, &p));
+  int rc = tdx_chi0_plan_launch(ctx, p, stream);
+  if (rc == TDX_OK && hipStreamSynchronize(as_stream(stream)) != hipSuccess)
+    rc = fail(TDX_ERR_HIP, "stream synchronisation failed");
+  tdx_chi0_plan_destroy(p);
+  return rc;
+}
+
+int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_t max_trans,
+                      int *best_variant, int *best_slice_log2, double *best_ms) {
+  clear_error();
+  TDX_REQUIRE(ctx && probe && best_variant && best_slice_log2 && best_ms, TDX_ERR_INVALID_ARG,
+              "null argument");
+  TDX_REQUIRE(prec == TDX_PREC_BF16X3, TDX_ERR_UNSUPPORTED, "only split-BF16 has variants");
+  TDX_REQUIRE(probe->tl && probe->P && probe->omega && probe->chi0, TDX_ERR_INVALID_ARG,
+              "probe has a null pointer");
+  TDX_TRY(check_device(ctx));
+  const long long nt = std::min<long long>(probe->n_trans, std::max<int64_t>(max_trans, 1));
+  const int ld = (probe->n_g + 15) / 16 * 16;
+  hipStream_t s = nullptr;
+  TDX_HIP(hipStreamCreate(&s));
+  hipEvent_t e0, e1;
+  TDX_HIP(hipEventCreate(&e0));
+  TDX_HIP(hipEventCreate(&e1));
+  const int slice_opts[] = {16, 18, 20};
+  double best = 1e300;
+  int bv = 0, bs = 18;
+  int rc = TDX_OK;
+  for (int v = 0; v < bf16x3_variant_count() && rc == TDX_OK; ++v) {
+    for (int sl : slice_opts) {
+      double ms_best = 1e300;
+      for (int rep = 0; rep < 3 && rc == TDX_OK; ++rep) {
+        hipEventRecord(e0, s);
+        rc = chi0_bf16x3_with(ctx, v, sl, probe->P, ld, probe->tl->delta, probe->tl->df, nt,
+                              probe->omega, probe->n_w, probe->eta, probe->n_g, probe->pref,
+                              (double2 *)probe->chi0, s);
+        hipEventRecord(e1, s);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) ms_best = std::min(ms_best, (double)ms);
+      }
+      if (rc != TDX_OK) break;
+      if (ms_best < best) {
+        best = ms_best;
+        bv = v;
+        bs = sl;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamDestroy(s);
+  if (rc != TDX_OK) return rc;
+  tdx_chi0_tune &t = ctx->tune[bucket_of(ld)];
+  t.variant = bv;
+  t.slice_log2 = bs;
+  t.ms = best;
+  *best_variant = bv;
+  *best_slice_log2 = bs;
+  *best_ms = best;
+  return TDX_OK;
+}
+
+int tdx_tune_save(tdx_ctx *ctx, const char *path) {
+  clear_error();
+  TDX_REQUIRE(ctx && path, TDX_ERR_INVALID_ARG, "null argument");
+  FILE *f = std::fopen(path, "w");
+  TDX_REQUIRE(f, TDX_ERR_INVALID_ARG, "cannot write %s", path);
+  std::fprintf(f, "{\"arch\": \"gfx950\", \"prec\": \"bf16x3\", \"entries\": [\n");
+  bool first = true;
+  for (int b = 0; b < 64; ++b) {
+    const tdx_chi0_tune &t = ctx->tune[b];
+    if (t.variant < 0) continue;
+    std::fprintf(f, "%s  {\"blocks\": %d, \"variant\": %d, \"slice_log2\": %d, \"ms\": %.4f}",
+                 first ? "" : ",\n", b, t.variant, t.slice_log2, t.ms);
+    first = false;
+  }
+  std::fprintf(f, "\n]}\n");
+  std::fclose(f);
+  return TDX_OK;
+}
+
+int tdx_tune_load(tdx_ctx *ctx, const char *path) {
+  clear_error();
+  TDX_REQUIRE(ctx && path, TDX_ERR_INVALID_ARG, "null argument");
+  FILE *f = std::fopen(path, "r");
+  TDX_REQUIRE(f, TDX_ERR_INVALID_ARG, "cannot read %s", path);
+  char line[512];
+  bool arch_ok = false;
+  int loaded = 0;
+  while (std::fgets(line, sizeof(line), f)) {
+    if (std::strstr(line, "\"arch\": \"gfx950\"")) arch_ok = true;
+    int b, v, sl;
+    double ms;
+    if (arch_ok && std::sscanf(line, " {\"blocks\": %d, \"variant\": %d, \"slice_log2\": %d, "
+                                     "\"ms\": %lf}", &b, &v, &sl, &ms) == 4) {
+      if (b >= 0 && b < 64 && v >= 0 && v < bf16x3_variant_count() && sl >= 10 && sl <= 30) {
+        ctx->tune[b] = tdx_chi0_tune{v, sl, ms};
+        ++loaded;
+      }
+    }
+  }
+  std::fclose(f);
+  TDX_REQUIRE(arch_ok, TDX_ERR_UNSUPPORTED, "%s is not a gfx950 tuning cache", path);
+  return TDX_OK;
+}
+
+}  // extern "C"

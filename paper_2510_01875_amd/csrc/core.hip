@@ -155,6 +155,7 @@ int tdx_create(int device, tdx_ctx **out) {
   TDX_HIP(hipSetDevice(device));
   tdx_ctx *ctx = new tdx_ctx();
   ctx->device = device;
+  ctx->n_cu = prop.multiProcessorCount;
   if (rocblas_create_handle(&ctx->blas) != rocblas_status_success) {
     delete ctx;
     return fail(TDX_ERR_HIP, "rocblas_create_handle failed");

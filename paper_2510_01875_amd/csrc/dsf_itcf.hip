@@ -10,7 +10,7 @@ namespace {
 // S = -Im chi / (pi n (1 - e^{-beta w})); w = 0 takes the limit from the
 // next grid point, -Im chi(w1) / (pi n beta w1).
 __global__ void k_dsf(const double2 *chi, const double *w, int n, double beta, double dens,
-                      double *S, int *bad) {
+                      double *S) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double wi = w[i];
@@ -20,8 +20,7 @@ __global__ void k_dsf(const double2 *chi, const double *w, int n, double beta, d
   } else if (i + 1 < n && w[i + 1] > 0.0) {
     v = -chi[i + 1].y / (M_PI * dens * beta * w[i + 1]);
   } else {
-    v = NAN;
-    atomicOr(bad, 1);
+    v = NAN;  // w = 0 without a positive neighbour
   }
   S[i] = v;
 }
@@ -65,11 +64,8 @@ int tdx_dsf(tdx_ctx *ctx, const double *chi00, const double *omega, int n_w, dou
               TDX_ERR_INVALID_ARG, "bad beta or density");
   TDX_TRY(check_device(ctx));
   hipStream_t s = as_stream(stream);
-  void *w;
-  TDX_TRY(ws_get(ctx, WS_MISC, sizeof(int), &w));
-  TDX_HIP(hipMemsetAsync(w, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_dsf, dim3((n_w + 255) / 256), dim3(256), 0, s, (const double2 *)chi00,
-                     omega, n_w, beta, density, S, (int *)w);
+                     omega, n_w, beta, density, S);
   TDX_HIP(hipGetLastError());
   return TDX_OK;
 }
@@ -80,7 +76,6 @@ int tdx_itcf(tdx_ctx *ctx, const double *S, const double *omega, int n_w, double
   TDX_REQUIRE(ctx && S && omega && tau && F, TDX_ERR_INVALID_ARG, "null argument");
   TDX_REQUIRE(n_w > 0 && n_tau > 0, TDX_ERR_SHAPE, "bad sizes");
   TDX_REQUIRE(std::isfinite(beta) && beta > 0, TDX_ERR_INVALID_ARG, "bad beta");
-  TDX_TRY(check_device(ctx));
   hipLaunchKernelGGL(k_itcf, dim3(n_tau), dim3(256), 0, as_stream(stream), S, omega, n_w, beta,
                      tau, F);
   TDX_HIP(hipGetLastError());

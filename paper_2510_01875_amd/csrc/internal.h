@@ -45,11 +45,21 @@ struct Workspace {
 
 }  // namespace tdx
 
+// Tile variant and slice length of the split-BF16 chi0 kernel for one
+// response-basis size class (ld / 16 blocks); variant -1 = default.
+struct tdx_chi0_tune {
+  int variant = -1;
+  int slice_log2 = 18;
+  double ms = 0.0;
+};
+
 struct tdx_ctx {
   int device = 0;
+  int n_cu = 0;
   rocblas_handle blas = nullptr;
   size_t limit = 0;  // 0 = unlimited
   tdx::Workspace ws[8];
+  tdx_chi0_tune tune[64];
 };
 
 namespace tdx {

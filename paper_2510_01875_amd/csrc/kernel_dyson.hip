@@ -406,20 +406,20 @@ int tdx_kernel_matrix(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const
   return TDX_OK;
 }
 
-int tdx_dyson(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w, int i_g0,
-              double *chi00, tdx_stream stream) {
+size_t tdx_dyson_work_bytes(int n_g, int n_w) {
+  return sizeof(double2) * (size_t)n_w * n_g * n_g;
+}
+
+int tdx_dyson_async(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w,
+                    int i_g0, double *chi00, void *work, int *info, tdx_stream stream) {
   clear_error();
-  TDX_REQUIRE(ctx && chi0 && K && chi00, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(ctx && chi0 && K && chi00 && work && info, TDX_ERR_INVALID_ARG, "null argument");
   TDX_REQUIRE(n_g > 0 && n_w > 0 && i_g0 >= 0 && i_g0 < n_g, TDX_ERR_SHAPE, "bad sizes");
   TDX_REQUIRE((size_t)n_g * 2 * sizeof(double2) <= 64 * 1024, TDX_ERR_SHAPE,
               "n_g %d too large for the LU kernel", n_g);
-  TDX_TRY(check_device(ctx));
+  TDX_REQUIRE(n_w <= 65535, TDX_ERR_SHAPE, "n_w %d above 65535", n_w);
   hipStream_t s = as_stream(stream);
-  void *w;
-  const size_t abytes = sizeof(double2) * (size_t)n_w * n_g * n_g;
-  TDX_TRY(ws_get(ctx, WS_DYSON, abytes + sizeof(int) * n_w, &w));
-  double2 *A = (double2 *)w;
-  int *info = (int *)((char *)w + abytes);
+  double2 *A = (double2 *)work;
   dim3 g((n_g + kT - 1) / kT, (n_g + kT - 1) / kT, n_w);
   hipLaunchKernelGGL(k_one_minus, g, dim3(kT, kT), 0, s, (const double2 *)chi0,
                      (const double2 *)K, n_g, A);
@@ -427,6 +427,21 @@ int tdx_dyson(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_
   hipLaunchKernelGGL(k_lu_solve, dim3(n_w), dim3(kLuThreads), sizeof(double2) * 2 * n_g, s, A,
                      (const double2 *)chi0, n_g, i_g0, (double2 *)chi00, info);
   TDX_HIP(hipGetLastError());
+  return TDX_OK;
+}
+
+int tdx_dyson(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w, int i_g0,
+              double *chi00, tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && chi0 && K && chi00, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(n_g > 0 && n_w > 0 && i_g0 >= 0 && i_g0 < n_g, TDX_ERR_SHAPE, "bad sizes");
+  TDX_TRY(check_device(ctx));
+  hipStream_t s = as_stream(stream);
+  void *w;
+  const size_t abytes = tdx_dyson_work_bytes(n_g, n_w);
+  TDX_TRY(ws_get(ctx, WS_DYSON, abytes + sizeof(int) * n_w, &w));
+  int *info = (int *)((char *)w + abytes);
+  TDX_TRY(tdx_dyson_async(ctx, chi0, K, n_g, n_w, i_g0, chi00, w, info, stream));
   std::vector<int> h(n_w);
   TDX_HIP(hipMemcpyAsync(h.data(), info, sizeof(int) * n_w, hipMemcpyDeviceToHost, s));
   TDX_HIP(hipStreamSynchronize(s));

@@ -237,7 +237,8 @@ def h16_c5(seed: int = 3) -> Workload:
                     n_tau=64, tau_half=True)
 
 
-def fcc_c4(seed: int = 4, n_q: int = 32, kgrid=(16, 16, 16)) -> Workload:
+def fcc_c4(seed: int = 4, n_q: int = 32, kgrid=(16, 16, 16), qmax: float = 4.0,
+           ecut_floor: float = 8.5) -> Workload:
     """fcc_c2 crystal with n_q seeded q-vectors and per-q temperature.
 
     |q| ~ U[0.5, 4] bohr^-1 along a normalised random integer direction in
@@ -253,7 +254,7 @@ def fcc_c4(seed: int = 4, n_q: int = 32, kgrid=(16, 16, 16)) -> Workload:
     N = np.array(kgrid)
     qs, Ts, ecs, wms = [], [], [], []
     while len(qs) < n_q:
-        mag = rng.uniform(0.5, 4.0)
+        mag = rng.uniform(0.5, qmax)
         d = rng.integers(-2, 3, size=3)
         T_ev = float(rng.choice([1.0, 2.0, 4.0, 8.0]))
         if not d.any():
@@ -266,7 +267,7 @@ def fcc_c4(seed: int = 4, n_q: int = 32, kgrid=(16, 16, 16)) -> Workload:
         qn = float(np.linalg.norm((qj / N) @ B))
         qs.append(tuple(int(x) for x in qj))
         Ts.append(ev(T_ev))
-        ecs.append(max(8.5, 0.5 * (qn + 0.5) ** 2))
+        ecs.append(max(ecut_floor, 0.5 * (qn + 0.5) ** 2))
         wms.append(min(max(2.0, 0.5 * qn * qn + 2 * qn), 11.0))
     return c2.with_(name="fcc_c4", kgrid=tuple(kgrid), qs=tuple(qs),
                     temperatures=tuple(Ts), ecut_chi=tuple(ecs), n_omega=800,
@@ -274,10 +275,9 @@ def fcc_c4(seed: int = 4, n_q: int = 32, kgrid=(16, 16, 16)) -> Workload:
 
 
 def fcc_c4_small(seed: int = 4) -> Workload:
-    """fcc_c4 at oracle size: 6 ragged q on a 4^3 grid, 40 bands."""
-    w = fcc_c4(seed=seed, n_q=6, kgrid=(4, 4, 4))
+    """fcc_c4 at oracle size: 6 ragged q (|q| <= 1.6) on a 4^3 grid, 40 bands."""
+    w = fcc_c4(seed=seed, n_q=6, kgrid=(4, 4, 4), qmax=1.6, ecut_floor=3.0)
     return w.with_(name="fcc_c4_small", ecut_wf=8.0, n_bands=40, n_omega=64,
-                   ecut_chi=tuple(min(e, 4.0) for e in w.ecut_chi),
                    dens_grid=(16, 16, 16))
 
 
