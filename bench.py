@@ -38,7 +38,8 @@ def f_alg(n_w, n_g, n_t):
 
 
 def run_step(tdx, ctx, w, st, setup, prec, qs, torch, keep=False):
-    """One pass of the path over the q indices `qs`; chi0 bracketed by events."""
+    """One pass of the path over the q indices `qs`, one chi0 launch per q,
+    chi0 bracketed by events (used for the comparison legs)."""
     stream = torch.cuda.current_stream()
     out = []
     for iq in qs:
@@ -64,6 +65,65 @@ def run_step(tdx, ctx, w, st, setup, prec, qs, torch, keep=False):
                         S=S if keep else None, F=F if keep else None))
         del c0
     return out
+
+
+class BatchedStep:
+    """The benchmark step: transitions and pair densities of every q into
+    fixed buffers, chi0 for every q (one grid launch per q, or with
+    persistent=True ONE persistent launch for all q from a plan built once),
+    then K, Dyson, S and F per q."""
+
+    def __init__(self, tdx, ctx, w, st, setup, prec, torch, persistent=False):
+        self.tdx, self.ctx, self.w, self.st, self.setup, self.prec = tdx, ctx, w, st, setup, prec
+        self.torch, self.persistent = torch, persistent
+        self.tr, self.P, self.items = [], [], []
+        pref = 2.0 / (st.n_k * st.omega_cell)
+        for iq in range(len(w.qs)):
+            self._occ(iq)
+            gb, i_g0, om, tau = setup[iq]
+            tr = tdx.transitions(ctx, st, w.qs[iq], w.f_trans_thr)
+            P = tdx.pair_density(ctx, st, w.qs[iq], tr, gb, prec)
+            self.tr.append(tr)
+            self.P.append(P)
+            self.items.append(tdx.Chi0Item(tr, P, gb.shape[0], om, w.eta, pref))
+        self.plan = tdx.Chi0Plan(ctx, self.items, prec)
+
+    def _occ(self, iq):
+        T = self.w.temperatures[iq]
+        if self.st.temperature != T:
+            self.tdx.occupations(self.ctx, self.st, T, self.w.n_electrons, self.w.f_trunc)
+
+    def __call__(self, keep=False):
+        tdx, ctx, w, st, torch = self.tdx, self.ctx, self.w, self.st, self.torch
+        for iq in range(len(w.qs)):
+            self._occ(iq)
+            gb = self.setup[iq][0]
+            n0 = len(self.tr[iq])
+            tr = tdx.transitions(ctx, st, w.qs[iq], w.f_trans_thr, out=self.tr[iq])
+            assert tr is self.tr[iq] and len(tr) == n0
+            tdx.pair_density(ctx, st, w.qs[iq], tr, gb, self.prec, out=self.P[iq])
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if self.persistent:
+            self.plan.launch()
+        else:
+            for it in self.items:
+                tdx.chi0(ctx, it.tr, it.P, it.out.shape[1], self.prec, it.omega, w.eta,
+                         it.c.pref, out=it.out)
+        e1.record(stream)
+        out = []
+        for iq in range(len(w.qs)):
+            gb, i_g0, om, tau = self.setup[iq]
+            T = w.temperatures[iq]
+            K = tdx.kernel_matrix(ctx, st, w.qs[iq], gb, w.xc, w.dens_grid)
+            c00 = tdx.dyson(ctx, self.items[iq].out, K, i_g0)
+            S = tdx.dsf(ctx, c00, om, 1.0 / T, w.n_electrons / st.omega_cell)
+            F = tdx.itcf(ctx, S, om, 1.0 / T, tau)
+            out.append(dict(iq=iq, n_t=len(self.tr[iq]), n_g=gb.shape[0], n_w=om.shape[0],
+                            S=S if keep else None, F=F if keep else None))
+        return out, (e0, e1)
 
 
 def errors(S, Sref, F, Fref):
@@ -118,6 +178,10 @@ def main():
     ap.add_argument("--compare", default="fp64,fp32",
                     help="precisions timed on the first q for comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the split-BF16 tile shape on q0 first and save the cache")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2510_01875_amd",
+                                                         "tune_gfx950.json"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path's sharding "
@@ -144,26 +208,58 @@ def main():
                       torch.as_tensor(w.omega_grid(iq), device="cuda"),
                       torch.as_tensor(w.tau_grid(iq), device="cuda")))
     qs = list(range(len(w.qs)))
+    tuned = None
+    if args.prec == "bf16x3":
+        if args.autotune:
+            b0 = setup[0][0]
+            tr0 = tdx.transitions(ctx, st, w.qs[0], w.f_trans_thr)
+            P0 = tdx.pair_density(ctx, st, w.qs[0], tr0, b0, "bf16x3")
+            probe = tdx.Chi0Item(tr0, P0, b0.shape[0], setup[0][2], w.eta,
+                                 2.0 / (st.n_k * st.omega_cell))
+            v, sl, ms = tdx.autotune_chi0(ctx, probe, max_trans=1 << 22)
+            tuned = {"variant": v, "slice_log2": sl, "probe_ms": ms, "source": "autotuned now"}
+            os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+            tdx.tune_save(ctx, os.path.join(ROOT, "gpurun_out", "tune_gfx950.json"))
+            del P0, tr0, probe
+            log(f"autotune: variant {v}, slice 2^{sl}, {ms:.1f} ms on the probe")
+        elif os.path.exists(args.tune_cache):
+            tdx.tune_load(ctx, args.tune_cache)
+            tuned = {"source": os.path.basename(args.tune_cache)}
+        v, sl = tdx.chi0_get_config(ctx, setup[0][0].shape[0])
+        tuned = dict(tuned or {"source": "default"}, variant=v, slice_log2=sl)
 
+    step = BatchedStep(tdx, ctx, w, st, setup, args.prec, torch)
     for i in range(args.warmup):
-        run_step(tdx, ctx, w, st, setup, args.prec, qs, torch)
+        step()
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    recs = []
+    recs, evs = [], []
     for i in range(args.steps):
-        recs += run_step(tdx, ctx, w, st, setup, args.prec, qs, torch, keep=(i == 0))
+        r, ev = step(keep=(i == 0))
+        recs += r
+        evs.append(ev)
         log(f"step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
 
-    chi0_ms = [r["ev"][0].elapsed_time(r["ev"][1]) for r in recs]
-    flops = [f_alg(r["n_w"], r["n_g"], r["n_t"]) for r in recs]
-    tflops = sum(flops) / (sum(chi0_ms) * 1e-3) / 1e12
+    launch_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    flops_step = sum(f_alg(r["n_w"], r["n_g"], r["n_t"]) for r in recs[: len(qs)])
+    tflops = flops_step / (sum(launch_ms) / len(launch_ms) * 1e-3) / 1e12
     n_eval = sum(r["n_w"] for r in recs)
     main_q0 = next(r for r in recs if r["iq"] == 0 and r["S"] is not None)
+    # the same step with one persistent launch for all q (ragged-batch form)
+    step.persistent = True
+    step()
+    torch.cuda.synchronize()
+    _, (p0, p1) = step()
+    torch.cuda.synchronize()
+    pers_ms = p0.elapsed_time(p1)
+    log(f"persistent batch: {pers_ms:.1f} ms")
+    step.plan.close()
+    del step
 
     legs = {}
     for prec in [p for p in args.compare.split(",") if p and p != args.prec]:
@@ -182,8 +278,8 @@ def main():
             err["fp32"] = errors(legs["fp32"]["S"], legs["fp64"]["S"], legs["fp32"]["F"],
                                  legs["fp64"]["F"])
 
-    per_launch = sum(flops) / len(flops)
-    avg_ms = sum(chi0_ms) / len(chi0_ms)
+    per_launch = flops_step
+    avg_ms = sum(launch_ms) / len(launch_ms)
     line = {
         "metric": "chi0 TFLOP/s + S(q,w) eval/s at stated error vs FP64, plain vs split-BF16",
         "value": tflops,
@@ -199,10 +295,13 @@ def main():
         "data": "synthetic (seeded model crystal; no paper data)",
         "config": {"workload": w.name, "kgrid": list(w.kgrid), "n_bands": w.n_bands,
                    "n_q": len(w.qs), "n_omega": w.n_omega,
-                   "n_g": [int(s[0].shape[0]) for s in setup],
-                   "n_trans": [r["n_t"] for r in recs[: len(qs)]], "xc": w.xc},
+                   "n_g": [int(s_[0].shape[0]) for s_ in setup],
+                   "n_trans": [r["n_t"] for r in recs[: len(qs)]], "xc": w.xc,
+                   "chi0_launch": "one grid launch per q", "tile": tuned},
         "s_eval_per_s": n_eval / t_total,
-        "chi0_ms": chi0_ms,
+        "chi0_ms_per_step": launch_ms,
+        "persistent_batch": {"chi0_ms": pers_ms, "tflops": flops_step / (pers_ms * 1e-3) / 1e12,
+                             "form": "one persistent launch for all q"},
         "build_states_s": t_states,
         "plain": {p: {"chi0_tflops": v["chi0_tflops"], "chi0_ms_q0": v["chi0_ms_q0"]}
                   for p, v in legs.items()},

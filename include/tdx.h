@@ -250,9 +250,8 @@ typedef struct tdx_chi0_plan tdx_chi0_plan;
  * until the plan is destroyed. */
 int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, int prec,
                          tdx_chi0_plan **out);
-/* Enqueue the plan: a counter reset kernel, ONE persistent kernel in which
- * every workgroup takes tiles from the queue until it is empty, and one
- * batched slice reduction.  No allocation, host synchronisation or memset:
+/* Enqueue the plan: ONE persistent kernel (two workgroups per CU) that walks
+ * the longest-first tile list round-robin, and one batched slice reduction.  No allocation, host synchronisation or memset:
  * the launch can be captured into a HIP graph and replayed.  Results are
  * independent of which workgroup ran which tile (fixed-order FP64 slice
  * reduction). */
@@ -269,7 +268,7 @@ int tdx_chi0_variants(int prec, int *count);
  * of n_g vectors (size classes of 16). */
 int tdx_chi0_set_config(tdx_ctx *ctx, int prec, int n_g, int variant, int slice_log2);
 int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slice_log2);
-/* Time every variant and slice length 2^{16,18,20} on the probe item (its
+/* Time every variant and slice length 2^{18,20} on the probe item (its
  * first max_trans transitions; probe->chi0 is overwritten), keep the fastest
  * for the probe's size class in the context and return it.  Synchronises. */
 int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_t max_trans,

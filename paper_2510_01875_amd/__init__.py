@@ -315,7 +315,9 @@ class Transitions:
         return self.count
 
 
-def transitions(ctx: Context, st: States, qj, thr: float, stream=None) -> Transitions:
+def transitions(ctx: Context, st: States, qj, thr: float, stream=None,
+                out: Optional[Transitions] = None) -> Transitions:
+    """Screened transition list; `out` (same size) is refilled in place."""
     q = (C.c_int * 3)(*qj)
     probe = TransC()
     probe.capacity = 0
@@ -323,9 +325,12 @@ def transitions(ctx: Context, st: States, qj, thr: float, stream=None) -> Transi
     code = _trans(ctx.handle, C.byref(st.c), q, thr, C.byref(probe), C.byref(cnt), _stream(stream))
     if code not in (OK, ERR_SHAPE):
         check(code)
-    tr = Transitions(cnt.value, ctx.device)
-    tr.k_offsets = torch.zeros(st.n_k + 1, dtype=torch.int64, device=st.eps.device)
-    tr.c.k_offsets = tr.k_offsets.data_ptr()
+    if out is not None and out.count == cnt.value:
+        tr = out
+    else:
+        tr = Transitions(cnt.value, ctx.device)
+        tr.k_offsets = torch.zeros(st.n_k + 1, dtype=torch.int64, device=st.eps.device)
+        tr.c.k_offsets = tr.k_offsets.data_ptr()
     check(_trans(ctx.handle, C.byref(st.c), q, thr, C.byref(tr.c), C.byref(cnt), _stream(stream)))
     return tr
 
@@ -336,11 +341,16 @@ def pair_density_bytes(n_trans, n_g, prec):
 
 
 def pair_density(ctx: Context, st: States, qj, tr: Transitions, gbasis: torch.Tensor,
-                 prec: str = "fp64", stream=None) -> torch.Tensor:
-    """P as a flat uint8 device buffer in the layout tdx.h documents."""
+                 prec: str = "fp64", stream=None,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """P as a flat uint8 device buffer in the layout tdx.h documents; `out`
+    (large enough) is overwritten in place."""
     n_g = gbasis.shape[0]
     nbytes = pair_density_bytes(len(tr), n_g, prec)
-    P = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=st.eps.device)
+    if out is not None and out.numel() >= nbytes:
+        P = out
+    else:
+        P = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=st.eps.device)
     q = (C.c_int * 3)(*qj)
     check(_pair(ctx.handle, C.byref(st.c), q, C.byref(tr.c), len(tr), _ptr(gbasis), n_g,
                 PREC[prec], _ptr(P), _stream(stream)))
@@ -459,7 +469,7 @@ class Chi0Item:
     def __init__(self, tr: Transitions, P: torch.Tensor, n_g: int, omega: torch.Tensor,
                  eta: float, pref: float, out: Optional[torch.Tensor] = None):
         n_w = omega.shape[0]
-        self.tr, self.P, self.omega = tr, P, omega
+        self.tr, self.P, self.omega, self.eta, self.pref = tr, P, omega, eta, pref
         self.out = out if out is not None else torch.empty(
             (n_w, n_g, n_g), dtype=torch.complex128, device=omega.device)
         c = Chi0ItemC()

@@ -30,6 +30,6 @@ int bf16x3_launch_grid(int v, const void *P, int ld, const double *delta, const 
                        long long n_trans, long long slice_len, int slices, const double *omega,
                        int n_w, double eta, int n_g, double2 *part, hipStream_t s);
 int bf16x3_launch_persistent(int v, const BatchItem *items, const BatchTile *tiles, int n_tiles,
-                             int *counter, int n_blocks, hipStream_t s);
+                             int n_blocks, hipStream_t s);
 
 }  // namespace tdx

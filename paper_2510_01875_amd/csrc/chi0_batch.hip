@@ -54,8 +54,6 @@ __global__ void k_reduce_batch(const ReduceItem *items) {
   }
 }
 
-__global__ void k_zero_int(int *p) { *p = 0; }
-
 int bucket_of(int ld) { return std::min(ld / 16, 63); }
 
 void pick(const tdx_ctx *ctx, int ld, int *variant, int *slice_log2) {
@@ -218,10 +216,11 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
                       it.omega, it.n_w, it.eta, it.n_g, nullptr};
     ri[i] = ReduceItem{nullptr, slices, per, it.pref, (double2 *)it.chi0};
     const int nwb = (it.n_w + wb - 1) / wb, ngb = ld / 16, ncb = (ld + cols - 1) / cols;
+    // frequency block fastest: consecutive tiles read the same rho rows
     for (int s = 0; s < slices; ++s)
-      for (int a = 0; a < nwb; ++a)
-        for (int g = 0; g < ngb; ++g)
-          for (int c = 0; c < ncb; ++c) tiles.push_back(BatchTile{i, a, g, c, s});
+      for (int g = 0; g < ngb; ++g)
+        for (int c = 0; c < ncb; ++c)
+          for (int a = 0; a < nwb; ++a) tiles.push_back(BatchTile{i, a, g, c, s});
   }
   // longest tiles first (the last slice of an item is shorter)
   std::stable_sort(tiles.begin(), tiles.end(), [&](const BatchTile &a, const BatchTile &b) {
@@ -252,7 +251,7 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
   p->tiles = (BatchTile *)(base + off_tiles);
   p->counter = (int *)(base + off_counter);
   p->n_tiles = (int)tiles.size();
-  p->n_blocks = std::max(1, std::min(p->n_tiles, 2 * std::max(ctx->n_cu, 1)));
+  p->n_blocks = std::max(8, 2 * std::max(ctx->n_cu, 1)) / 8 * 8;  // a multiple of the XCD count
   int rc = TDX_OK;
   if (hipMemcpy(p->items, bi.data(), sizeof(BatchItem) * n_items, hipMemcpyHostToDevice) !=
           hipSuccess ||
@@ -280,10 +279,7 @@ int tdx_chi0_plan_launch(tdx_ctx *ctx, tdx_chi0_plan *p, tdx_stream stream) {
                        it.pref, it.chi0, stream));
     return TDX_OK;
   }
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, p->counter);
-  TDX_HIP(hipGetLastError());
-  TDX_TRY(bf16x3_launch_persistent(p->variant, p->items, p->tiles, p->n_tiles, p->counter,
-                                   p->n_blocks, s));
+  TDX_TRY(bf16x3_launch_persistent(p->variant, p->items, p->tiles, p->n_tiles, p->n_blocks, s));
   const unsigned rb = (unsigned)std::min<size_t>((p->max_per_slice + 255) / 256, 4096);
   hipLaunchKernelGGL(k_reduce_batch, dim3(rb, p->n_items), dim3(256), 0, s, p->reduce);
   TDX_HIP(hipGetLastError());
@@ -329,7 +325,7 @@ int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_
   hipEvent_t e0, e1;
   TDX_HIP(hipEventCreate(&e0));
   TDX_HIP(hipEventCreate(&e1));
-  const int slice_opts[] = {16, 18, 20};
+  const int slice_opts[] = {18, 20};
   double best = 1e300;
   int bv = 0, bs = 18;
   int rc = TDX_OK;

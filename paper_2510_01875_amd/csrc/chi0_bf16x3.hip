@@ -15,13 +15,14 @@
 // slice of transitions.  Per chunk of CHUNK transitions the B fragments
 // (already in lane order and already rotated for the imaginary part), the
 // FP32 rho rows and the weights are staged in LDS; the next chunk's global
-// loads are in flight while the current chunk runs (two LDS buffers).  Each
-// slice sums in FP32; slices are reduced in FP64 in a fixed order, so results
-// do not depend on which workgroup ran which tile.
+// loads are in flight while the current chunk runs (two LDS buffers).  Sums
+// run in FP32 over 256 chunks and are folded into the tile's FP64 partial;
+// slices are reduced in FP64 in a fixed order, so results do not depend on
+// which workgroup ran which tile.
 //
 // Two launch forms share the tile routine: a grid with one tile per
-// workgroup, and a persistent grid that pulls tiles of many q-vectors from a
-// longest-first work queue (one launch for a ragged batch).
+// workgroup, and a persistent grid that walks the longest-first tile list of
+// many q-vectors (one launch for a ragged batch).
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
@@ -59,6 +60,8 @@ struct Cfg {
   static_assert(256 % kCols == 0 && 256 % kWBlock == 0, "tile must divide the block");
   static_assert(kNB >= 1 && kNA >= 1, "chunk too small");
 };
+
+constexpr int kFoldChunks = 256;  // chunks summed in FP32 between folds
 
 __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
@@ -154,9 +157,42 @@ __device__ inline void store_chunk(const Prefetch<C> &pf, unsigned int *buf, dou
   }
 }
 
+// Fold the FP32 accumulators into the tile's FP64 partial in global memory
+// (the workgroup owns that region): the first fold stores, later ones add.
+template <int WPW, int SUB>
+__device__ inline void fold(f32x4 (&ar)[WPW][SUB], f32x4 (&ai)[WPW][SUB], double2 *part, int n_w,
+                            int n_g, int w0, int row0, int col0, int lane, int wave, bool first) {
+#pragma unroll
+  for (int i = 0; i < WPW; ++i) {
+    const int w = w0 + wave * WPW + i;
+#pragma unroll
+    for (int b = 0; b < SUB; ++b) {
+      const int col = col0 + b * 16 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        // D[row][col]: element j of lane l is row 4*(l/16)+j, column l%16
+        const int row = row0 + 4 * (lane >> 4) + j;
+        if (w < n_w && row < n_g && col < n_g) {
+          double2 *d = part + ((size_t)w * n_g + row) * n_g + col;
+          double2 v = make_double2((double)ar[i][b][j], (double)ai[i][b][j]);
+          if (!first) {
+            const double2 o = *d;
+            v.x += o.x;
+            v.y += o.y;
+          }
+          *d = v;
+        }
+      }
+      ar[i][b] = f32x4{0, 0, 0, 0};
+      ai[i][b] = f32x4{0, 0, 0, 0};
+    }
+  }
+}
+
 // One tile: rows row0..row0+15, columns col0..col0+kCols-1, frequencies
-// w0..w0+kWBlock-1, transitions [t_lo, t_hi).  Writes the FP32 slice sum into
-// part (the slice's [n_w][n_g][n_g] block).
+// w0..w0+kWBlock-1, transitions [t_lo, t_hi).  Sums run in FP32 for at most
+// kFoldChunks chunks and are folded into part (the slice's [n_w][n_g][n_g]
+// block, FP64) between runs.
 template <int WPW, int SUB, int CHUNK>
 __device__ __attribute__((always_inline)) void chi0_tile(unsigned int *lds, const uint2 *P, int ld, const double *delta,
                           const double *df, long long n_trans, long long t_lo, long long t_hi,
@@ -192,88 +228,89 @@ __device__ __attribute__((always_inline)) void chi0_tile(unsigned int *lds, cons
   }
   __syncthreads();
   int cur = 0;
-  for (long long tc = t_lo; tc < t_hi; tc += CHUNK) {
-    const long long nx = tc + CHUNK;
-    const bool more = nx < t_hi, full = nx + CHUNK <= t_hi;
-    if (more) {
-      if (full)
-        load_chunk<C, true>(pf, P, lds_, colc, row0, delta, df, nx, n_trans, tid);
-      else
-        load_chunk<C, false>(pf, P, lds_, colc, row0, delta, df, nx, n_trans, tid);
-    }
-    const unsigned int *buf = lds + cur * C::kBufWords;
-    const u32x4 *bfr = (const u32x4 *)buf;
-    const float2 *rq = (const float2 *)(buf + C::kBWords);
-    const float2 *wt = (const float2 *)(buf + C::kBWords + C::kRhoWords);
-#pragma unroll
-    for (int s = 0; s < C::kSteps; ++s) {
-      const int tb = s * 16 + 4 * kq;
-      float2 rho[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) rho[j] = rq[(tb + j) * 16 + r];
-      u32x4 ah[WPW], al[WPW];
-#pragma unroll
-      for (int i = 0; i < WPW; ++i) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float2 w = wt[(tb + j) * C::kWBlock + wave * WPW + i];
-          const float are = fmaf(w.x, rho[j].x, -w.y * rho[j].y);
-          const float aim = fmaf(w.x, rho[j].y, w.y * rho[j].x);
-          const unsigned int h = cvt_pk(are, aim);
-          ah[i][j] = h;
-          al[i][j] = cvt_pk(are - lo_f(h), aim - hi_f(h));
-        }
+  bool first = true;
+  constexpr long long kRun = (long long)kFoldChunks * CHUNK;
+  for (long long rs = t_lo; rs < t_hi; rs += kRun) {
+    const long long re = std::min(t_hi, rs + kRun);
+    for (long long tc = rs; tc < re; tc += CHUNK) {
+      const long long nx = tc + CHUNK;
+      const bool more = nx < t_hi, full = nx + CHUNK <= t_hi;
+      if (more) {
+        if (full)
+          load_chunk<C, true>(pf, P, lds_, colc, row0, delta, df, nx, n_trans, tid);
+        else
+          load_chunk<C, false>(pf, P, lds_, colc, row0, delta, df, nx, n_trans, tid);
       }
-#pragma unroll
-      for (int b = 0; b < SUB; ++b) {
-        const u32x4 *bp = bfr + ((s * SUB + b) * 4) * 64 + lane;
-        const bf16x8 bhr = as_bf16x8(bp[0]), blr = as_bf16x8(bp[64]);
-        const bf16x8 bhi = as_bf16x8(bp[128]), bli = as_bf16x8(bp[192]);
-#pragma unroll
+      const unsigned int *buf = lds + cur * C::kBufWords;
+      const u32x4 *bfr = (const u32x4 *)buf;
+      const float2 *rq = (const float2 *)(buf + C::kBWords);
+      const float2 *wt = (const float2 *)(buf + C::kBWords + C::kRhoWords);
+  #pragma unroll
+      for (int s = 0; s < C::kSteps; ++s) {
+        const int tb = s * 16 + 4 * kq;
+        float2 rho[4];
+  #pragma unroll
+        for (int j = 0; j < 4; ++j) rho[j] = rq[(tb + j) * 16 + r];
+        u32x4 ah[WPW], al[WPW];
+  #pragma unroll
         for (int i = 0; i < WPW; ++i) {
-          const bf16x8 Ah = as_bf16x8(ah[i]), Al = as_bf16x8(al[i]);
-          f32x4 cr = ar[i][b], ci = ai[i][b];
-          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bhr, cr, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bhi, ci, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, blr, cr, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bli, ci, 0, 0, 0);
-          cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, bhr, cr, 0, 0, 0);
-          ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, bhi, ci, 0, 0, 0);
-          ar[i][b] = cr;
-          ai[i][b] = ci;
+  #pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float2 w = wt[(tb + j) * C::kWBlock + wave * WPW + i];
+            const float are = fmaf(w.x, rho[j].x, -w.y * rho[j].y);
+            const float aim = fmaf(w.x, rho[j].y, w.y * rho[j].x);
+            const unsigned int h = cvt_pk(are, aim);
+            ah[i][j] = h;
+            al[i][j] = cvt_pk(are - lo_f(h), aim - hi_f(h));
+          }
+        }
+  #pragma unroll
+        for (int b = 0; b < SUB; ++b) {
+          const u32x4 *bp = bfr + ((s * SUB + b) * 4) * 64 + lane;
+          const bf16x8 bhr = as_bf16x8(bp[0]), blr = as_bf16x8(bp[64]);
+          const bf16x8 bhi = as_bf16x8(bp[128]), bli = as_bf16x8(bp[192]);
+  #pragma unroll
+          for (int i = 0; i < WPW; ++i) {
+            const bf16x8 Ah = as_bf16x8(ah[i]), Al = as_bf16x8(al[i]);
+            f32x4 cr = ar[i][b], ci = ai[i][b];
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bhr, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bhi, ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, blr, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bli, ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, bhr, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, bhi, ci, 0, 0, 0);
+            ar[i][b] = cr;
+            ai[i][b] = ci;
+          }
         }
       }
-    }
-    if (more) {
-      unsigned int *nb = lds + (cur ^ 1) * C::kBufWords;
-      if (full)
-        store_chunk<C, true>(pf, nb, om, w_ok, eta, tid, nx, t_hi, col_ok);
-      else
-        store_chunk<C, false>(pf, nb, om, w_ok, eta, tid, nx, t_hi, col_ok);
-    }
-    __syncthreads();
-    cur ^= 1;
-  }
-  // D[row][col]: element j of lane l is row 4*(l/16)+j, column l%16
-#pragma unroll
-  for (int i = 0; i < WPW; ++i) {
-    const int w = w0 + wave * WPW + i;
-    if (w >= n_w) continue;
-#pragma unroll
-    for (int b = 0; b < SUB; ++b) {
-      const int col = col0 + b * 16 + (lane & 15);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int row = row0 + 4 * (lane >> 4) + j;
-        if (row < n_g && col < n_g)
-          part[((size_t)w * n_g + row) * n_g + col] =
-              make_double2((double)ar[i][b][j], (double)ai[i][b][j]);
+      if (more) {
+        unsigned int *nb = lds + (cur ^ 1) * C::kBufWords;
+        if (full)
+          store_chunk<C, true>(pf, nb, om, w_ok, eta, tid, nx, t_hi, col_ok);
+        else
+          store_chunk<C, false>(pf, nb, om, w_ok, eta, tid, nx, t_hi, col_ok);
       }
+      __syncthreads();
+      cur ^= 1;
     }
+    fold<WPW, SUB>(ar, ai, part, n_w, n_g, w0, row0, col0, lane, wave, first);
+    first = false;
   }
 }
 
-// One tile per workgroup: x = frequency block, y = (G block, G' block), z = slice.
+// Workgroups are dispatched round-robin over the 8 XCDs (id % 8), each with
+// its own L2.  Logical tile L runs on workgroup (L % per) * 8 + L / per with
+// per = total / 8, so every XCD runs a contiguous range of logical tiles and
+// neighbouring tiles, which read the same pair-density rows, share an L2.
+__device__ inline int xcd_logical(int id, int total) {
+  const int per = total / 8;
+  if (id >= per * 8) return id;  // ragged tail keeps its place
+  return (id % 8) * per + id / 8;
+}
+
+// One tile per workgroup; logical tile = (frequency block fastest, then
+// (G block, G' block), then slice).
 template <int WPW, int SUB, int CHUNK>
 __global__ void __launch_bounds__(256, 2)
     k_chi0_bf16x3(const uint2 *P, int ld, const double *delta, const double *df,
@@ -281,29 +318,32 @@ __global__ void __launch_bounds__(256, 2)
                   double eta, int n_g, int ncb, double2 *part) {
   typedef Cfg<WPW, SUB, CHUNK> C;
   extern __shared__ unsigned int lds[];
-  const int gb = blockIdx.y / ncb, gc = blockIdx.y % ncb;
-  const long long t_lo = (long long)blockIdx.z * slice_len;
+  const int nx = gridDim.x, ny = gridDim.y;
+  const int id = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+  const int L = xcd_logical(id, nx * ny * gridDim.z);
+  const int bx = L % nx, by = (L / nx) % ny, bz = L / (nx * ny);
+  const int gb = by / ncb, gc = by % ncb;
+  const long long t_lo = (long long)bz * slice_len;
   const long long t_hi = std::min(n_trans, t_lo + slice_len);
   chi0_tile<WPW, SUB, CHUNK>(lds, P, ld, delta, df, n_trans, t_lo, t_hi, omega, n_w, eta, n_g,
-                             blockIdx.x * C::kWBlock, gb * 16, gc * C::kCols,
-                             part + (size_t)blockIdx.z * n_w * n_g * n_g);
+                             bx * C::kWBlock, gb * 16, gc * C::kCols,
+                             part + (size_t)bz * n_w * n_g * n_g);
 }
 
-// Persistent form: every workgroup takes tiles from the queue until it is
-// empty.  The queue counter is a device integer zeroed before the launch;
-// every workgroup leaves once the counter passes the tile count.
+// Persistent form: a fixed grid (two workgroups per CU) walks the
+// longest-first tile list in rounds of gridDim.x tiles (XCD-aware within a
+// round), so every workgroup runs a similar amount of work and leaves when it
+// passes the end.  No LDS beyond the tile's double buffer (two workgroups still fit per
+// CU) and no atomics; the assignment is deterministic.
 template <int WPW, int SUB, int CHUNK>
 __global__ void __launch_bounds__(256, 2)
-    k_chi0_bf16x3_persistent(const BatchItem *items, const BatchTile *tiles, int n_tiles,
-                             int *counter) {
+    k_chi0_bf16x3_persistent(const BatchItem *items, const BatchTile *tiles, int n_tiles) {
   typedef Cfg<WPW, SUB, CHUNK> C;
   extern __shared__ unsigned int lds[];
-  __shared__ int s_idx;
-  for (;;) {
-    if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
-    __syncthreads();
-    const int idx = s_idx;
-    __syncthreads();
+  const int G = gridDim.x;
+  for (int base = 0; base < n_tiles; base += G) {
+    // round `base`: logical tiles base..base+G-1, a contiguous block per XCD
+    const int idx = base + xcd_logical(blockIdx.x, G);
     if (idx >= n_tiles) break;
     const BatchTile tl = tiles[idx];
     const BatchItem it = items[tl.item];
@@ -313,6 +353,7 @@ __global__ void __launch_bounds__(256, 2)
                                t_lo, t_hi, it.omega, it.n_w, it.eta, it.n_g,
                                tl.wblk * C::kWBlock, tl.gb * 16, tl.gc * C::kCols,
                                it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
+    __syncthreads();  // the next tile's prologue rewrites the LDS buffers
   }
 }
 
@@ -357,10 +398,10 @@ int bf16x3_launch_grid(int v, const void *P, int ld, const double *delta, const 
 }
 
 int bf16x3_launch_persistent(int v, const BatchItem *items, const BatchTile *tiles, int n_tiles,
-                             int *counter, int n_blocks, hipStream_t s) {
+                             int n_blocks, hipStream_t s) {
   const Variant &V = kVariants[v];
   TDX_HIP(hipFuncSetAttribute(V.pers_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)V.lds));
-  void *args[] = {(void *)&items, (void *)&tiles, (void *)&n_tiles, (void *)&counter};
+  void *args[] = {(void *)&items, (void *)&tiles, (void *)&n_tiles};
   TDX_HIP(hipLaunchKernel(V.pers_fn, dim3(n_blocks), dim3(256), args, V.lds, s));
   return TDX_OK;
 }

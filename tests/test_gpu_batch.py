@@ -140,7 +140,7 @@ def test_autotuner_picks_a_variant_and_round_trips_the_cache(tdx, ctx):
     n_g = len(p["basis"])
     v, sl, ms = tdx.autotune_chi0(ctx, p["item"])
     _say(f"  best variant {v} slice 2^{sl} {ms:.3f} ms")
-    assert 0 <= v < tdx.chi0_variants("bf16x3") and sl in (16, 18, 20) and ms > 0
+    assert 0 <= v < tdx.chi0_variants("bf16x3") and sl in (18, 20) and ms > 0
     assert tdx.chi0_get_config(ctx, n_g) == (v, sl)
     path = os.path.join(tempfile.mkdtemp(), "tune.json")
     tdx.tune_save(ctx, path)
