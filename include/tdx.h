@@ -330,6 +330,92 @@ int tdx_itcf(tdx_ctx *ctx, const double *S, const double *omega, int n_w,
              double beta, const double *tau, int n_tau, double *F,
              tdx_stream stream);
 
+/* ------------------------------------------------------------------ */
+/* Reverse mode: vector-Jacobian products of F(q,tau) (FP64)           */
+/* ------------------------------------------------------------------ */
+
+/* Gradients of F(q,tau) (Eq. 1 with S from Eq. 8) with respect to the
+ * temperature T, the broadening eta and the tabulated shell values v_s of
+ * the potential, one call per step of the forward chain, run in reverse:
+ *   itcf_vjp -> dsf_vjp -> dyson_vjp -> chi0_vjp -> weights_vjp
+ *   -> occupations_vjp, pair_density_vjp (per q) -> potential_vjp (once).
+ * A real cotangent xbar means dL = sum xbar dx; a complex one zbar means
+ * dL = Re sum conj(zbar) dz.  The kernel K is held fixed (RPA: it does not
+ * depend on T, eta or v).  Temperature enters through beta = 1/T in S and
+ * F (the caller chains beta_bar and tau_bar) and through the occupations
+ * (occupations_vjp).  Calls that accumulate ("+=") leave zeroing to the
+ * caller so that several q can share one set of state cotangents. */
+
+/* F(tau_j) = sum_i c_i S_i (e^{-tau_j w_i} + e^{-(beta - tau_j) w_i}).
+ * F_bar: device [n_tau].  Writes S_bar [n_w], tau_bar [n_tau] and
+ * beta_bar [1] (the explicit beta of the second exponential only). */
+int tdx_itcf_vjp(tdx_ctx *ctx, const double *S, const double *omega, int n_w, double beta,
+                 const double *tau, int n_tau, const double *F_bar, double *S_bar,
+                 double *tau_bar, double *beta_bar, tdx_stream stream);
+
+/* S = -Im chi00 / (pi n (1 - e^{-beta w})) (w = 0 from the next point).
+ * Writes chi00_bar (device complex128 [n_w]) and beta_bar [1]. */
+int tdx_dsf_vjp(tdx_ctx *ctx, const double *chi00, const double *omega, int n_w, double beta,
+                double density, const double *S_bar, double *chi00_bar, double *beta_bar,
+                tdx_stream stream);
+
+/* chi00 = [A^{-1} chi0 e]_{g0}, A = 1 - chi0 K.  The cotangent of chi0(w)
+ * is the rank-1 matrix u(w) v(w)^H with u = chi00_bar conj(A^{-T} e) and
+ * v = e + K A^{-1} chi0 e; u, v: device complex128 [n_w][n_g] (written).
+ * work: tdx_dyson_work_bytes(n_g, n_w) bytes; info: device int [n_w],
+ * 0 or the failing pivot column + 1 (u, v NaN for that frequency).
+ * No allocation or synchronisation. */
+int tdx_dyson_vjp(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w,
+                  int i_g0, const double *chi00_bar, double *u, double *v, void *work,
+                  int *info, tdx_stream stream);
+
+/* chi0 = pref sum_t w_t rho_t rho_t^H, w_t = df_t / (w - delta_t + i eta),
+ * with cotangent u v^H per frequency.  For lambda = pref (u^H rho_t)
+ * conj(v^H rho_t) and r = 1/(w - delta_t + i eta), writes
+ *   w_bar: device complex128 [n_trans][2] = (sum_w lambda r, sum_w lambda r^2)
+ * (so df_bar = Re w_bar[0], delta_bar = df Re w_bar[1],
+ *  eta_bar = df Im w_bar[1]), and, if rho_bar is not NULL, the pair-density
+ * cotangent rho_bar: device complex128 [n_trans][ld], ld = n_g rounded up
+ * to 16.  P: FP64 pair densities (TDX_PREC_FP64 layout).  No allocation or
+ * synchronisation. */
+int tdx_chi0_vjp(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, const double *P, int n_g,
+                 const double *omega, int n_w, double eta, double pref, const double *u,
+                 const double *v, double *w_bar, double *rho_bar, tdx_stream stream);
+
+/* From w_bar of one q: accumulates the occupation and eigenvalue
+ * cotangents of the states (occ_bar, eps_bar: device [n_k][nb_max], +=)
+ * through df_t = f_n(k) - f_m(k') and delta_t = eps_m(k') - eps_n(k), and
+ * eta_bar (device [1], +=).  Synchronises. */
+int tdx_weights_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const tdx_translist *tl,
+                    int64_t n_trans, const double *w_bar, double *occ_bar, double *eps_bar,
+                    double *eta_bar, tdx_stream stream);
+
+/* Occupations f = 1/(1 + e^{(eps - mu)/T}) with mu fixed by the electron
+ * count, at the states' current temperature and mu (call tdx_occupations
+ * for the q's temperature first).  Writes T_bar (device [1], the
+ * occupation path only) and accumulates eps_bar (+=, through mu(eps)). */
+int tdx_occupations_vjp(tdx_ctx *ctx, const tdx_states *st, const double *occ_bar,
+                        double *eps_bar, double *T_bar, tdx_stream stream);
+
+/* rho_t(G) = sum_G1 c*_nk(G1) c_mk'(G1 + G + G_s): accumulates the
+ * orbital cotangents coef_bar (device complex128 [n_k][nb_max][npw_max],
+ * +=) from rho_bar of one q (layout of tdx_chi0_vjp).  Synchronises. */
+int tdx_pair_density_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
+                         const tdx_translist *tl, int64_t n_trans, const int *gbasis, int n_g,
+                         const double *rho_bar, double *coef_bar, tdx_stream stream);
+
+/* Shell-value gradient from the eigenvalue and orbital cotangents of the
+ * kept bands: with H(k) rebuilt and fully diagonalised (all N_pw pairs),
+ *   y_n = sum_{m not in the multiplet of n} psi_m <psi_m|cbar_n> / (eps_n - eps_m),
+ *   v_bar_s = sum_kn Re (eps_bar_n psi_n + y_n)^H (dH/dv_s) psi_n,
+ * dH/dv_s = [G - G' on shell s] sum_I e^{-i (G-G').R_I}.  Rotations inside
+ * a kept multiplet leave the loss unchanged, so those pairs are dropped.
+ * md must be the model the states were built from; v_bar: host
+ * [n_shells] (written).  Synchronises. */
+int tdx_potential_vjp(tdx_ctx *ctx, const tdx_model *md, const tdx_states *st,
+                      const double *eps_bar, const double *coef_bar, double *v_bar,
+                      tdx_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

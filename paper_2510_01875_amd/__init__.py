@@ -137,6 +137,28 @@ _dyson_async = _sig("tdx_dyson_async", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_
 _itcf = _sig("tdx_itcf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_void_p,
                           C.c_int, C.c_void_p, C.c_void_p])
 
+_itcf_vjp = _sig("tdx_itcf_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
+                                  C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_void_p])
+_dsf_vjp = _sig("tdx_dsf_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
+                                C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
+_dyson_vjp = _sig("tdx_dyson_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p])
+_chi0_vjp = _sig("tdx_chi0_vjp", [C.c_void_p, C.POINTER(TransC), C.c_int64, C.c_void_p, C.c_int,
+                                  C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
+_weights_vjp = _sig("tdx_weights_vjp", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
+                                        C.POINTER(TransC), C.c_int64, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p])
+_occ_vjp = _sig("tdx_occupations_vjp", [C.c_void_p, C.POINTER(StatesC), C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p])
+_pair_vjp = _sig("tdx_pair_density_vjp", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
+                                          C.POINTER(TransC), C.c_int64, C.c_void_p, C.c_int,
+                                          C.c_void_p, C.c_void_p, C.c_void_p])
+_pot_vjp = _sig("tdx_potential_vjp", [C.c_void_p, C.POINTER(Model), C.POINTER(StatesC),
+                                      C.c_void_p, C.c_void_p, c_dbl_p, C.c_void_p])
+
 EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_set_workspace_limit", "tdx_states_query", "tdx_build_states",
             "tdx_occupations", "tdx_response_basis", "tdx_transitions",
@@ -144,7 +166,9 @@ EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
             "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
             "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_autotune_chi0", "tdx_tune_save",
-            "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async"]
+            "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async", "tdx_itcf_vjp",
+            "tdx_dsf_vjp", "tdx_dyson_vjp", "tdx_chi0_vjp", "tdx_weights_vjp",
+            "tdx_occupations_vjp", "tdx_pair_density_vjp", "tdx_potential_vjp"]
 
 
 def check(code):
@@ -414,6 +438,103 @@ def itcf(ctx: Context, S: torch.Tensor, omega: torch.Tensor, beta: float, tau: t
     check(_itcf(ctx.handle, _ptr(S), _ptr(omega), omega.shape[0], beta, _ptr(tau),
                 tau.shape[0], _ptr(F), _stream(stream)))
     return F
+
+
+# ------------------------------------------------------------ reverse mode
+# Cotangent convention: real x -> dL = sum xbar dx; complex z ->
+# dL = Re sum conj(zbar) dz (PyTorch's convention for complex gradients).
+def itcf_vjp(ctx: Context, S: torch.Tensor, omega: torch.Tensor, beta: float, tau: torch.Tensor,
+             F_bar: torch.Tensor, stream=None):
+    """(S_bar [n_w], tau_bar [n_tau], beta_bar [1]) of F = itcf(S, omega, beta, tau)."""
+    dev = S.device
+    S_bar = torch.empty_like(S)
+    tau_bar = torch.empty_like(tau)
+    beta_bar = torch.empty(1, dtype=torch.float64, device=dev)
+    check(_itcf_vjp(ctx.handle, _ptr(S), _ptr(omega), omega.shape[0], beta, _ptr(tau),
+                    tau.shape[0], _ptr(F_bar), _ptr(S_bar), _ptr(tau_bar), _ptr(beta_bar),
+                    _stream(stream)))
+    return S_bar, tau_bar, beta_bar
+
+
+def dsf_vjp(ctx: Context, chi00: torch.Tensor, omega: torch.Tensor, beta: float, density: float,
+            S_bar: torch.Tensor, stream=None):
+    """(chi00_bar complex [n_w], beta_bar [1]) of S = dsf(chi00, omega, beta, density)."""
+    chi_bar = torch.empty_like(chi00)
+    beta_bar = torch.empty(1, dtype=torch.float64, device=chi00.device)
+    check(_dsf_vjp(ctx.handle, _ptr(chi00), _ptr(omega), omega.shape[0], beta, density,
+                   _ptr(S_bar), _ptr(chi_bar), _ptr(beta_bar), _stream(stream)))
+    return chi_bar, beta_bar
+
+
+def dyson_vjp(ctx: Context, chi0_t: torch.Tensor, K: torch.Tensor, i_g0: int,
+              chi00_bar: torch.Tensor, stream=None):
+    """(u, v) [n_w, n_g] with chi0_bar(w) = u(w) v(w)^H; raises on a singular pivot."""
+    n_w, n_g, _ = chi0_t.shape
+    dev = chi0_t.device
+    u = torch.empty((n_w, n_g), dtype=torch.complex128, device=dev)
+    v = torch.empty_like(u)
+    work = torch.empty(dyson_work_bytes(n_g, n_w), dtype=torch.uint8, device=dev)
+    info = torch.zeros(n_w, dtype=torch.int32, device=dev)
+    check(_dyson_vjp(ctx.handle, _ptr(chi0_t), _ptr(K), n_g, n_w, i_g0, _ptr(chi00_bar), _ptr(u),
+                     _ptr(v), _ptr(work), _ptr(info), _stream(stream)))
+    bad = torch.nonzero(info).flatten()
+    if bad.numel():
+        raise TdxError(ERR_NUMERIC, f"Dyson matrix singular at frequency {int(bad[0])}")
+    return u, v
+
+
+def chi0_vjp(ctx: Context, tr: Transitions, P: torch.Tensor, n_g: int, omega: torch.Tensor,
+             eta: float, pref: float, u: torch.Tensor, v: torch.Tensor, want_rho: bool = False,
+             stream=None, n_trans: Optional[int] = None):
+    """(w_bar complex [T, 2], rho_bar complex [T, ld] or None) for FP64 P
+    (the first n_trans transitions if given)."""
+    dev = omega.device
+    T = len(tr) if n_trans is None else int(n_trans)
+    ld = (n_g + 15) // 16 * 16
+    w_bar = torch.zeros((max(T, 1), 2), dtype=torch.complex128, device=dev)
+    rho_bar = (torch.zeros((max(T, 1), ld), dtype=torch.complex128, device=dev)
+               if want_rho else None)
+    check(_chi0_vjp(ctx.handle, C.byref(tr.c), T, _ptr(P), n_g, _ptr(omega), omega.shape[0], eta,
+                    pref, _ptr(u), _ptr(v), _ptr(w_bar),
+                    _ptr(rho_bar) if rho_bar is not None else None, _stream(stream)))
+    return w_bar[:T], (rho_bar[:T] if rho_bar is not None else None)
+
+
+def weights_vjp(ctx: Context, st: States, qj, tr: Transitions, w_bar: torch.Tensor,
+                occ_bar: torch.Tensor, eps_bar: torch.Tensor, eta_bar: torch.Tensor,
+                stream=None):
+    """Accumulate occ_bar, eps_bar [n_k, nb_max] and eta_bar [1] from one q's w_bar."""
+    q = (C.c_int * 3)(*qj)
+    check(_weights_vjp(ctx.handle, C.byref(st.c), q, C.byref(tr.c), len(tr), _ptr(w_bar),
+                       _ptr(occ_bar), _ptr(eps_bar), _ptr(eta_bar), _stream(stream)))
+
+
+def occupations_vjp(ctx: Context, st: States, occ_bar: torch.Tensor, eps_bar: torch.Tensor,
+                    stream=None) -> torch.Tensor:
+    """T_bar [1] of the occupations at the states' temperature; eps_bar += through mu."""
+    T_bar = torch.empty(1, dtype=torch.float64, device=occ_bar.device)
+    check(_occ_vjp(ctx.handle, C.byref(st.c), _ptr(occ_bar), _ptr(eps_bar), _ptr(T_bar),
+                   _stream(stream)))
+    return T_bar
+
+
+def pair_density_vjp(ctx: Context, st: States, qj, tr: Transitions, gbasis: torch.Tensor,
+                     rho_bar: torch.Tensor, coef_bar: torch.Tensor, stream=None):
+    """Accumulate coef_bar [n_k, nb_max, npw_max] from one q's rho_bar."""
+    q = (C.c_int * 3)(*qj)
+    check(_pair_vjp(ctx.handle, C.byref(st.c), q, C.byref(tr.c), len(tr), _ptr(gbasis),
+                    gbasis.shape[0], _ptr(rho_bar), _ptr(coef_bar), _stream(stream)))
+
+
+def potential_vjp(ctx: Context, w, st: States, eps_bar: torch.Tensor, coef_bar: torch.Tensor,
+                  stream=None) -> np.ndarray:
+    """Gradient with respect to the tabulated shell values of w's potential."""
+    keep = []
+    m = make_model(w, keep)
+    out = np.zeros(len(w.potential.shell_n2), dtype=np.float64)
+    check(_pot_vjp(ctx.handle, C.byref(m), C.byref(st.c), _ptr(eps_bar), _ptr(coef_bar),
+                   out.ctypes.data_as(c_dbl_p), _stream(stream)))
+    return out
 
 
 # --------------------------------------------------------------- pipeline

@@ -58,7 +58,7 @@ struct tdx_ctx {
   int n_cu = 0;
   rocblas_handle blas = nullptr;
   size_t limit = 0;  // 0 = unlimited
-  tdx::Workspace ws[8];
+  tdx::Workspace ws[12];
   tdx_chi0_tune tune[64];
 };
 
@@ -73,6 +73,9 @@ enum WsSlot {
   WS_DENS = 5,     // density partial sums
   WS_MISC = 6,     // small per-call tables (k+q maps, lookups)
   WS_MISC2 = 7,
+  WS_ADJ = 8,       // adjoint: per-frequency vectors, state tables
+  WS_ADJ2 = 9,      // adjoint: eigen-adjoint products
+  WS_ADJ3 = 10,     // adjoint: reductions
 };
 
 size_t ws_total(const tdx_ctx *ctx);

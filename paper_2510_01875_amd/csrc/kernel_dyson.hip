@@ -342,6 +342,175 @@ __global__ void __launch_bounds__(kLuThreads)
   }
 }
 
+
+// Reverse mode of the Dyson step.  chi_00 = e^T A^{-1} chi0 e with
+// A = 1 - chi0 K (e = e_g0), so d chi_00 = a^T d chi0 b with
+//   a = A^{-T} e            (row g0 of A^{-1}),
+//   b = e + K x,  x = A^{-1} chi0 e   (column g0 of 1 + K chi).
+// With the cotangent convention dL = Re(conj(cbar) d chi_00) the cotangent
+// of chi0 is the rank-1 matrix u v^H, u = cbar conj(a), v = b.
+// One workgroup per frequency: LU with partial pivoting of A in place (rows
+// swapped whole, multipliers stored below the diagonal, pivot order kept),
+// then U x = L^{-1} P chi0 e, and for a: U^T y = e, L^T z = y, a = P^T z.
+__device__ inline void block_dot(double re, double im, double *sr, double *si) {
+  const int t = threadIdx.x;
+  sr[t] = re;
+  si[t] = im;
+  __syncthreads();
+  for (int s = kLuThreads / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      sr[t] += sr[t + s];
+      si[t] += si[t + s];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kLuThreads)
+    k_lu_vjp(double2 *Aall, const double2 *chi0, const double2 *K, int n, int g0,
+             const double2 *cbar, double2 *u, double2 *v, int *info) {
+  extern __shared__ double2 sm[];
+  double2 *x = sm;                   // [n]
+  double2 *y = sm + n;               // [n]
+  int *piv = (int *)(sm + 2 * n);    // [n]
+  __shared__ double pv[kLuThreads];
+  __shared__ int pi[kLuThreads];
+  __shared__ double sr[kLuThreads], si[kLuThreads];
+  __shared__ int fail;
+  const int w = blockIdx.x, t = threadIdx.x;
+  double2 *A = Aall + (size_t)w * n * n;
+  const double2 *C = chi0 + (size_t)w * n * n;
+  for (int i = t; i < n; i += kLuThreads) x[i] = C[(size_t)i * n + g0];
+  if (t == 0) fail = 0;
+  __syncthreads();
+  for (int c = 0; c < n; ++c) {
+    double best = -1.0;
+    int arg = n;
+    for (int r = c + t; r < n; r += kLuThreads) {
+      const double a = cabs1(A[(size_t)r * n + c]);
+      if (a > best) {
+        best = a;
+        arg = r;
+      }
+    }
+    pv[t] = best;
+    pi[t] = arg;
+    __syncthreads();
+    for (int s = kLuThreads / 2; s > 0; s >>= 1) {
+      if (t < s && (pv[t + s] > pv[t] || (pv[t + s] == pv[t] && pi[t + s] < pi[t]))) {
+        pv[t] = pv[t + s];
+        pi[t] = pi[t + s];
+      }
+      __syncthreads();
+    }
+    const int p = pi[0];
+    const double pmax = pv[0];
+    if (!(pmax > 0.0) || !isfinite(pmax)) {
+      if (t == 0) fail = c + 1;
+      __syncthreads();
+      break;
+    }
+    if (t == 0) piv[c] = p;
+    if (p != c) {
+      for (int j = t; j < n; j += kLuThreads) {
+        const double2 e = A[(size_t)c * n + j];
+        A[(size_t)c * n + j] = A[(size_t)p * n + j];
+        A[(size_t)p * n + j] = e;
+      }
+      if (t == 0) {
+        const double2 e = x[c];
+        x[c] = x[p];
+        x[p] = e;
+      }
+    }
+    __syncthreads();
+    const double2 d = A[(size_t)c * n + c];
+    for (int r = c + 1 + t; r < n; r += kLuThreads) A[(size_t)r * n + c] = cdiv(A[(size_t)r * n + c], d);
+    __syncthreads();
+    const int m = n - c - 1;
+    for (long e = t; e < (long)m * (m + 1); e += kLuThreads) {
+      const int r = c + 1 + (int)(e / (m + 1));
+      const int j = c + 1 + (int)(e % (m + 1));  // j == n: right-hand side
+      const double2 l = A[(size_t)r * n + c];
+      const double2 src = j < n ? A[(size_t)c * n + j] : x[c];
+      double2 &dst = j < n ? A[(size_t)r * n + j] : x[r];
+      dst.x = fma(-l.x, src.x, fma(l.y, src.y, dst.x));
+      dst.y = fma(-l.x, src.y, fma(-l.y, src.x, dst.y));
+    }
+    __syncthreads();
+  }
+  double2 *uw = u + (size_t)w * n, *vw = v + (size_t)w * n;
+  if (fail) {
+    for (int i = t; i < n; i += kLuThreads) uw[i] = vw[i] = make_double2(NAN, NAN);
+    if (t == 0) info[w] = fail;
+    return;
+  }
+  // U x = (L^{-1} P chi0 e), x overwritten
+  for (int r = n - 1; r >= 0; --r) {
+    double re = 0.0, im = 0.0;
+    for (int j = r + 1 + t; j < n; j += kLuThreads) {
+      const double2 a = A[(size_t)r * n + j], b = x[j];
+      re = fma(a.x, b.x, fma(-a.y, b.y, re));
+      im = fma(a.x, b.y, fma(a.y, b.x, im));
+    }
+    block_dot(re, im, sr, si);
+    if (t == 0) x[r] = cdiv(make_double2(x[r].x - sr[0], x[r].y - si[0]), A[(size_t)r * n + r]);
+    __syncthreads();
+  }
+  // v = e + K x
+  for (int i = t; i < n; i += kLuThreads) {
+    double re = i == g0 ? 1.0 : 0.0, im = 0.0;
+    const double2 *Ki = K + (size_t)i * n;
+    for (int j = 0; j < n; ++j) {
+      const double2 a = Ki[j], b = x[j];
+      re = fma(a.x, b.x, fma(-a.y, b.y, re));
+      im = fma(a.x, b.y, fma(a.y, b.x, im));
+    }
+    vw[i] = make_double2(re, im);
+  }
+  // U^T y = e (forward), entries of U^T are A[j][i], j <= i
+  for (int i = 0; i < n; ++i) {
+    double re = 0.0, im = 0.0;
+    for (int j = t; j < i; j += kLuThreads) {
+      const double2 a = A[(size_t)j * n + i], b = y[j];
+      re = fma(a.x, b.x, fma(-a.y, b.y, re));
+      im = fma(a.x, b.y, fma(a.y, b.x, im));
+    }
+    block_dot(re, im, sr, si);
+    if (t == 0)
+      y[i] = cdiv(make_double2((i == g0 ? 1.0 : 0.0) - sr[0], -si[0]), A[(size_t)i * n + i]);
+    __syncthreads();
+  }
+  // L^T z = y (backward, unit diagonal), z overwrites y
+  for (int i = n - 1; i >= 0; --i) {
+    double re = 0.0, im = 0.0;
+    for (int j = i + 1 + t; j < n; j += kLuThreads) {
+      const double2 a = A[(size_t)j * n + i], b = y[j];
+      re = fma(a.x, b.x, fma(-a.y, b.y, re));
+      im = fma(a.x, b.y, fma(a.y, b.x, im));
+    }
+    block_dot(re, im, sr, si);
+    if (t == 0) y[i] = make_double2(y[i].x - sr[0], y[i].y - si[0]);
+    __syncthreads();
+  }
+  // a = P^T z: undo the row swaps last to first
+  if (t == 0) {
+    for (int c = n - 1; c >= 0; --c) {
+      const int p = piv[c];
+      const double2 e = y[c];
+      y[c] = y[p];
+      y[p] = e;
+    }
+    info[w] = 0;
+  }
+  __syncthreads();
+  const double2 cb = cbar[w];
+  for (int i = t; i < n; i += kLuThreads) {
+    const double2 a = y[i];  // u = cbar conj(a)
+    uw[i] = make_double2(cb.x * a.x + cb.y * a.y, cb.y * a.x - cb.x * a.y);
+  }
+}
+
 }  // namespace
 }  // namespace tdx
 
@@ -448,6 +617,29 @@ int tdx_dyson(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_
   for (int i = 0; i < n_w; ++i)
     TDX_REQUIRE(h[i] == 0, TDX_ERR_NUMERIC, "Dyson matrix singular at frequency %d (column %d)",
                 i, h[i] - 1);
+  return TDX_OK;
+}
+
+int tdx_dyson_vjp(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w, int i_g0,
+                  const double *chi00_bar, double *u, double *v, void *work, int *info,
+                  tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && chi0 && K && chi00_bar && u && v && work && info, TDX_ERR_INVALID_ARG,
+              "null argument");
+  TDX_REQUIRE(n_g > 0 && n_w > 0 && i_g0 >= 0 && i_g0 < n_g, TDX_ERR_SHAPE, "bad sizes");
+  const size_t lds = (sizeof(double2) * 2 + sizeof(int)) * (size_t)n_g;
+  TDX_REQUIRE(lds <= 64 * 1024, TDX_ERR_SHAPE, "n_g %d too large for the LU kernel", n_g);
+  TDX_REQUIRE(n_w <= 65535, TDX_ERR_SHAPE, "n_w %d above 65535", n_w);
+  hipStream_t s = as_stream(stream);
+  double2 *A = (double2 *)work;
+  dim3 g((n_g + kT - 1) / kT, (n_g + kT - 1) / kT, n_w);
+  hipLaunchKernelGGL(k_one_minus, g, dim3(kT, kT), 0, s, (const double2 *)chi0,
+                     (const double2 *)K, n_g, A);
+  TDX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_lu_vjp, dim3(n_w), dim3(kLuThreads), lds, s, A, (const double2 *)chi0,
+                     (const double2 *)K, n_g, i_g0, (const double2 *)chi00_bar, (double2 *)u,
+                     (double2 *)v, info);
+  TDX_HIP(hipGetLastError());
   return TDX_OK;
 }
 

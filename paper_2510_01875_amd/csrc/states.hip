@@ -11,6 +11,7 @@
 #include <cstring>
 
 #include "internal.h"
+#include "tables.h"
 
 namespace tdx {
 namespace {
@@ -303,6 +304,240 @@ int occupations_impl(tdx_ctx *ctx, tdx_states *st, double T, double ne, double f
   return TDX_OK;
 }
 
+
+// ---------------------------------------------------------------- adjoint
+// Structure factors S(d) = sum_I exp(-i G(d).R_I) of the shell vectors.
+__global__ void k_shell_sf(const int *d, int n_vec, double3 b0, double3 b1, double3 b2,
+                           const double *pos, int n_atoms, double2 *sf) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n_vec) return;
+  const int d0 = d[3 * v], d1 = d[3 * v + 1], d2 = d[3 * v + 2];
+  const double gx = d0 * b0.x + d1 * b1.x + d2 * b2.x;
+  const double gy = d0 * b0.y + d1 * b1.y + d2 * b2.y;
+  const double gz = d0 * b0.z + d1 * b1.z + d2 * b2.z;
+  double sr = 0.0, si = 0.0;
+  for (int a = 0; a < n_atoms; ++a) {
+    double sn, cs;
+    sincos(gx * pos[3 * a] + gy * pos[3 * a + 1] + gz * pos[3 * a + 2], &sn, &cs);
+    sr += cs;
+    si -= sn;
+  }
+  sf[v] = make_double2(sr, si);
+}
+
+// W_mn <- W_mn / (eps_n - eps_m) over all eigenpairs m of one k, zero for
+// m in the multiplet of n (the loss is invariant under rotations inside a
+// kept multiplet) and for columns n beyond the kept bands.  W is
+// column-major n x nb_max (ld n).
+__global__ void k_eig_scale(double2 *W, const double *D, int n, int nb_max, const int *nb, int k) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (m >= n || c >= nb_max) return;
+  double2 &w = W[(size_t)c * n + m];
+  if (c >= nb[k]) {
+    w = make_double2(0.0, 0.0);
+    return;
+  }
+  const double gap = D[c] - D[m];
+  const double f = fabs(gap) > kDegenTol ? 1.0 / gap : 0.0;
+  w = make_double2(w.x * f, w.y * f);
+}
+
+// Shell derivatives of one kept band n of one k:
+//   part[k][n][s] = Re sum_G conj(x(G)) sum_{d on shell s} S(d) psi_n(G - d),
+//   x = eps_bar_n psi_n + y_n  (dL = Re x^H dH psi_n, dH = sum_s dv_s M_s).
+// One workgroup per (n, k of the batch).
+__global__ void __launch_bounds__(256)
+    k_shell_contract(const double2 *coef, const double *eps_bar, const int *npw, const int *nb,
+                     const int *miller, int nb_max, int npw_max, const int *klist,
+                     const double2 *Y, int n, const int *lut, long box, int M0, int M1, int M2,
+                     const int *dvec, const int *dshell, const double2 *sf, int n_vec,
+                     int n_shells, double *part) {
+  __shared__ double sh[256];
+  __shared__ double acc[64];
+  const int band = blockIdx.x, kk = blockIdx.y;
+  const int k = klist[kk];
+  if (band >= nb[k]) return;
+  const double2 *psi = coef + ((size_t)k * nb_max + band) * npw_max;
+  const double2 *y = Y + ((size_t)kk * nb_max + band) * n;
+  const double eb = eps_bar[(size_t)k * nb_max + band];
+  const int *mk = miller + (size_t)k * npw_max * 3;
+  const int *lutk = lut + (size_t)k * box;
+  const int W1 = 2 * M1 + 1, W2 = 2 * M2 + 1;
+  if (threadIdx.x < n_shells) acc[threadIdx.x] = 0.0;
+  __syncthreads();
+  for (int v = 0; v < n_vec; ++v) {
+    const int d0 = dvec[3 * v], d1 = dvec[3 * v + 1], d2 = dvec[3 * v + 2];
+    const double2 S = sf[v];
+    double re = 0.0;
+    for (int i = threadIdx.x; i < npw[k]; i += 256) {
+      const int x0 = mk[3 * i] - d0 + M0, x1 = mk[3 * i + 1] - d1 + M1, x2 = mk[3 * i + 2] - d2 + M2;
+      if (x0 < 0 || x0 > 2 * M0 || x1 < 0 || x1 >= W1 || x2 < 0 || x2 >= W2) continue;
+      const int j = lutk[((long)x0 * W1 + x1) * W2 + x2];
+      if (j < 0) continue;
+      const double2 p = psi[i], yy = y[i], q = psi[j];
+      const double xr = eb * p.x + yy.x, xi = eb * p.y + yy.y;
+      const double sr = S.x * q.x - S.y * q.y, si = S.x * q.y + S.y * q.x;  // S(d) psi(G - d)
+      re += xr * sr + xi * si;                                             // Re conj(x) (.)
+    }
+    sh[threadIdx.x] = re;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[dshell[v]] += sh[0];
+    __syncthreads();
+  }
+  if (threadIdx.x < n_shells)
+    part[((size_t)k * nb_max + band) * n_shells + threadIdx.x] = acc[threadIdx.x];
+}
+
+// v_bar[s] = sum over (k, n) of part[k][n][s], fixed order.
+__global__ void __launch_bounds__(256)
+    k_shell_sum(const double *part, const int *nb, int nk, int nb_max, int n_shells,
+                double *v_bar) {
+  __shared__ double sh[256];
+  const int s = blockIdx.x;
+  double a = 0.0;
+  for (long i = threadIdx.x; i < (long)nk * nb_max; i += 256)
+    if ((int)(i % nb_max) < nb[i / nb_max]) a += part[(size_t)i * n_shells + s];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) v_bar[s] = sh[0];
+}
+
+// Hamiltonian tables shared by the states build and the potential adjoint:
+// V on the box of Miller differences, k in Cartesian form, k-points grouped
+// by basis size, eigensolver workspaces for up to kb_max k at a time.
+struct HSetup {
+  int D0 = 0, D1 = 0, D2 = 0;
+  double3 b0, b1, b2;
+  double2 *vt = nullptr;
+  double *kc = nullptr, *pos = nullptr;
+  int *klist = nullptr;
+  std::vector<int> npw, order;
+  int kb_max = 1;
+  double2 *dA = nullptr;
+  double *dD = nullptr, *dE = nullptr;
+  int *dinfo = nullptr, *d_flag = nullptr;
+};
+
+int h_setup(tdx_ctx *ctx, const tdx_model *md, const HostBasis &hb, hipStream_t s, HSetup *h) {
+  const Lattice &L = hb.L;
+  const int nk = md->kgrid[0] * md->kgrid[1] * md->kgrid[2];
+  const int npw_max = hb.npw_max;
+  h->npw.resize(nk);
+  std::vector<double> kc(3 * (size_t)nk);
+  for (int k = 0; k < nk; ++k) {
+    h->npw[k] = (int)hb.m[k].size() / 3;
+    int r[3];
+    kindex_split(k, md->kgrid, r);
+    double red[3];
+    mp_point(md->kgrid, r[0], r[1], r[2], red);
+    for (int j = 0; j < 3; ++j)
+      kc[3 * k + j] = red[0] * L.b[0][j] + red[1] * L.b[1][j] + red[2] * L.b[2][j];
+  }
+  h->D0 = 2 * hb.mmax[0];
+  h->D1 = 2 * hb.mmax[1];
+  h->D2 = 2 * hb.mmax[2];
+  const size_t nvt = (size_t)(2 * h->D0 + 1) * (2 * h->D1 + 1) * (2 * h->D2 + 1);
+  const size_t small_bytes = sizeof(double) * (3 * nk + 3 * std::max(md->n_atoms, 1) + 64) +
+                             sizeof(int) * (64 + nk);
+  void *tab;
+  TDX_TRY(ws_get(ctx, WS_MISC2, nvt * sizeof(double2) + small_bytes, &tab));
+  h->vt = (double2 *)tab;
+  h->kc = (double *)(h->vt + nvt);
+  double *d_pos = h->kc + 3 * nk;
+  double *d_sv = d_pos + 3 * std::max(md->n_atoms, 1);
+  int *d_sn = (int *)(d_sv + 64);
+  h->klist = d_sn + 64;
+  h->pos = d_pos;
+  TDX_HIP(hipMemcpyAsync(h->kc, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice, s));
+  if (md->n_atoms)
+    TDX_HIP(hipMemcpyAsync(d_pos, md->positions, sizeof(double) * 3 * md->n_atoms,
+                           hipMemcpyHostToDevice, s));
+  if (md->n_shells) {
+    TDX_HIP(hipMemcpyAsync(d_sv, md->shell_v, sizeof(double) * md->n_shells, hipMemcpyHostToDevice, s));
+    TDX_HIP(hipMemcpyAsync(d_sn, md->shell_n2, sizeof(int) * md->n_shells, hipMemcpyHostToDevice, s));
+  }
+  h->b0 = make_double3(L.b[0][0], L.b[0][1], L.b[0][2]);
+  h->b1 = make_double3(L.b[1][0], L.b[1][1], L.b[1][2]);
+  h->b2 = make_double3(L.b[2][0], L.b[2][1], L.b[2][2]);
+  hipLaunchKernelGGL(k_vtable, dim3((unsigned)std::min<size_t>((nvt + 255) / 256, 65535)), dim3(256),
+                     0, s, h->vt, h->D0, h->D1, h->D2, h->b0, h->b1, h->b2, L.volume, d_pos,
+                     md->n_atoms, d_sn, d_sv, md->n_shells, md->shell_unit, md->gauss, md->z_ion,
+                     md->sigma);
+  TDX_HIP(hipGetLastError());
+  h->order.resize(nk);
+  for (int k = 0; k < nk; ++k) h->order[k] = k;
+  std::stable_sort(h->order.begin(), h->order.end(),
+                   [&](int a, int b) { return h->npw[a] < h->npw[b]; });
+  TDX_HIP(hipMemcpyAsync(h->klist, h->order.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
+  const size_t per_max = (size_t)npw_max * npw_max * sizeof(double2);
+  h->kb_max = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, ((size_t)4 << 30) / per_max));
+  void *wa, *wb;
+  TDX_TRY(ws_get(ctx, WS_EIG, per_max * h->kb_max, &wa));
+  TDX_TRY(ws_get(ctx, WS_EIG_AUX,
+                 ((size_t)2 * npw_max * sizeof(double) + sizeof(int)) * h->kb_max + 256, &wb));
+  h->dA = (double2 *)wa;
+  h->dD = (double *)wb;
+  h->dE = h->dD + (size_t)npw_max * h->kb_max;
+  h->dinfo = (int *)(h->dE + (size_t)npw_max * h->kb_max);
+  h->d_flag = h->dinfo + h->kb_max;
+  TDX_REQUIRE(rocblas_set_stream(ctx->blas, s) == rocblas_status_success, TDX_ERR_HIP,
+              "rocblas_set_stream failed");
+  // the host vectors above are released on return: wait for their copies
+  TDX_HIP(hipStreamSynchronize(s));
+  return TDX_OK;
+}
+
+// All eigenpairs of the nkb k-points order[g0 ...] (basis size n) into
+// h.dA (column-major eigenvectors) and h.dD (ascending eigenvalues):
+// divide and conquer, QR iteration if it returns non-finite vectors.
+// Synchronises.
+int eig_batch(tdx_ctx *ctx, const int *miller, int npw_max, HSetup &h, int g0, int nkb, int n,
+              hipStream_t s) {
+  std::vector<int> hinfo(nkb + 1);
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    dim3 g((n + 15) / 16, (n + 15) / 16, nkb);
+    hipLaunchKernelGGL(k_build_h, g, dim3(16, 16), 0, s, h.dA, n, h.klist + g0, nkb, miller,
+                       npw_max, h.kc, h.vt, h.D0, h.D1, h.D2, h.b0, h.b1, h.b2);
+    TDX_HIP(hipGetLastError());
+    rocblas_status rs =
+        attempt == 0
+            ? rocsolver_zheevd_strided_batched(ctx->blas, rocblas_evect_original,
+                                               rocblas_fill_upper, n,
+                                               (rocblas_double_complex *)h.dA, n,
+                                               (rocblas_stride)n * n, h.dD, n, h.dE, n, h.dinfo,
+                                               nkb)
+            : rocsolver_zheev_strided_batched(ctx->blas, rocblas_evect_original,
+                                              rocblas_fill_upper, n,
+                                              (rocblas_double_complex *)h.dA, n,
+                                              (rocblas_stride)n * n, h.dD, n, h.dE, n, h.dinfo,
+                                              nkb);
+    TDX_REQUIRE(rs == rocblas_status_success, TDX_ERR_HIP, "rocsolver eigensolver failed (%d)",
+                (int)rs);
+    TDX_HIP(hipMemsetAsync(h.d_flag, 0, sizeof(int), s));
+    const size_t cnt = (size_t)nkb * n * n;
+    hipLaunchKernelGGL(k_finite, dim3((unsigned)std::min<size_t>((cnt + 255) / 256, 4096)),
+                       dim3(256), 0, s, h.dA, cnt, h.d_flag);
+    TDX_HIP(hipGetLastError());
+    TDX_HIP(hipMemcpyAsync(hinfo.data(), h.dinfo, sizeof(int) * nkb, hipMemcpyDeviceToHost, s));
+    TDX_HIP(hipMemcpyAsync(&hinfo[nkb], h.d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    TDX_HIP(hipStreamSynchronize(s));
+    bool ok = hinfo[nkb] == 0;
+    for (int i = 0; i < nkb; ++i) ok = ok && hinfo[i] == 0;
+    if (ok) return TDX_OK;
+    TDX_REQUIRE(attempt == 0, TDX_ERR_NUMERIC, "eigensolver failed for basis size %d", n);
+  }
+  return TDX_OK;
+}
+
 }  // namespace
 }  // namespace tdx
 
@@ -350,110 +585,25 @@ int tdx_build_states(tdx_ctx *ctx, const tdx_model *md, double T, tdx_states *st
     }
   }
   const int npw_max = hb.npw_max;
-
-  // basis tables
-  std::vector<int> npw(nk), mill((size_t)nk * npw_max * 3, 0);
-  std::vector<double> kc(3 * (size_t)nk);
-  for (int k = 0; k < nk; ++k) {
-    npw[k] = (int)hb.m[k].size() / 3;
+  HSetup h;
+  TDX_TRY(h_setup(ctx, md, hb, s, &h));
+  std::vector<int> mill((size_t)nk * npw_max * 3, 0);
+  for (int k = 0; k < nk; ++k)
     std::copy(hb.m[k].begin(), hb.m[k].end(), mill.begin() + (size_t)k * npw_max * 3);
-    int r[3];
-    kindex_split(k, md->kgrid, r);
-    double red[3];
-    mp_point(md->kgrid, r[0], r[1], r[2], red);
-    for (int j = 0; j < 3; ++j) kc[3 * k + j] = red[0] * L.b[0][j] + red[1] * L.b[1][j] + red[2] * L.b[2][j];
-  }
-  TDX_HIP(hipMemcpyAsync(st->npw, npw.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
+  TDX_HIP(hipMemcpyAsync(st->npw, h.npw.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
   TDX_HIP(hipMemcpyAsync(st->miller, mill.data(), sizeof(int) * mill.size(), hipMemcpyHostToDevice, s));
-
-  // V(G) on the box of Miller differences
-  const int D0 = 2 * hb.mmax[0], D1 = 2 * hb.mmax[1], D2 = 2 * hb.mmax[2];
-  const size_t nvt = (size_t)(2 * D0 + 1) * (2 * D1 + 1) * (2 * D2 + 1);
-  const size_t small_bytes = sizeof(double) * (3 * nk + 3 * std::max(md->n_atoms, 1) + 64) +
-                             sizeof(int) * (64 + nk);
-  void *tab;
-  TDX_TRY(ws_get(ctx, WS_MISC2, nvt * sizeof(double2) + small_bytes, &tab));
-  double2 *d_vt = (double2 *)tab;
-  double *d_kc = (double *)(d_vt + nvt);
-  double *d_pos = d_kc + 3 * nk;
-  double *d_sv = d_pos + 3 * std::max(md->n_atoms, 1);
-  int *d_sn = (int *)(d_sv + 64);
-  int *d_klist = d_sn + 64;
-  TDX_HIP(hipMemcpyAsync(d_kc, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice, s));
-  if (md->n_atoms)
-    TDX_HIP(hipMemcpyAsync(d_pos, md->positions, sizeof(double) * 3 * md->n_atoms,
-                           hipMemcpyHostToDevice, s));
-  if (md->n_shells) {
-    TDX_HIP(hipMemcpyAsync(d_sv, md->shell_v, sizeof(double) * md->n_shells, hipMemcpyHostToDevice, s));
-    TDX_HIP(hipMemcpyAsync(d_sn, md->shell_n2, sizeof(int) * md->n_shells, hipMemcpyHostToDevice, s));
-  }
-  const double3 b0 = make_double3(L.b[0][0], L.b[0][1], L.b[0][2]);
-  const double3 b1 = make_double3(L.b[1][0], L.b[1][1], L.b[1][2]);
-  const double3 b2 = make_double3(L.b[2][0], L.b[2][1], L.b[2][2]);
-  hipLaunchKernelGGL(k_vtable, dim3((unsigned)std::min<size_t>((nvt + 255) / 256, 65535)), dim3(256),
-                     0, s, d_vt, D0, D1, D2, b0, b1, b2, L.volume, d_pos, md->n_atoms, d_sn,
-                     d_sv, md->n_shells, md->shell_unit, md->gauss, md->z_ion, md->sigma);
-  TDX_HIP(hipGetLastError());
-
-  // k-points grouped by basis size: one unpadded batched eigensolve per size
-  std::vector<int> order(nk);
-  for (int k = 0; k < nk; ++k) order[k] = k;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return npw[a] < npw[b]; });
-  TDX_HIP(hipMemcpyAsync(d_klist, order.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
-  const size_t per_max = (size_t)npw_max * npw_max * sizeof(double2);
-  const int kb_max = (int)std::max<size_t>(1, std::min<size_t>((size_t)nk, ((size_t)4 << 30) / per_max));
-  void *wa, *wb;
-  TDX_TRY(ws_get(ctx, WS_EIG, per_max * kb_max, &wa));
-  TDX_TRY(ws_get(ctx, WS_EIG_AUX, ((size_t)2 * npw_max * sizeof(double) + sizeof(int)) * kb_max + 256, &wb));
-  double2 *dA = (double2 *)wa;
-  double *dD = (double *)wb;
-  double *dE = dD + (size_t)npw_max * kb_max;
-  int *dinfo = (int *)(dE + (size_t)npw_max * kb_max);
-  int *d_flag = dinfo + kb_max;
-  TDX_REQUIRE(rocblas_set_stream(ctx->blas, s) == rocblas_status_success, TDX_ERR_HIP,
-              "rocblas_set_stream failed");
-  std::vector<int> hinfo(kb_max + 1);
   for (int g0 = 0; g0 < nk;) {
-    const int n = npw[order[g0]];
+    const int n = h.npw[h.order[g0]];
     int g1 = g0;
-    while (g1 < nk && npw[order[g1]] == n && g1 - g0 < kb_max) ++g1;
+    while (g1 < nk && h.npw[h.order[g1]] == n && g1 - g0 < h.kb_max) ++g1;
     const int nkb = g1 - g0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-      dim3 g((n + 15) / 16, (n + 15) / 16, nkb);
-      hipLaunchKernelGGL(k_build_h, g, dim3(16, 16), 0, s, dA, n, d_klist + g0, nkb, st->miller,
-                         npw_max, d_kc, d_vt, D0, D1, D2, b0, b1, b2);
-      TDX_HIP(hipGetLastError());
-      // divide and conquer first; QR iteration if it returns non-finite vectors
-      rocblas_status rs =
-          attempt == 0
-              ? rocsolver_zheevd_strided_batched(ctx->blas, rocblas_evect_original,
-                                                 rocblas_fill_upper, n,
-                                                 (rocblas_double_complex *)dA, n,
-                                                 (rocblas_stride)n * n, dD, n, dE, n, dinfo, nkb)
-              : rocsolver_zheev_strided_batched(ctx->blas, rocblas_evect_original,
-                                                rocblas_fill_upper, n,
-                                                (rocblas_double_complex *)dA, n,
-                                                (rocblas_stride)n * n, dD, n, dE, n, dinfo, nkb);
-      TDX_REQUIRE(rs == rocblas_status_success, TDX_ERR_HIP, "rocsolver eigensolver failed (%d)",
-                  (int)rs);
-      TDX_HIP(hipMemsetAsync(d_flag, 0, sizeof(int), s));
-      const size_t cnt = (size_t)nkb * n * n;
-      hipLaunchKernelGGL(k_finite, dim3((unsigned)std::min<size_t>((cnt + 255) / 256, 4096)),
-                         dim3(256), 0, s, dA, cnt, d_flag);
-      TDX_HIP(hipGetLastError());
-      TDX_HIP(hipMemcpyAsync(hinfo.data(), dinfo, sizeof(int) * nkb, hipMemcpyDeviceToHost, s));
-      TDX_HIP(hipMemcpyAsync(&hinfo[kb_max], d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
-      TDX_HIP(hipStreamSynchronize(s));
-      bool ok = hinfo[kb_max] == 0;
-      for (int i = 0; i < nkb; ++i) ok = ok && hinfo[i] == 0;
-      if (ok) break;
-      TDX_REQUIRE(attempt == 0, TDX_ERR_NUMERIC, "eigensolver failed for basis size %d", n);
-    }
-    hipLaunchKernelGGL(k_extract, dim3(st->nb_max, nkb), dim3(256), 0, s, dA, dD, n,
-                       d_klist + g0, nkb, st->nb_max, npw_max, st->eps, (double2 *)st->coef);
+    TDX_TRY(eig_batch(ctx, st->miller, npw_max, h, g0, nkb, n, s));
+    hipLaunchKernelGGL(k_extract, dim3(st->nb_max, nkb), dim3(256), 0, s, h.dA, h.dD, n,
+                       h.klist + g0, nkb, st->nb_max, npw_max, st->eps, (double2 *)st->coef);
     TDX_HIP(hipGetLastError());
     g0 = g1;
   }
+  int *d_flag = h.d_flag;
 
   // band counts
   TDX_HIP(hipMemsetAsync(d_flag, 0, sizeof(int), s));
@@ -473,6 +623,120 @@ int tdx_occupations(tdx_ctx *ctx, tdx_states *st, double T, double ne, double f_
   TDX_REQUIRE(ctx && st && st->eps && st->nb && st->occ, TDX_ERR_INVALID_ARG, "null argument");
   TDX_TRY(check_device(ctx));
   return occupations_impl(ctx, st, T, ne, f_trunc, as_stream(stream));
+}
+
+int tdx_potential_vjp(tdx_ctx *ctx, const tdx_model *md, const tdx_states *st,
+                      const double *eps_bar, const double *coef_bar, double *v_bar,
+                      tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && st && eps_bar && coef_bar && v_bar, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_TRY(validate(md));
+  TDX_REQUIRE(md->n_shells > 0, TDX_ERR_INVALID_ARG, "the model has no tabulated shells");
+  TDX_TRY(check_device(ctx));
+  hipStream_t s = as_stream(stream);
+  HostBasis hb;
+  TDX_TRY(host_basis(md, &hb));
+  const int nk = md->kgrid[0] * md->kgrid[1] * md->kgrid[2];
+  TDX_REQUIRE(st->n_k == nk && st->npw_max == hb.npw_max, TDX_ERR_SHAPE,
+              "states were not built from this model's basis");
+  const int npw_max = st->npw_max, nb_max = st->nb_max, ns = md->n_shells;
+  HSetup h;
+  TDX_TRY(h_setup(ctx, md, hb, s, &h));
+  // shell vectors on the box of Miller differences
+  std::vector<int> dv, ds;
+  const Lattice &L = hb.L;
+  for (int d0 = -h.D0; d0 <= h.D0; ++d0)
+    for (int d1 = -h.D1; d1 <= h.D1; ++d1)
+      for (int d2 = -h.D2; d2 <= h.D2; ++d2) {
+        if (!d0 && !d1 && !d2) continue;
+        double g[3];
+        for (int j = 0; j < 3; ++j) g[j] = d0 * L.b[0][j] + d1 * L.b[1][j] + d2 * L.b[2][j];
+        const double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+        int hit = -1;
+        for (int j = 0; j < ns; ++j) {
+          const double s2 = md->shell_unit * md->shell_unit * md->shell_n2[j];
+          if (std::fabs(g2 - s2) <= 1e-9 * s2) hit = j;
+        }
+        if (hit < 0) continue;
+        dv.push_back(d0);
+        dv.push_back(d1);
+        dv.push_back(d2);
+        ds.push_back(hit);
+      }
+  const int n_vec = (int)ds.size();
+  const int M0 = st->mmax[0], M1 = st->mmax[1], M2 = st->mmax[2];
+  const long box = (long)(2 * M0 + 1) * (2 * M1 + 1) * (2 * M2 + 1);
+  const size_t lut_bytes = (sizeof(int) * (size_t)nk * box + 255) / 256 * 256;
+  const size_t vec_bytes = (sizeof(int) * 4 * (size_t)std::max(n_vec, 1) + 255) / 256 * 256;
+  const size_t sf_bytes = sizeof(double2) * (size_t)std::max(n_vec, 1);
+  const size_t part_bytes = sizeof(double) * ((size_t)nk * nb_max * ns + 64);
+  void *wt, *wy, *wp;
+  TDX_TRY(ws_get(ctx, WS_ADJ, lut_bytes + vec_bytes + sf_bytes, &wt));
+  TDX_TRY(ws_get(ctx, WS_ADJ2, sizeof(double2) * 2 * (size_t)h.kb_max * npw_max * nb_max, &wy));
+  TDX_TRY(ws_get(ctx, WS_ADJ3, part_bytes, &wp));
+  int *d_lut = (int *)wt;
+  int *d_vec = (int *)((char *)wt + lut_bytes);
+  int *d_shell = d_vec + 3 * std::max(n_vec, 1);
+  double2 *d_sf = (double2 *)((char *)wt + lut_bytes + vec_bytes);
+  double2 *dW = (double2 *)wy;
+  double2 *dY = dW + (size_t)h.kb_max * npw_max * nb_max;
+  double *d_part = (double *)wp;
+  double *d_vbar = d_part + (size_t)nk * nb_max * ns;
+  if (n_vec) {
+    TDX_HIP(hipMemcpyAsync(d_vec, dv.data(), sizeof(int) * dv.size(), hipMemcpyHostToDevice, s));
+    TDX_HIP(hipMemcpyAsync(d_shell, ds.data(), sizeof(int) * ds.size(), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_shell_sf, dim3((n_vec + 127) / 128), dim3(128), 0, s, d_vec, n_vec, h.b0,
+                       h.b1, h.b2, h.pos, md->n_atoms, d_sf);
+    TDX_HIP(hipGetLastError());
+    TDX_HIP(hipStreamSynchronize(s));
+  }
+  TDX_HIP(hipMemsetAsync(d_lut, 0xff, lut_bytes, s));
+  TDX_HIP(hipMemsetAsync(d_part, 0, part_bytes, s));
+  hipLaunchKernelGGL(k_lut, dim3((npw_max + 255) / 256, nk), dim3(256), 0, s, st->miller, st->npw,
+                     npw_max, nk, M0, M1, M2, d_lut, box);
+  TDX_HIP(hipGetLastError());
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  for (int g0 = 0; g0 < nk;) {
+    const int n = h.npw[h.order[g0]];
+    int g1 = g0;
+    while (g1 < nk && h.npw[h.order[g1]] == n && g1 - g0 < h.kb_max) ++g1;
+    const int nkb = g1 - g0;
+    TDX_TRY(eig_batch(ctx, st->miller, npw_max, h, g0, nkb, n, s));
+    for (int kk = 0; kk < nkb; ++kk) {
+      const int k = h.order[g0 + kk];
+      const rocblas_double_complex *psi = (const rocblas_double_complex *)(h.dA + (size_t)kk * n * n);
+      rocblas_double_complex *W = (rocblas_double_complex *)(dW + (size_t)kk * nb_max * n);
+      rocblas_double_complex *Y = (rocblas_double_complex *)(dY + (size_t)kk * nb_max * n);
+      const rocblas_double_complex *cb =
+          (const rocblas_double_complex *)(coef_bar + 2 * (size_t)k * nb_max * npw_max);
+      // W = Psi^H Cbar: overlaps of the cotangent rows with every eigenvector
+      TDX_REQUIRE(rocblas_zgemm(ctx->blas, rocblas_operation_conjugate_transpose,
+                                rocblas_operation_none, n, nb_max, n, &one, psi, n, cb, npw_max,
+                                &zero, W, n) == rocblas_status_success,
+                  TDX_ERR_HIP, "rocblas_zgemm failed");
+      hipLaunchKernelGGL(k_eig_scale, dim3((n + 255) / 256, nb_max), dim3(256), 0, s,
+                         (double2 *)W, h.dD + (size_t)kk * n, n, nb_max, st->nb, k);
+      TDX_HIP(hipGetLastError());
+      // Y = Psi (F o W): y_n = sum_{m != n} psi_m <m|cbar_n> / (eps_n - eps_m)
+      TDX_REQUIRE(rocblas_zgemm(ctx->blas, rocblas_operation_none, rocblas_operation_none, n,
+                                nb_max, n, &one, psi, n, W, n, &zero, Y, n) ==
+                      rocblas_status_success,
+                  TDX_ERR_HIP, "rocblas_zgemm failed");
+    }
+    hipLaunchKernelGGL(k_shell_contract, dim3(nb_max, nkb), dim3(256), 0, s,
+                       (const double2 *)st->coef, eps_bar, st->npw, st->nb, st->miller, nb_max,
+                       npw_max, h.klist + g0, (const double2 *)dY, n, d_lut, box, M0, M1, M2,
+                       d_vec, d_shell, d_sf, n_vec, ns, d_part);
+    TDX_HIP(hipGetLastError());
+    TDX_HIP(hipStreamSynchronize(s));
+    g0 = g1;
+  }
+  hipLaunchKernelGGL(k_shell_sum, dim3(ns), dim3(256), 0, s, d_part, st->nb, nk, nb_max, ns,
+                     d_vbar);
+  TDX_HIP(hipGetLastError());
+  TDX_HIP(hipMemcpyAsync(v_bar, d_vbar, sizeof(double) * ns, hipMemcpyDeviceToHost, s));
+  TDX_HIP(hipStreamSynchronize(s));
+  return TDX_OK;
 }
 
 }  // extern "C"
