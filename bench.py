@@ -182,7 +182,21 @@ def main():
                     help="tune the split-BF16 tile shape on q0 first and save the cache")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2510_01875_amd",
                                                          "tune_gfx950.json"))
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (out = in * 1.0, "
+                         "five launches): the reference kernel for scaling HBM byte counters")
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        import torch
+        n = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe": {"bytes_read": n * 8, "bytes_written": n * 8,
+                                         "launches": 5}}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path's sharding "
               "over q, frequency or transition blocks is described in DESIGN.md",

@@ -75,6 +75,17 @@ __device__ inline unsigned int cvt_pk(float a, float b) {
 __device__ inline float lo_f(unsigned int w) { return __uint_as_float(w << 16); }
 __device__ inline float hi_f(unsigned int w) { return __uint_as_float(w & 0xffff0000u); }
 
+// LDS index (float2 units) of rho(tl, row) and of the weight (tl, w): the
+// four transition groups kq that one MFMA K-step reads side by side are
+// adjacent, so a read instruction touches consecutive words.
+__device__ inline int rho_index(int tl, int row) {
+  return (((tl >> 4) * 4 + (tl & 3)) * 4 + ((tl & 15) >> 2)) * 16 + row;
+}
+template <class C>
+__device__ inline int wt_index(int tl, int w) {
+  return (((tl >> 4) * 4 + (tl & 3)) * C::kWBlock + w) * 4 + ((tl & 15) >> 2);
+}
+
 template <class C>
 struct Prefetch {
   uint2 b[C::kNB];
@@ -140,20 +151,22 @@ __device__ inline void store_chunk(const Prefetch<C> &pf, unsigned int *buf, dou
     const int tl = ta + 16 * i;
     const bool ok = FULL || tc + tl < t_hi;
     const uint2 q = pf.a[i];
-    rq[tl * 16 + ca] = ok ? make_float2(lo_f(q.x) + lo_f(q.y), hi_f(q.x) + hi_f(q.y))
+    rq[rho_index(tl, ca)] = ok ? make_float2(lo_f(q.x) + lo_f(q.y), hi_f(q.x) + hi_f(q.y))
                           : make_float2(0.f, 0.f);
   }
-  // weights df / (w - delta + i eta) in FP64, stored in FP32
+  // weights df / (w - delta + i eta): w - delta in FP64 (it may cancel),
+  // the rest in FP32 (relative error ~1e-7, far below the 2^-16 of the
+  // split products)
   const int tw = tid / C::kWBlock, wi = tid % C::kWBlock;
+  const float etaf = (float)eta;
 #pragma unroll
   for (int i = 0; i < C::kNW; ++i) {
     const int tl = tw + (256 / C::kWBlock) * i;
     if (C::kWPart && tl >= C::kChunk) break;
     const bool ok = (FULL || tc + tl < t_hi) && w_ok;
-    const double x = om - pf.d[i];
-    const double sc = pf.f[i] / fma(x, x, eta * eta);
-    wt[tl * C::kWBlock + wi] =
-        ok ? make_float2((float)(sc * x), (float)(-sc * eta)) : make_float2(0.f, 0.f);
+    const float x = (float)(om - pf.d[i]);
+    const float sc = (float)pf.f[i] * __builtin_amdgcn_rcpf(fmaf(x, x, etaf * etaf));
+    wt[wt_index<C>(tl, wi)] = ok ? make_float2(sc * x, -sc * etaf) : make_float2(0.f, 0.f);
   }
 }
 
@@ -219,6 +232,9 @@ __device__ __attribute__((always_inline)) void chi0_tile(unsigned int *lds, cons
   const bool w_ok = wi < n_w;
   const double om = omega[std::min(wi, n_w - 1)];
   const size_t lds_ = (size_t)ld;
+  // 16-column blocks of this tile inside the padded basis (ld is a multiple
+  // of 16); blocks past it are not multiplied
+  const int nsub = std::min(SUB, (ld - col0) / 16);
   if (t_lo + CHUNK <= t_hi) {
     load_chunk<C, true>(pf, P, lds_, colc, row0, delta, df, t_lo, n_trans, tid);
     store_chunk<C, true>(pf, lds, om, w_ok, eta, tid, t_lo, t_hi, col_ok);
@@ -247,16 +263,15 @@ __device__ __attribute__((always_inline)) void chi0_tile(unsigned int *lds, cons
       const float2 *wt = (const float2 *)(buf + C::kBWords + C::kRhoWords);
   #pragma unroll
       for (int s = 0; s < C::kSteps; ++s) {
-        const int tb = s * 16 + 4 * kq;
         float2 rho[4];
   #pragma unroll
-        for (int j = 0; j < 4; ++j) rho[j] = rq[(tb + j) * 16 + r];
+        for (int j = 0; j < 4; ++j) rho[j] = rq[(s * 4 + j) * 64 + lane];
         u32x4 ah[WPW], al[WPW];
   #pragma unroll
         for (int i = 0; i < WPW; ++i) {
   #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const float2 w = wt[(tb + j) * C::kWBlock + wave * WPW + i];
+            const float2 w = wt[((s * 4 + j) * C::kWBlock + wave * WPW + i) * 4 + kq];
             const float are = fmaf(w.x, rho[j].x, -w.y * rho[j].y);
             const float aim = fmaf(w.x, rho[j].y, w.y * rho[j].x);
             const unsigned int h = cvt_pk(are, aim);
@@ -266,6 +281,7 @@ __device__ __attribute__((always_inline)) void chi0_tile(unsigned int *lds, cons
         }
   #pragma unroll
         for (int b = 0; b < SUB; ++b) {
+          if (b >= nsub) break;  // uniform across the workgroup
           const u32x4 *bp = bfr + ((s * SUB + b) * 4) * 64 + lane;
           const bf16x8 bhr = as_bf16x8(bp[0]), blr = as_bf16x8(bp[64]);
           const bf16x8 bhi = as_bf16x8(bp[128]), bli = as_bf16x8(bp[192]);
