@@ -7,7 +7,8 @@ namespace tdx {
 
 // One q-vector of a batch: its transitions, pair densities and outputs.
 struct BatchItem {
-  const void *P;
+  const void *P;  // split-BF16 fragment words
+  const void *R;  // FP32 rho rows that follow them
   int ld;
   const double *delta, *df;
   long long n_trans, slice_len;
@@ -26,7 +27,15 @@ struct BatchTile {
 
 int bf16x3_variant_count();
 void bf16x3_variant_shape(int v, int *wblock, int *cols);
-int bf16x3_launch_grid(int v, const void *P, int ld, const double *delta, const double *df,
+// The FP32 rho block that follows the fragment words of a split-BF16
+// pair-density buffer laid out for p_rows transitions (rows padded to a
+// multiple of 32 plus one zero chunk of 32).
+inline const void *bf16x3_rho(const void *P, long long p_rows, int ld) {
+  return (const char *)P + (size_t)(((p_rows + 31) / 32 + 1) * 32) * ld * 16;
+}
+
+int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double *delta,
+                       const double *df,
                        long long n_trans, long long slice_len, int slices, const double *omega,
                        int n_w, double eta, int n_g, double2 *part, hipStream_t s);
 int bf16x3_launch_persistent(int v, const BatchItem *items, const BatchTile *tiles, int n_tiles,

@@ -12,10 +12,14 @@
 // so that D_re accumulates Re chi0 and D_im accumulates Im chi0.
 //
 // A tile is 16 G x (16 SUB) G' for 4 WPW frequencies (4 waves x WPW) over one
-// slice of transitions.  Per chunk of CHUNK transitions the B fragments
-// (already in lane order and already rotated for the imaginary part), the
-// FP32 rho rows and the weights are staged in LDS; the next chunk's global
-// loads are in flight while the current chunk runs (two LDS buffers).  Sums
+// slice of transitions.  The pair densities arrive in a layout made for this
+// kernel: per quad of transitions and column, the 16-byte groups hi, lo,
+// rot(hi), rot(lo) (rot(re, im) = (-im, re)), so that one 16-byte-per-lane
+// global-to-LDS transfer fills one lane-ordered B fragment, and the FP32 rho
+// rows for the left operand.  Per chunk of CHUNK transitions the fragments
+// and rho rows are copied into LDS with no register staging and no
+// arithmetic; only the weights pass through registers.  The next chunk's
+// transfers are in flight while the current chunk runs (two LDS buffers).  Sums
 // run in FP32 over 256 chunks and are folded into the tile's FP64 partial;
 // slices are reduced in FP64 in a fixed order, so results do not depend on
 // which workgroup ran which tile.
@@ -51,22 +55,16 @@ struct Cfg {
   static constexpr int kWtWords = CHUNK * kWBlock * 2;       // [t][w] float2
   static constexpr int kBufWords = kBWords + kRhoWords + kWtWords;
   static constexpr size_t kLds = 2 * (size_t)kBufWords * 4;
-  static constexpr int kNB = CHUNK * kCols / 256;    // B entries per thread
-  static constexpr int kNA = CHUNK * 16 / 256;       // rho entries per thread
   // weights per thread; when the chunk holds fewer than 256 weights only the
   // first CHUNK * kWBlock threads store one
   static constexpr bool kWPart = CHUNK * kWBlock < 256;
   static constexpr int kNW = kWPart ? 1 : CHUNK * kWBlock / 256;
-  static_assert(256 % kCols == 0 && 256 % kWBlock == 0, "tile must divide the block");
-  static_assert(kNB >= 1 && kNA >= 1, "chunk too small");
+  static_assert(256 % kWBlock == 0 && CHUNK % 16 == 0, "tile must divide the block");
 };
 
 constexpr int kFoldChunks = 256;  // chunks summed in FP32 between folds
 
 __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
-
-// (re | im << 16) -> (-im | re << 16)
-__device__ inline unsigned int rot_neg(unsigned int w) { return ((w >> 16) ^ 0x8000u) | (w << 16); }
 
 __device__ inline unsigned int cvt_pk(float a, float b) {
   return __builtin_bit_cast(unsigned int, __builtin_convertvector((f32x2){a, b}, bf16x2));
@@ -86,87 +84,86 @@ __device__ inline int wt_index(int tl, int w) {
   return (((tl >> 4) * 4 + (tl & 3)) * C::kWBlock + w) * 4 + ((tl & 15) >> 2);
 }
 
-template <class C>
-struct Prefetch {
-  uint2 b[C::kNB];
-  uint2 a[C::kNA];
-  double d[C::kNW], f[C::kNW];
-};
+typedef __attribute__((address_space(3))) void lds_void;
 
-// Global loads of one chunk into registers.  Full chunks (every row inside
-// the slice, the common case) load with no predicate; the ragged last chunk
-// of the list clamps its rows into the array and store_chunk zeroes them.
-// Loads are unconditional so they stay in flight until the values are stored.
-template <class C, bool FULL>
-__device__ inline void load_chunk(Prefetch<C> &pf, const uint2 *P, size_t ld, int colc, int row0,
-                                  const double *delta, const double *df, long long tc,
-                                  long long n_trans, int tid) {
-  const int tb = tid / C::kCols;
+// 16 bytes per lane from global memory straight into LDS: lane l writes
+// dst + 16 l (dst uniform across the wave).  No registers are involved.
+__device__ inline void dma16(const void *src, unsigned int *dst) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void *)dst, 16, 0, 0);
+}
+
+// Wait for this wave's outstanding global loads, LDS transfers included.
+__device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0f70); }  // vmcnt(0)
+
+// Stage the B fragments and the FP32 rho rows of the chunk starting at
+// transition tc (a multiple of 16) into buf by LDS DMA.  The pair-density
+// buffer carries a zero chunk past its last transition, so whole chunks are
+// read without clamping; each transfer is a wave-uniform base plus a
+// per-lane offset fixed for the tile (lane_b, lane_r).
+//  - B: block (s, b, comp) is the lane-ordered fragment of K-step s,
+//    16-column block b and component comp (hi, lo, rot hi, rot lo); wave w
+//    stages comp = w of every block.  Lane (kq = l/16, c16 = l%16) copies the
+//    16-byte word group of transitions tc + 16 s + 4 kq .. +3 at column
+//    col0 + 16 b + c16: lane_b = (4 kq ld + c16) * 16 bytes.
+//  - rho: block d holds float2 slots 64 d .. 64 d + 63 of the layout
+//    rho_index; lane l copies rows row0 + 2 m, +1 (m = l & 7) of transition
+//    tc + 16 (d/2) + 2 (d&1) + h + 4 kq2 (h = l/32, kq2 = l/8 & 3):
+//    lane_r = ((h + 4 kq2) ld + 2 m) * 8 bytes.
+template <class C>
+__device__ inline void dma_chunk(const unsigned char *P4, const unsigned char *R, int ld,
+                                 long long tc, int col0, int row0, int nsub, unsigned int *buf,
+                                 int wave, unsigned lane_b, unsigned lane_r) {
 #pragma unroll
-  for (int i = 0; i < C::kNB; ++i) {
-    const long long t0 = tc + tb + (256 / C::kCols) * i;
-    const long long t = FULL ? t0 : std::min(t0, n_trans - 1);
-    pf.b[i] = P[(size_t)t * ld + colc];
+  for (int m = 0; m < C::kSteps * (C::kCols / 16); ++m) {
+    const int s = m / (C::kCols / 16), b = m % (C::kCols / 16);
+    if (b >= nsub) continue;  // uniform across the workgroup
+    const unsigned char *base =
+        P4 + ((((size_t)(tc >> 2) + 4 * s) * 4 + wave) * ld + col0 + 16 * b) * 16;
+    dma16(base + lane_b, buf + (m * 4 + wave) * 256);
   }
-  const int ta = tid >> 4, ca = tid & 15;
-#pragma unroll
-  for (int i = 0; i < C::kNA; ++i) {
-    const long long t0 = tc + ta + 16 * i;
-    const long long t = FULL ? t0 : std::min(t0, n_trans - 1);
-    pf.a[i] = P[(size_t)t * ld + row0 + ca];
-  }
-  const int tw = tid / C::kWBlock;
-#pragma unroll
-  for (int i = 0; i < C::kNW; ++i) {
-    const long long t0 = tc + tw + (256 / C::kWBlock) * i;
-    const long long t = (FULL && !C::kWPart) ? t0 : std::min(t0, n_trans - 1);
-    pf.d[i] = delta[t];
-    pf.f[i] = df[t];
+  for (int d = wave; d < C::kChunk / 8; d += 4) {
+    const unsigned char *base =
+        R + ((size_t)(tc + 16 * (d >> 1) + 2 * (d & 1)) * ld + row0) * 8;
+    dma16(base + lane_r, buf + C::kBWords + d * 256);
   }
 }
 
-template <class C, bool FULL>
-__device__ inline void store_chunk(const Prefetch<C> &pf, unsigned int *buf, double om, bool w_ok,
-                                   double eta, int tid, long long tc, long long t_hi,
-                                   bool col_ok) {
-  unsigned int *bw = buf;
-  float2 *rq = (float2 *)(buf + C::kBWords);
+// Weights df / (w - delta + i eta) of one chunk: loads into registers ...
+template <class C>
+struct Weights {
+  double d[C::kNW], f[C::kNW];
+};
+
+template <class C>
+__device__ inline void load_weights(Weights<C> &pw, const double *delta, const double *df,
+                                    long long tc, long long t_max, int tid) {
+  const int tw = tid / C::kWBlock;
+#pragma unroll
+  for (int i = 0; i < C::kNW; ++i) {
+    const int tl = std::min(tw + (256 / C::kWBlock) * i, C::kChunk - 1);
+    const long long t = std::min(tc + tl, t_max);
+    pw.d[i] = delta[t];
+    pw.f[i] = df[t];
+  }
+}
+
+// ... and into LDS: w - delta in FP64 (it may cancel), the rest in FP32
+// (relative error ~1e-7, far below the 2^-16 of the split products); zero
+// past the end of the slice or of the frequency grid.
+template <class C>
+__device__ inline void store_weights(const Weights<C> &pw, unsigned int *buf, double om,
+                                     bool w_ok, float eta, int tid, long long tc,
+                                     long long t_hi) {
   float2 *wt = (float2 *)(buf + C::kBWords + C::kRhoWords);
-  const int c = tid % C::kCols, b = c >> 4, tb = tid / C::kCols;
-#pragma unroll
-  for (int i = 0; i < C::kNB; ++i) {
-    const int tl = tb + (256 / C::kCols) * i;
-    const int s = tl >> 4, kq = (tl & 15) >> 2, jj = tl & 3, l = kq * 16 + (c & 15);
-    const bool ok = col_ok && (FULL || tc + tl < t_hi);
-    const unsigned int x = ok ? pf.b[i].x : 0u, y = ok ? pf.b[i].y : 0u;
-    const int base = ((s * (C::kCols / 16) + b) * 4) * 256 + l * 4 + jj;
-    bw[base] = x;
-    bw[base + 256] = y;
-    bw[base + 512] = rot_neg(x);
-    bw[base + 768] = rot_neg(y);
-  }
-  const int ta = tid >> 4, ca = tid & 15;
-#pragma unroll
-  for (int i = 0; i < C::kNA; ++i) {
-    const int tl = ta + 16 * i;
-    const bool ok = FULL || tc + tl < t_hi;
-    const uint2 q = pf.a[i];
-    rq[rho_index(tl, ca)] = ok ? make_float2(lo_f(q.x) + lo_f(q.y), hi_f(q.x) + hi_f(q.y))
-                          : make_float2(0.f, 0.f);
-  }
-  // weights df / (w - delta + i eta): w - delta in FP64 (it may cancel),
-  // the rest in FP32 (relative error ~1e-7, far below the 2^-16 of the
-  // split products)
   const int tw = tid / C::kWBlock, wi = tid % C::kWBlock;
-  const float etaf = (float)eta;
 #pragma unroll
   for (int i = 0; i < C::kNW; ++i) {
     const int tl = tw + (256 / C::kWBlock) * i;
     if (C::kWPart && tl >= C::kChunk) break;
-    const bool ok = (FULL || tc + tl < t_hi) && w_ok;
-    const float x = (float)(om - pf.d[i]);
-    const float sc = (float)pf.f[i] * __builtin_amdgcn_rcpf(fmaf(x, x, etaf * etaf));
-    wt[wt_index<C>(tl, wi)] = ok ? make_float2(sc * x, -sc * etaf) : make_float2(0.f, 0.f);
+    const bool ok = tc + tl < t_hi && w_ok;
+    const float x = (float)(om - pw.d[i]);
+    const float sc = (float)pw.f[i] * __builtin_amdgcn_rcpf(fmaf(x, x, eta * eta));
+    wt[wt_index<C>(tl, wi)] = ok ? make_float2(sc * x, -sc * eta) : make_float2(0.f, 0.f);
   }
 }
 
@@ -207,13 +204,14 @@ __device__ inline void fold(f32x4 (&ar)[WPW][SUB], f32x4 (&ai)[WPW][SUB], double
 // kFoldChunks chunks and are folded into part (the slice's [n_w][n_g][n_g]
 // block, FP64) between runs.
 template <int WPW, int SUB, int CHUNK>
-__device__ __attribute__((always_inline)) void chi0_tile(unsigned int *lds, const uint2 *P, int ld, const double *delta,
-                          const double *df, long long n_trans, long long t_lo, long long t_hi,
-                          const double *omega, int n_w, double eta, int n_g, int w0, int row0,
-                          int col0, double2 *part) {
+__device__ __attribute__((always_inline)) void chi0_tile(
+    unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
+    const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
+    int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
   typedef Cfg<WPW, SUB, CHUNK> C;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int r = lane & 15, kq = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int kq = lane >> 4;
 
   f32x4 ar[WPW][SUB], ai[WPW][SUB];
 #pragma unroll
@@ -224,24 +222,22 @@ __device__ __attribute__((always_inline)) void chi0_tile(unsigned int *lds, cons
       ai[i][b] = f32x4{0, 0, 0, 0};
     }
 
-  Prefetch<C> pf;
-  const int cc = col0 + tid % C::kCols;
-  const int colc = std::min(cc, ld - 1);
-  const bool col_ok = cc < ld;
+  const unsigned char *P4 = (const unsigned char *)P, *Rr = (const unsigned char *)R;
+  const long long t_max = n_trans - 1;
+  const unsigned lane_b = (unsigned)(4 * kq * ld + (lane & 15)) * 16u;
+  const unsigned lane_r = (unsigned)(((lane >> 5) + 4 * ((lane >> 3) & 3)) * ld + 2 * (lane & 7)) * 8u;
+  Weights<C> pw;
   const int wi = w0 + tid % C::kWBlock;
   const bool w_ok = wi < n_w;
   const double om = omega[std::min(wi, n_w - 1)];
-  const size_t lds_ = (size_t)ld;
+  const float etaf = (float)eta;
   // 16-column blocks of this tile inside the padded basis (ld is a multiple
-  // of 16); blocks past it are not multiplied
+  // of 16); blocks past it are neither staged nor multiplied
   const int nsub = std::min(SUB, (ld - col0) / 16);
-  if (t_lo + CHUNK <= t_hi) {
-    load_chunk<C, true>(pf, P, lds_, colc, row0, delta, df, t_lo, n_trans, tid);
-    store_chunk<C, true>(pf, lds, om, w_ok, eta, tid, t_lo, t_hi, col_ok);
-  } else {
-    load_chunk<C, false>(pf, P, lds_, colc, row0, delta, df, t_lo, n_trans, tid);
-    store_chunk<C, false>(pf, lds, om, w_ok, eta, tid, t_lo, t_hi, col_ok);
-  }
+  dma_chunk<C>(P4, Rr, ld, t_lo, col0, row0, nsub, lds, wave, lane_b, lane_r);
+  load_weights<C>(pw, delta, df, t_lo, t_max, tid);
+  store_weights<C>(pw, lds, om, w_ok, etaf, tid, t_lo, t_hi);
+  wait_vm();
   __syncthreads();
   int cur = 0;
   bool first = true;
@@ -250,12 +246,11 @@ __device__ __attribute__((always_inline)) void chi0_tile(unsigned int *lds, cons
     const long long re = std::min(t_hi, rs + kRun);
     for (long long tc = rs; tc < re; tc += CHUNK) {
       const long long nx = tc + CHUNK;
-      const bool more = nx < t_hi, full = nx + CHUNK <= t_hi;
+      const bool more = nx < t_hi;
       if (more) {
-        if (full)
-          load_chunk<C, true>(pf, P, lds_, colc, row0, delta, df, nx, n_trans, tid);
-        else
-          load_chunk<C, false>(pf, P, lds_, colc, row0, delta, df, nx, n_trans, tid);
+        dma_chunk<C>(P4, Rr, ld, nx, col0, row0, nsub, lds + (cur ^ 1) * C::kBufWords, wave,
+                     lane_b, lane_r);
+        load_weights<C>(pw, delta, df, nx, t_max, tid);
       }
       const unsigned int *buf = lds + cur * C::kBufWords;
       const u32x4 *bfr = (const u32x4 *)buf;
@@ -281,7 +276,7 @@ __device__ __attribute__((always_inline)) void chi0_tile(unsigned int *lds, cons
         }
   #pragma unroll
         for (int b = 0; b < SUB; ++b) {
-          if (b >= nsub) break;  // uniform across the workgroup
+          if (b < nsub) {  // uniform across the workgroup
           const u32x4 *bp = bfr + ((s * SUB + b) * 4) * 64 + lane;
           const bf16x8 bhr = as_bf16x8(bp[0]), blr = as_bf16x8(bp[64]);
           const bf16x8 bhi = as_bf16x8(bp[128]), bli = as_bf16x8(bp[192]);
@@ -298,15 +293,11 @@ __device__ __attribute__((always_inline)) void chi0_tile(unsigned int *lds, cons
             ar[i][b] = cr;
             ai[i][b] = ci;
           }
+          }
         }
       }
-      if (more) {
-        unsigned int *nb = lds + (cur ^ 1) * C::kBufWords;
-        if (full)
-          store_chunk<C, true>(pf, nb, om, w_ok, eta, tid, nx, t_hi, col_ok);
-        else
-          store_chunk<C, false>(pf, nb, om, w_ok, eta, tid, nx, t_hi, col_ok);
-      }
+      if (more) store_weights<C>(pw, lds + (cur ^ 1) * C::kBufWords, om, w_ok, etaf, tid, nx, t_hi);
+      wait_vm();
       __syncthreads();
       cur ^= 1;
     }
@@ -329,7 +320,7 @@ __device__ inline int xcd_logical(int id, int total) {
 // (G block, G' block), then slice).
 template <int WPW, int SUB, int CHUNK>
 __global__ void __launch_bounds__(256, 2)
-    k_chi0_bf16x3(const uint2 *P, int ld, const double *delta, const double *df,
+    k_chi0_bf16x3(const void *P, const void *R, int ld, const double *delta, const double *df,
                   long long n_trans, long long slice_len, const double *omega, int n_w,
                   double eta, int n_g, int ncb, double2 *part) {
   typedef Cfg<WPW, SUB, CHUNK> C;
@@ -341,7 +332,7 @@ __global__ void __launch_bounds__(256, 2)
   const int gb = by / ncb, gc = by % ncb;
   const long long t_lo = (long long)bz * slice_len;
   const long long t_hi = std::min(n_trans, t_lo + slice_len);
-  chi0_tile<WPW, SUB, CHUNK>(lds, P, ld, delta, df, n_trans, t_lo, t_hi, omega, n_w, eta, n_g,
+  chi0_tile<WPW, SUB, CHUNK>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega, n_w, eta, n_g,
                              bx * C::kWBlock, gb * 16, gc * C::kCols,
                              part + (size_t)bz * n_w * n_g * n_g);
 }
@@ -365,7 +356,7 @@ __global__ void __launch_bounds__(256, 2)
     const BatchItem it = items[tl.item];
     const long long t_lo = tl.slice * it.slice_len;
     const long long t_hi = std::min(it.n_trans, t_lo + it.slice_len);
-    chi0_tile<WPW, SUB, CHUNK>(lds, (const uint2 *)it.P, it.ld, it.delta, it.df, it.n_trans,
+    chi0_tile<WPW, SUB, CHUNK>(lds, it.P, it.R, it.ld, it.delta, it.df, it.n_trans,
                                t_lo, t_hi, it.omega, it.n_w, it.eta, it.n_g,
                                tl.wblk * C::kWBlock, tl.gb * 16, tl.gc * C::kCols,
                                it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
@@ -398,7 +389,8 @@ void bf16x3_variant_shape(int v, int *wblock, int *cols) {
   *cols = 16 * kVariants[v].sub;
 }
 
-int bf16x3_launch_grid(int v, const void *P, int ld, const double *delta, const double *df,
+int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double *delta,
+                       const double *df,
                        long long n_trans, long long slice_len, int slices, const double *omega,
                        int n_w, double eta, int n_g, double2 *part, hipStream_t s) {
   const Variant &V = kVariants[v];
@@ -406,7 +398,8 @@ int bf16x3_launch_grid(int v, const void *P, int ld, const double *delta, const 
   int ncb = (ld + 16 * V.sub - 1) / (16 * V.sub);
   dim3 grid((n_w + 4 * V.wpw - 1) / (4 * V.wpw), nblk * ncb, (unsigned)slices);
   TDX_HIP(hipFuncSetAttribute(V.grid_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)V.lds));
-  void *args[] = {(void *)&P,       (void *)&ld,        (void *)&delta, (void *)&df,
+  void *args[] = {(void *)&P,       (void *)&R,         (void *)&ld,
+                  (void *)&delta,   (void *)&df,
                   (void *)&n_trans, (void *)&slice_len, (void *)&omega, (void *)&n_w,
                   (void *)&eta,     (void *)&n_g,       (void *)&ncb,   (void *)&part};
   TDX_HIP(hipLaunchKernel(V.grid_fn, grid, dim3(256), args, V.lds, s));

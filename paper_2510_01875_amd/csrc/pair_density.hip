@@ -20,6 +20,20 @@ namespace {
 constexpr int kTile = 16;   // G and m tile
 constexpr int kChunk = 32;  // G2 chunk
 
+// Rows of the split-BF16 layout: the transition count rounded up to 32 plus
+// one more chunk of 32 zero rows, so that the chi0 kernel can read whole
+// chunks past the end without clamping.
+__host__ __device__ inline long long pad_rows(long long n_trans) {
+  return ((n_trans + 31) / 32 + 1) * 32;
+}
+
+__device__ inline unsigned int pack_bf16(__hip_bfloat16 lo, __hip_bfloat16 hi) {
+  return (unsigned int)__bfloat16_as_ushort(lo) | ((unsigned int)__bfloat16_as_ushort(hi) << 16);
+}
+
+// (re | im << 16) -> (-im | re << 16)
+__device__ inline unsigned int rot_neg(unsigned int w) { return ((w >> 16) ^ 0x8000u) | (w << 16); }
+
 template <int FMT>
 __device__ inline void store(void *P, long long t, int g, int ld, long long n_trans, double re,
                              double im) {
@@ -29,16 +43,43 @@ __device__ inline void store(void *P, long long t, int g, int ld, long long n_tr
   } else if (FMT == TDX_PREC_FP32) {
     ((float2 *)P)[i] = make_float2((float)re, (float)im);
   } else {
+    // fragment words [t/4][comp][ld][t%4] with comp = hi, lo, rot(hi), rot(lo)
+    // and each word = (re, im) as two bf16, followed by rho in FP32 [T][ld]
     const float r32 = (float)re, i32 = (float)im;
     const __hip_bfloat16 rh = __float2bfloat16(r32), ih = __float2bfloat16(i32);
     const __hip_bfloat16 rl = __float2bfloat16(r32 - __bfloat162float(rh));
     const __hip_bfloat16 il = __float2bfloat16(i32 - __bfloat162float(ih));
-    __hip_bfloat16 *b = (__hip_bfloat16 *)P + 4 * i;
-    b[0] = rh;
-    b[1] = ih;
-    b[2] = rl;
-    b[3] = il;
+    const unsigned int whi = pack_bf16(rh, ih), wlo = pack_bf16(rl, il);
+    unsigned int *w = (unsigned int *)P + (((size_t)(t >> 2) * 4) * ld + g) * 4 + (t & 3);
+    const size_t comp = (size_t)ld * 4;
+    w[0] = whi;
+    w[comp] = wlo;
+    w[2 * comp] = rot_neg(whi);
+    w[3 * comp] = rot_neg(wlo);
+    float2 *R = (float2 *)((char *)P + (size_t)pad_rows(n_trans) * ld * 16);
+    R[i] = make_float2(r32, i32);
   }
+}
+
+// Rows n_trans .. pad_rows(n_trans)-1 of both blocks (fragment words and
+// FP32 rho) are zero.
+__global__ void k_zero_pad(unsigned int *P, long long n_trans, int ld) {
+  const long long rows = pad_rows(n_trans);
+  const long long q0 = n_trans >> 2;
+  const int r0 = (int)(n_trans & 3);
+  const long long nq = rows / 4 - q0;
+  const long long nfrag = nq * 16 * ld;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nfrag;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int jj = (int)(e & 3);
+    if (e < 16LL * ld && jj < r0) continue;  // live rows of the partial quad
+    P[(size_t)q0 * 16 * ld + e] = 0u;
+  }
+  float2 *R = (float2 *)((char *)P + (size_t)rows * ld * 16);
+  const long long nrho = (rows - n_trans) * ld;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nrho;
+       e += (long long)gridDim.x * blockDim.x)
+    R[(size_t)n_trans * ld + e] = make_float2(0.f, 0.f);
 }
 
 template <int FMT>
@@ -127,6 +168,7 @@ using namespace tdx;
 extern "C" {
 
 size_t tdx_pair_density_bytes(int64_t n_trans, int n_g, int prec) {
+  if (prec == TDX_PREC_BF16X3) return (size_t)pad_rows(n_trans) * ld_of(n_g) * 24;
   const size_t per = prec == TDX_PREC_FP64 ? 16 : 8;
   return (size_t)n_trans * ld_of(n_g) * per;
 }
@@ -181,6 +223,9 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
   } else if (prec == TDX_PREC_FP32) {
     TDX_PD(TDX_PREC_FP32);
   } else {
+    hipLaunchKernelGGL(k_zero_pad, dim3(64), dim3(256), 0, s, (unsigned int *)P,
+                       (long long)n_trans, ld);
+    TDX_HIP(hipGetLastError());
     TDX_PD(TDX_PREC_BF16X3);
   }
 #undef TDX_PD
