@@ -27,6 +27,7 @@ struct BatchTile {
 
 int bf16x3_variant_count();
 void bf16x3_variant_shape(int v, int *wblock, int *cols);
+int bf16x3_variant_occupancy(int v);  // workgroups per CU
 // The FP32 rho block that follows the fragment words of a split-BF16
 // pair-density buffer laid out for p_rows transitions (rows padded to a
 // multiple of 32 plus one zero chunk of 32).

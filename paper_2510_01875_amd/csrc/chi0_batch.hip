@@ -251,7 +251,7 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
   p->tiles = (BatchTile *)(base + off_tiles);
   p->counter = (int *)(base + off_counter);
   p->n_tiles = (int)tiles.size();
-  p->n_blocks = std::max(8, 2 * std::max(ctx->n_cu, 1)) / 8 * 8;  // a multiple of the XCD count
+  p->n_blocks = std::max(8, bf16x3_variant_occupancy(v) * std::max(ctx->n_cu, 1)) / 8 * 8;  // a multiple of the XCD count
   int rc = TDX_OK;
   if (hipMemcpy(p->items, bi.data(), sizeof(BatchItem) * n_items, hipMemcpyHostToDevice) !=
           hipSuccess ||

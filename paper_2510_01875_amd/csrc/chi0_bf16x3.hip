@@ -317,9 +317,12 @@ __device__ inline int xcd_logical(int id, int total) {
 }
 
 // One tile per workgroup; logical tile = (frequency block fastest, then
-// (G block, G' block), then slice).
-template <int WPW, int SUB, int CHUNK>
-__global__ void __launch_bounds__(256, 2)
+// (G block, G' block), then slice).  OCC = workgroups per CU (2 for every
+// listed shape: one wave per SIMD leaves LDS and dependency latency exposed,
+// measured at about 60 % of the two-wave rate for 16 x 128 and 16 x 144
+// tiles that fill the 512-entry register file).
+template <int WPW, int SUB, int CHUNK, int OCC>
+__global__ void __launch_bounds__(256, OCC)
     k_chi0_bf16x3(const void *P, const void *R, int ld, const double *delta, const double *df,
                   long long n_trans, long long slice_len, const double *omega, int n_w,
                   double eta, int n_g, int ncb, double2 *part) {
@@ -337,13 +340,13 @@ __global__ void __launch_bounds__(256, 2)
                              part + (size_t)bz * n_w * n_g * n_g);
 }
 
-// Persistent form: a fixed grid (two workgroups per CU) walks the
+// Persistent form: a fixed grid (OCC workgroups per CU) walks the
 // longest-first tile list in rounds of gridDim.x tiles (XCD-aware within a
 // round), so every workgroup runs a similar amount of work and leaves when it
 // passes the end.  No LDS beyond the tile's double buffer (two workgroups still fit per
 // CU) and no atomics; the assignment is deterministic.
-template <int WPW, int SUB, int CHUNK>
-__global__ void __launch_bounds__(256, 2)
+template <int WPW, int SUB, int CHUNK, int OCC>
+__global__ void __launch_bounds__(256, OCC)
     k_chi0_bf16x3_persistent(const BatchItem *items, const BatchTile *tiles, int n_tiles) {
   typedef Cfg<WPW, SUB, CHUNK> C;
   extern __shared__ unsigned int lds[];
@@ -365,19 +368,19 @@ __global__ void __launch_bounds__(256, 2)
 }
 
 struct Variant {
-  int wpw, sub, chunk;
+  int wpw, sub, chunk, occ;
   size_t lds;
   const void *grid_fn;
   const void *pers_fn;
 };
 
-#define TDX_V(W, S, K)                                                                   \
+#define TDX_V(W, S, K, O)                                                                \
   Variant {                                                                              \
-    W, S, K, Cfg<W, S, K>::kLds, (const void *)k_chi0_bf16x3<W, S, K>,                   \
-        (const void *)k_chi0_bf16x3_persistent<W, S, K>                                  \
+    W, S, K, O, Cfg<W, S, K>::kLds, (const void *)k_chi0_bf16x3<W, S, K, O>,             \
+        (const void *)k_chi0_bf16x3_persistent<W, S, K, O>                               \
   }
-const Variant kVariants[] = {TDX_V(4, 4, 32), TDX_V(2, 8, 16), TDX_V(4, 2, 32),
-                             TDX_V(2, 4, 32)};
+const Variant kVariants[] = {TDX_V(4, 4, 32, 2), TDX_V(2, 8, 16, 2), TDX_V(4, 2, 32, 2),
+                             TDX_V(2, 4, 32, 2)};
 #undef TDX_V
 
 }  // namespace
@@ -388,6 +391,8 @@ void bf16x3_variant_shape(int v, int *wblock, int *cols) {
   *wblock = 4 * kVariants[v].wpw;
   *cols = 16 * kVariants[v].sub;
 }
+
+int bf16x3_variant_occupancy(int v) { return kVariants[v].occ; }
 
 int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double *delta,
                        const double *df,
