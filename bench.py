@@ -15,6 +15,7 @@ the FP64 oracle's chi0 step on a bounded sample of the same crystal.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -124,6 +125,35 @@ class BatchedStep:
             out.append(dict(iq=iq, n_t=len(self.tr[iq]), n_g=gb.shape[0], n_w=om.shape[0],
                             S=S if keep else None, F=F if keep else None))
         return out, (e0, e1)
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "counters_k_chi0_bf16x3_fcc_c2.md")
+TRAFFIC_SOURCES = ["paper_2510_01875_amd/csrc/chi0_bf16x3.hip",
+                   "paper_2510_01875_amd/csrc/chi0_batch.hip",
+                   "paper_2510_01875_amd/csrc/chi0_batch.h",
+                   "paper_2510_01875_amd/csrc/pair_density.hip"]
+
+
+def measured_traffic(workload, prec):
+    """HBM bytes per step of the split-BF16 chi0 launches from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by the plain-copy
+    calibration), or None if that summary was taken on other kernel sources
+    or another workload."""
+    if workload != "fcc_c2" or prec != "bf16x3" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    rec = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(("#", "|", "-", "`")):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel_sources_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return float(rec["traffic_bytes_per_step"])
 
 
 def errors(S, Sref, F, Fref):
@@ -323,7 +353,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": per_launch / (avg_ms * 1e-3) / 1e12,
                      "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
                      "frac": per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],
-                     "traffic": None,
+                     "traffic": measured_traffic(w.name, args.prec),
                      "kernel": {"bf16x3": "k_chi0_bf16x3", "fp32": "k_chi0_mfma<1>",
                                 "fp64": "k_chi0_mfma<0>"}[args.prec],
                      "issued_mfma_frac": (3.0 if args.prec == "bf16x3" else 1.0)
