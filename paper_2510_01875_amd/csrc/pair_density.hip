@@ -2,12 +2,9 @@
 //
 // With G2 = G1 + G + G_s in the basis of k' (k + q = k' + G_s):
 //   rho_t(G) = sum_{G2 in basis(k')} conj(c_nk(G2 - G - G_s)) c_mk'(G2).
-// One workgroup per (k, n) row of the transition list: the row's conj(c_nk)
-// sits in LDS, the shifted copy U[G][G2] is gathered from it through a
-// Miller-index lookup box, and the m-rows c_mk' stream through LDS tiles, so
-// that rho[m][G] = sum_G2 U[G][G2] c_mk'(G2) is a small dense product.
+// One wavefront per (k, n) row of the transition list computes the row as a
+// complex matrix product on the FP64 MFMA (details at the kernel).
 // Accumulation is FP64; the store converts to the requested layout.
-#include <hip/hip_bf16.h>
 
 #include <cmath>
 
@@ -17,8 +14,6 @@
 namespace tdx {
 namespace {
 
-constexpr int kTile = 16;   // G and m tile
-constexpr int kChunk = 32;  // G2 chunk
 
 // Rows of the split-BF16 layout: the transition count rounded up to 32 plus
 // one more chunk of 32 zero rows, so that the chi0 kernel can read whole
@@ -27,8 +22,13 @@ __host__ __device__ inline long long pad_rows(long long n_trans) {
   return ((n_trans + 31) / 32 + 1) * 32;
 }
 
-__device__ inline unsigned int pack_bf16(__hip_bfloat16 lo, __hip_bfloat16 hi) {
-  return (unsigned int)__bfloat16_as_ushort(lo) | ((unsigned int)__bfloat16_as_ushort(hi) << 16);
+// Round-to-nearest-even of an FP32 value to bf16, from its bit pattern
+// (finite inputs).  Integer arithmetic keeps the two roundings FP64 -> FP32
+// -> bf16 separate: a fused FP64 -> bf16 conversion would round ties of the
+// FP32 value differently.
+__device__ inline unsigned int rne_bf16(float x) {
+  const unsigned int u = __float_as_uint(x);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
 // (re | im << 16) -> (-im | re << 16)
@@ -46,10 +46,10 @@ __device__ inline void store(void *P, long long t, int g, int ld, long long n_tr
     // fragment words [t/4][comp][ld][t%4] with comp = hi, lo, rot(hi), rot(lo)
     // and each word = (re, im) as two bf16, followed by rho in FP32 [T][ld]
     const float r32 = (float)re, i32 = (float)im;
-    const __hip_bfloat16 rh = __float2bfloat16(r32), ih = __float2bfloat16(i32);
-    const __hip_bfloat16 rl = __float2bfloat16(r32 - __bfloat162float(rh));
-    const __hip_bfloat16 il = __float2bfloat16(i32 - __bfloat162float(ih));
-    const unsigned int whi = pack_bf16(rh, ih), wlo = pack_bf16(rl, il);
+    const unsigned int rh = rne_bf16(r32), ih = rne_bf16(i32);
+    const unsigned int rl = rne_bf16(r32 - __uint_as_float(rh << 16));
+    const unsigned int il = rne_bf16(i32 - __uint_as_float(ih << 16));
+    const unsigned int whi = rh | (ih << 16), wlo = rl | (il << 16);
     unsigned int *w = (unsigned int *)P + (((size_t)(t >> 2) * 4) * ld + g) * 4 + (t & 3);
     const size_t comp = (size_t)ld * 4;
     w[0] = whi;
@@ -82,79 +82,101 @@ __global__ void k_zero_pad(unsigned int *P, long long n_trans, int ld) {
     R[(size_t)n_trans * ld + e] = make_float2(0.f, 0.f);
 }
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPdGT = 9;  // 16-wide G tiles held in accumulators at once
+
+// One wavefront per (k, n) row of the transition list.  For the row's
+// transitions m (tiles of 16) and the response vectors G (tiles of 16,
+// kPdGT at a time) the pair densities are the complex matrix product
+//   rho[m][G] = sum_{G2 in basis(k')} c_mk'(G2) U[G2][G],
+//   U[G2][G] = conj(c_nk)(G2 - G - G_s)  (0 if outside the basis of k),
+// on the FP64 16x16x4 MFMA, four real products per K-step of four G2.  Lane
+// l feeds A = c_{m(l%16)}(G2 = 4 s + l/16) and B = U[4 s + l/16][16 gt + l%16];
+// the B operand is gathered per lane through the Miller-index lookup box of
+// k, which sits in LDS next to conj(c_nk).  The output element j of lane l is
+// m row l/16 + 4 j, G column l%16.
 template <int FMT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     k_pair_density(const double2 *coef, const int *miller, const int *npw, int nb_max,
                    int npw_max, const int *tm, const long long *rowbeg, const long long *rowend,
                    const int *kpmap, const int *gsmap, const int *gbasis, int n_g, int ld,
                    const int *lut, long box, int M0, int M1, int M2, void *P,
                    long long n_trans) {
-  extern __shared__ double2 ckn[];  // [npw_max] conj(c_nk)
-  __shared__ double2 U[kTile][kChunk + 1];
-  __shared__ double2 C[kTile][kChunk + 1];
-  __shared__ int mrow[kTile];
-
+  extern __shared__ double2 ckn[];                 // [npw_max] conj(c_nk)
+  int *lutk = (int *)(ckn + npw_max);              // [box] lookup of k
   const int n = blockIdx.x, k = blockIdx.y;
   const long long t0 = rowbeg[(size_t)k * nb_max + n], t1 = rowend[(size_t)k * nb_max + n];
   if (t1 <= t0) return;
+  const int lane = threadIdx.x;
   const int kp = kpmap[k];
   const int gs0 = gsmap[3 * k], gs1 = gsmap[3 * k + 1], gs2 = gsmap[3 * k + 2];
   const int npk = npw[k], npj = npw[kp];
-  const int tid = threadIdx.x;
-  const int tx = tid % kTile, ty = tid / kTile;  // tx: G (or G2), ty: m
-
-  for (int i = tid; i < npk; i += 256) {
+  for (int i = lane; i < npk; i += 64) {
     const double2 c = coef[((size_t)k * nb_max + n) * npw_max + i];
     ckn[i] = make_double2(c.x, -c.y);
   }
+  for (long i = lane; i < box; i += 64) lutk[i] = lut[(size_t)k * box + i];
   __syncthreads();
-  const int *lutk = lut + (size_t)k * box;
-  const int *mj = miller + (size_t)kp * npw_max * 3;
   const int W1 = 2 * M1 + 1, W2 = 2 * M2 + 1;
-
-  for (long long tb = t0; tb < t1; tb += kTile) {
-    if (tid < kTile) mrow[tid] = (tb + tid < t1) ? tm[tb + tid] : -1;
-    for (int gb = 0; gb < ld; gb += kTile) {
-      double ar = 0.0, ai = 0.0;
-      for (int jb = 0; jb < npj; jb += kChunk) {
-        __syncthreads();
-        // U[g][j] = conj(c_nk)(G2_j - G_g - G_s), 512 entries
-        for (int e = tid; e < kTile * kChunk; e += 256) {
-          const int g = e / kChunk, j = e % kChunk;
-          const int gi = gb + g, ji = jb + j;
-          double2 u = make_double2(0.0, 0.0);
-          if (gi < n_g && ji < npj) {
-            const int x0 = mj[3 * ji] - gbasis[3 * gi] - gs0 + M0;
-            const int x1 = mj[3 * ji + 1] - gbasis[3 * gi + 1] - gs1 + M1;
-            const int x2 = mj[3 * ji + 2] - gbasis[3 * gi + 2] - gs2 + M2;
-            if (x0 >= 0 && x0 <= 2 * M0 && x1 >= 0 && x1 < W1 && x2 >= 0 && x2 < W2) {
+  const int *mj = miller + (size_t)kp * npw_max * 3;
+  const double2 *cj = coef + (size_t)kp * nb_max * npw_max;
+  const int r = lane & 15, kq = lane >> 4;
+  const int n_gt = ld / 16;
+  for (long long tm0 = t0; tm0 < t1; tm0 += 16) {
+    // this lane's A row: transition tm0 + r (zero past the row)
+    const bool row_ok = tm0 + r < t1;
+    const double2 *crow = cj + (size_t)(row_ok ? tm[tm0 + r] : 0) * npw_max;
+    for (int gt0 = 0; gt0 < n_gt; gt0 += kPdGT) {
+      f64x4 acr[kPdGT], aci[kPdGT];
+      // G + G_s of this lane's column in each tile, packed as three 10-bit
+      // fields offset by 512
+      unsigned gp[kPdGT];
+#pragma unroll
+      for (int q = 0; q < kPdGT; ++q) {
+        acr[q] = aci[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+        const int g = std::min((gt0 + q) * 16 + r, n_g - 1);
+        gp[q] = (unsigned)(gbasis[3 * g] + gs0 + 512) |
+                ((unsigned)(gbasis[3 * g + 1] + gs1 + 512) << 10) |
+                ((unsigned)(gbasis[3 * g + 2] + gs2 + 512) << 20);
+      }
+      for (int j0 = 0; j0 < npj; j0 += 4) {
+        const int j = j0 + kq;
+        const bool j_ok = j < npj && row_ok;
+        const double2 a = j_ok ? crow[j] : make_double2(0.0, 0.0);
+        const int jc = std::min(j, npj - 1);
+        const int m0 = mj[3 * jc] + M0, m1 = mj[3 * jc + 1] + M1, m2 = mj[3 * jc + 2] + M2;
+#pragma unroll
+        for (int q = 0; q < kPdGT; ++q) {
+          if (gt0 + q < n_gt) {  // uniform across the wave
+            const int g = (gt0 + q) * 16 + r;
+            const int x0 = m0 + 512 - (int)(gp[q] & 1023u);
+            const int x1 = m1 + 512 - (int)((gp[q] >> 10) & 1023u);
+            const int x2 = m2 + 512 - (int)(gp[q] >> 20);
+            double2 u = make_double2(0.0, 0.0);
+            if (j < npj && g < n_g && x0 >= 0 && x0 <= 2 * M0 && x1 >= 0 && x1 < W1 && x2 >= 0 &&
+                x2 < W2) {
               const int idx = lutk[((long)x0 * W1 + x1) * W2 + x2];
               if (idx >= 0) u = ckn[idx];
             }
+            acr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, u.x, acr[q], 0, 0, 0);
+            acr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, u.y, acr[q], 0, 0, 0);
+            aci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, u.y, aci[q], 0, 0, 0);
+            aci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, u.x, aci[q], 0, 0, 0);
           }
-          U[g][j] = u;
-        }
-        // C[m][j] = c_mk'(G2_j)
-        for (int e = tid; e < kTile * kChunk; e += 256) {
-          const int mi = e / kChunk, j = e % kChunk;
-          const int m = mrow[mi], ji = jb + j;
-          C[mi][j] = (m >= 0 && ji < npj) ? coef[((size_t)kp * nb_max + m) * npw_max + ji]
-                                          : make_double2(0.0, 0.0);
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int j = 0; j < kChunk; ++j) {
-          const double2 u = U[tx][j], c = C[ty][j];
-          ar = fma(u.x, c.x, ar);
-          ar = fma(-u.y, c.y, ar);
-          ai = fma(u.x, c.y, ai);
-          ai = fma(u.y, c.x, ai);
         }
       }
-      const long long t = tb + ty;
-      if (t < t1) store<FMT>(P, t, gb + tx, ld, n_trans, ar, ai);
+#pragma unroll
+      for (int q = 0; q < kPdGT; ++q) {
+        if (gt0 + q < n_gt) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const long long t = tm0 + kq + 4 * e;
+            if (t < t1) store<FMT>(P, t, (gt0 + q) * 16 + r, ld, n_trans, acr[q][e], aci[q][e]);
+          }
+        }
+      }
     }
-    __syncthreads();
   }
 }
 
@@ -180,8 +202,14 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
   TDX_REQUIRE(ctx && st && qj && tl && gbasis && P, TDX_ERR_INVALID_ARG, "null argument");
   TDX_REQUIRE(prec >= TDX_PREC_FP64 && prec <= TDX_PREC_BF16X3, TDX_ERR_INVALID_ARG, "bad prec");
   TDX_REQUIRE(n_g > 0 && n_trans >= 0 && n_trans <= tl->capacity, TDX_ERR_SHAPE, "bad sizes");
-  TDX_REQUIRE(st->npw_max * sizeof(double2) <= 120 * 1024, TDX_ERR_SHAPE,
-              "plane-wave basis of %d exceeds the LDS row buffer", st->npw_max);
+  for (int i = 0; i < 3; ++i)
+    TDX_REQUIRE(st->mmax[i] < 200, TDX_ERR_SHAPE, "Miller range %d too large", st->mmax[i]);
+  TDX_REQUIRE(st->npw_max * sizeof(double2) +
+                      sizeof(int) * (size_t)(2 * st->mmax[0] + 1) * (2 * st->mmax[1] + 1) *
+                          (2 * st->mmax[2] + 1) <=
+                  150 * 1024,
+              TDX_ERR_SHAPE, "plane-wave basis of %d and its lookup box exceed LDS",
+              st->npw_max);
   TDX_TRY(check_device(ctx));
   if (n_trans == 0) return TDX_OK;
   hipStream_t s = as_stream(stream);
@@ -210,12 +238,12 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
                      nb_max, d_rb, d_re);
   TDX_HIP(hipGetLastError());
   const int ld = ld_of(n_g);
-  const size_t lds = sizeof(double2) * st->npw_max;
+  const size_t lds = sizeof(double2) * st->npw_max + sizeof(int) * (size_t)box;
   dim3 grid(nb_max, nk);
 #define TDX_PD(F)                                                                              \
   TDX_HIP(hipFuncSetAttribute((const void *)k_pair_density<F>,                                 \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));          \
-  hipLaunchKernelGGL(k_pair_density<F>, grid, dim3(256), lds, s, (const double2 *)st->coef,    \
+  hipLaunchKernelGGL(k_pair_density<F>, grid, dim3(64), lds, s, (const double2 *)st->coef,     \
                      st->miller, st->npw, nb_max, st->npw_max, tl->m, d_rb, d_re, d_kp, d_gs,  \
                      gbasis, n_g, ld, d_lut, box, M0, M1, M2, P, (long long)n_trans)
   if (prec == TDX_PREC_FP64) {
