@@ -178,7 +178,10 @@ int tdx_response_basis(const double cell[9], const int kgrid[3], const int qj[3]
  *   k_offsets[n_k + 1] int64 (CSR by k).
  * The count is always written to *count (host).  With capacity < count
  * nothing else is written and SHAPE is returned: call once with
- * capacity 0 to size the buffers.  Synchronises. */
+ * capacity 0 to size the buffers.  A call whose pointers are all null is
+ * such a count query and returns OK when the set is empty.  Otherwise
+ * k_offsets must be given, and the five per-transition arrays too unless
+ * the set is empty (INVALID_ARG).  Synchronises. */
 typedef struct {
   int64_t capacity;
   int *k, *n, *m;
@@ -195,15 +198,22 @@ int tdx_transitions(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
 /* ------------------------------------------------------------------ */
 
 /* rho_t(G) = <n k| e^{-i(q+G).r} |m k+q> = sum_G1 c*_nk(G1) c_m,k'(G1+G+G_s)
- * for every transition t and response vector G (basis from
- * tdx_response_basis, copied to device: gbasis [n_g][3] int32).
- * Computed in FP64; stored per `prec`, row stride ld = n_g rounded up to a
- * multiple of 16 (zero-padded):
+ * for the first n_trans transitions of the list and every response vector G
+ * (basis from tdx_response_basis, copied to device: gbasis [n_g][3] int32).
+ * Computed in FP64 (MFMA); stored per `prec` with row stride ld = n_g rounded
+ * up to a multiple of 16 (zero-padded):
  *   FP64:   complex128 P[T][ld]
  *   FP32:   complex64  P[T][ld]
- *   BF16X3: bf16 quads [T][ld][4] = (re_hi, im_hi, re_lo, im_lo), with
- *           x32 = fp32(x), hi = RNE_bf16(x32), lo = RNE_bf16(x32 - hi).
- * P must hold tdx_pair_density_bytes(...) bytes. */
+ *   BF16X3: with x32 = fp32(x), hi = RNE_bf16(x32), lo = RNE_bf16(x32 - hi)
+ *           and T' = T rounded up to 32 plus 32 (rows past T are zero):
+ *           fragment words uint32 [T'/4][4][ld][4]: for each quad of
+ *           transitions and column, the four 16-byte groups hi, lo, rot(hi),
+ *           rot(lo), each word a (re, im) bf16 pair (re in the low half) and
+ *           rot(re, im) = (-im, re), the last index the transition in the
+ *           quad; then complex64 x32 rows [T'][ld].
+ * P must hold tdx_pair_density_bytes(...) bytes.  tdx_chi0 must be given the
+ * same n_trans as the buffer was written for (the split-BF16 layout depends
+ * on it). */
 size_t tdx_pair_density_bytes(int64_t n_trans, int n_g, int prec);
 int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
                      const tdx_translist *tl, int64_t n_trans,

@@ -365,18 +365,20 @@ def pair_density_bytes(n_trans, n_g, prec):
 
 
 def pair_density(ctx: Context, st: States, qj, tr: Transitions, gbasis: torch.Tensor,
-                 prec: str = "fp64", stream=None,
-                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """P as a flat uint8 device buffer in the layout tdx.h documents; `out`
-    (large enough) is overwritten in place."""
+                 prec: str = "fp64", stream=None, out: Optional[torch.Tensor] = None,
+                 n_trans: Optional[int] = None) -> torch.Tensor:
+    """P as a flat uint8 device buffer in the layout tdx.h documents, for the
+    first n_trans transitions (all by default); `out` (large enough) is
+    overwritten in place."""
     n_g = gbasis.shape[0]
-    nbytes = pair_density_bytes(len(tr), n_g, prec)
+    nt = len(tr) if n_trans is None else int(n_trans)
+    nbytes = pair_density_bytes(nt, n_g, prec)
     if out is not None and out.numel() >= nbytes:
         P = out
     else:
         P = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=st.eps.device)
     q = (C.c_int * 3)(*qj)
-    check(_pair(ctx.handle, C.byref(st.c), q, C.byref(tr.c), len(tr), _ptr(gbasis), n_g,
+    check(_pair(ctx.handle, C.byref(st.c), q, C.byref(tr.c), nt, _ptr(gbasis), n_g,
                 PREC[prec], _ptr(P), _stream(stream)))
     return P
 
@@ -396,11 +398,14 @@ def pair_density_view(P: torch.Tensor, n_trans: int, n_g: int, prec: str) -> tor
 # ------------------------------------------------------------------ chi0
 def chi0(ctx: Context, tr: Transitions, P: torch.Tensor, n_g: int, prec: str,
          omega: torch.Tensor, eta: float, pref: float, out: Optional[torch.Tensor] = None,
-         stream=None) -> torch.Tensor:
+         stream=None, n_trans: Optional[int] = None) -> torch.Tensor:
+    """chi0 over the first n_trans transitions (all by default; P must have
+    been written for the same count)."""
     n_w = omega.shape[0]
+    nt = len(tr) if n_trans is None else int(n_trans)
     if out is None:
         out = torch.empty((n_w, n_g, n_g), dtype=torch.complex128, device=omega.device)
-    check(_chi0(ctx.handle, C.byref(tr.c), len(tr), _ptr(P), n_g, PREC[prec], _ptr(omega), n_w,
+    check(_chi0(ctx.handle, C.byref(tr.c), nt, _ptr(P), n_g, PREC[prec], _ptr(omega), n_w,
                 eta, pref, _ptr(out), _stream(stream)))
     return out
 

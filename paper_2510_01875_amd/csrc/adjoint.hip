@@ -493,7 +493,7 @@ struct QTables {
 };
 
 int q_tables(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const tdx_translist *tl,
-             bool with_lut, hipStream_t s, QTables *q) {
+             long long n_trans, bool with_lut, hipStream_t s, QTables *q) {
   const int nk = st->n_k, nb_max = st->nb_max;
   const int M0 = st->mmax[0], M1 = st->mmax[1], M2 = st->mmax[2];
   q->box = (long)(2 * M0 + 1) * (2 * M1 + 1) * (2 * M2 + 1);
@@ -519,7 +519,7 @@ int q_tables(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const tdx_tran
   TDX_HIP(hipMemcpyAsync(q->kinv, kinv.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
   TDX_HIP(hipMemsetAsync(q->rowbeg, 0, row_bytes, s));
   hipLaunchKernelGGL(k_rows, dim3(nk), dim3(256), 0, s, (const long long *)tl->k_offsets, tl->n,
-                     nb_max, q->rowbeg, q->rowend);
+                     nb_max, n_trans, q->rowbeg, q->rowend);
   TDX_HIP(hipGetLastError());
   if (with_lut) {
     TDX_HIP(hipMemsetAsync(q->lut, 0xff, lut_bytes, s));
@@ -601,7 +601,7 @@ int tdx_weights_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const t
   if (n_trans == 0) return TDX_OK;
   hipStream_t s = as_stream(stream);
   QTables q;
-  TDX_TRY(q_tables(ctx, st, qj, tl, false, s, &q));
+  TDX_TRY(q_tables(ctx, st, qj, tl, n_trans, false, s, &q));
   const long tot = (long)st->n_k * st->nb_max;
   hipLaunchKernelGGL(k_weights_states, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                      (const double2 *)w_bar, tl->df, tl->m, q.rowbeg, q.rowend, st->nb, q.kinv,
@@ -642,7 +642,7 @@ int tdx_pair_density_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
   if (n_trans == 0) return TDX_OK;
   hipStream_t s = as_stream(stream);
   QTables q;
-  TDX_TRY(q_tables(ctx, st, qj, tl, true, s, &q));
+  TDX_TRY(q_tables(ctx, st, qj, tl, n_trans, true, s, &q));
   const int M0 = st->mmax[0], M1 = st->mmax[1], M2 = st->mmax[2];
   dim3 grid(st->nb_max, st->n_k);
   hipLaunchKernelGGL(k_pd_vjp_out, grid, dim3(256), 0, s, (const double2 *)st->coef, st->miller,

@@ -207,7 +207,12 @@ extern "C" int tdx_chi0(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, 
   const int ld = (n_g + 15) / 16 * 16;
   const size_t out_elems = (size_t)n_w * n_g * n_g;
   if (n_trans == 0) {
-    TDX_HIP(hipMemsetAsync(chi0, 0, out_elems * sizeof(double2), s));
+    // a reduction over no slices writes zeros (a kernel, not a memset node,
+    // so a caller may capture this call)
+    const unsigned rb = (unsigned)std::min<size_t>((out_elems + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_reduce_slices, dim3(rb), dim3(256), 0, s, (const double2 *)nullptr, 0,
+                       out_elems, pref, (double2 *)chi0);
+    TDX_HIP(hipGetLastError());
     return TDX_OK;
   }
   if (prec == TDX_PREC_BF16X3)

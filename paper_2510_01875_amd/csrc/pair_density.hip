@@ -235,7 +235,7 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
                      st->npw, st->npw_max, nk, M0, M1, M2, d_lut, box);
   TDX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_rows, dim3(nk), dim3(256), 0, s, (const long long *)tl->k_offsets, tl->n,
-                     nb_max, d_rb, d_re);
+                     nb_max, (long long)n_trans, d_rb, d_re);
   TDX_HIP(hipGetLastError());
   const int ld = ld_of(n_g);
   const size_t lds = sizeof(double2) * st->npw_max + sizeof(int) * (size_t)box;

@@ -18,11 +18,12 @@ __global__ void k_lut(const int *miller, const int *npw, int npw_max, int nk, in
   lut[(size_t)k * box + idx] = i;
 }
 
-// First and one-past-last transition of every (k, n) row (0, 0 if empty).
-__global__ void k_rows(const long long *koff, const int *tn, int nb_max, long long *rowbeg,
-                       long long *rowend) {
+// First and one-past-last transition of every (k, n) row (0, 0 if empty),
+// over the first n_trans transitions of the list only.
+__global__ void k_rows(const long long *koff, const int *tn, int nb_max, long long n_trans,
+                       long long *rowbeg, long long *rowend) {
   const int k = blockIdx.x;
-  const long long t0 = koff[k], t1 = koff[k + 1];
+  const long long t0 = koff[k], t1 = koff[k + 1] < n_trans ? koff[k + 1] : n_trans;
   for (long long t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
     const int n = tn[t];
     if (t == t0 || tn[t - 1] != n) rowbeg[(size_t)k * nb_max + n] = t;

@@ -111,7 +111,9 @@ extern "C" int tdx_transitions(tdx_ctx *ctx, const tdx_states *st, const int qj[
   if (tl->capacity < off[nk])
     return fail(TDX_ERR_SHAPE, "transition capacity %lld < %lld", (long long)tl->capacity,
                 (long long)off[nk]);
-  TDX_REQUIRE(tl->k && tl->n && tl->m && tl->delta && tl->df && tl->k_offsets,
+  if (!tl->k && !tl->n && !tl->m && !tl->delta && !tl->df && !tl->k_offsets)
+    return TDX_OK;  // a count query
+  TDX_REQUIRE(tl->k_offsets && (off[nk] == 0 || (tl->k && tl->n && tl->m && tl->delta && tl->df)),
               TDX_ERR_INVALID_ARG, "a transition buffer is null");
   TDX_HIP(hipMemcpyAsync(d_koff, off.data(), sizeof(long long) * (nk + 1), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_trans_fill, dim3(nk), dim3(kThreads), sizeof(long long) * nb_max, s,
