@@ -206,11 +206,11 @@ int tdx_transitions(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
  *   FP32:   complex64  P[T][ld]
  *   BF16X3: with x32 = fp32(x), hi = RNE_bf16(x32), lo = RNE_bf16(x32 - hi)
  *           and T' = T rounded up to 32 plus 32 (rows past T are zero):
- *           fragment words uint32 [T'/4][4][ld][4]: for each quad of
- *           transitions and column, the four 16-byte groups hi, lo, rot(hi),
- *           rot(lo), each word a (re, im) bf16 pair (re in the low half) and
- *           rot(re, im) = (-im, re), the last index the transition in the
- *           quad; then complex64 x32 rows [T'][ld].
+ *           fragment words uint32 [T'/4][2][ld][4]: for each quad of
+ *           transitions and column, the two 16-byte groups hi and lo, each
+ *           word a (re, im) bf16 pair (re in the low half), the last index
+ *           the transition in the quad; then complex64 x32 rows [T'][ld]
+ *           (16 bytes per row and column in all).
  * P must hold tdx_pair_density_bytes(...) bytes.  tdx_chi0 must be given the
  * same n_trans as the buffer was written for (the split-BF16 layout depends
  * on it). */

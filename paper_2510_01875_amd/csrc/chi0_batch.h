@@ -32,7 +32,7 @@ int bf16x3_variant_occupancy(int v);  // workgroups per CU
 // pair-density buffer laid out for p_rows transitions (rows padded to a
 // multiple of 32 plus one zero chunk of 32).
 inline const void *bf16x3_rho(const void *P, long long p_rows, int ld) {
-  return (const char *)P + (size_t)(((p_rows + 31) / 32 + 1) * 32) * ld * 16;
+  return (const char *)P + (size_t)(((p_rows + 31) / 32 + 1) * 32) * ld * 8;
 }
 
 int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double *delta,

@@ -6,23 +6,30 @@
 // per product.  The left operand A = w_t(w) rho_t(G) is formed in FP32 from
 // the FP64 weight and the stored pair density, then split.
 //
-// One MFMA covers K = 32 reals = 16 transitions with (re, im) interleaved:
-//   A[G][2t + p]     = (Re, Im)(w_t rho_t(G)),
-//   B_re[2t + p][G'] = (Re, Im) rho_t(G'),   B_im[2t + p][G'] = (-Im, Re) rho_t(G'),
-// so that D_re accumulates Re chi0 and D_im accumulates Im chi0.
+// One MFMA covers K = 32 reals = 16 transitions with (re, im) interleaved.
+// With a = w_t rho_t(G) and b = rho_t(G'), chi0(G, G') sums a conj(b):
+//   A[G][2t + p]     = (Re a, Im a),   A_rot[G][2t + p] = (Im a, -Re a),
+//   B[2t + p][G']    = (Re b, Im b),
+// so that A B accumulates Re chi0 and A_rot B accumulates Im chi0.  The
+// rotation is applied to A, which is formed in registers anyway (A_rot is
+// the split of (Im a, -Re a), exactly the rotated split of A because
+// rounding to nearest even is odd-symmetric), so B carries two components
+// (hi, lo) and no rotated copies.
 //
-// A tile is 16 G x (16 SUB) G' for 4 WPW frequencies (4 waves x WPW) over one
-// slice of transitions.  The pair densities arrive in a layout made for this
-// kernel: per quad of transitions and column, the 16-byte groups hi, lo,
-// rot(hi), rot(lo) (rot(re, im) = (-im, re)), so that one 16-byte-per-lane
-// global-to-LDS transfer fills one lane-ordered B fragment, and the FP32 rho
-// rows for the left operand.  Per chunk of CHUNK transitions the fragments
-// and rho rows are copied into LDS with no register staging and no
-// arithmetic; only the weights pass through registers.  The next chunk's
-// transfers are in flight while the current chunk runs (two LDS buffers).  Sums
-// run in FP32 over 256 chunks and are folded into the tile's FP64 partial;
-// slices are reduced in FP64 in a fixed order, so results do not depend on
-// which workgroup ran which tile.
+// A tile is 16 G x (16 NSUB) G' for 4 WPW frequencies (4 waves x WPW) over
+// one slice of transitions.  The pair densities arrive in a layout made for
+// this kernel: per quad of transitions and column, the 16-byte groups hi and
+// lo, so that one 16-byte-per-lane global-to-LDS transfer fills one
+// lane-ordered B fragment, and the FP32 rho rows for the left operand.  Per
+// chunk of CHUNK transitions the fragments and rho rows are copied into LDS
+// with no register staging and no arithmetic; only the weights pass through
+// registers.  The next chunk's transfers are in flight while the current
+// chunk runs (two LDS buffers).  The number of 16-column blocks of a tile is
+// a compile-time constant (the ragged last tile of a row runs its own
+// instance), so the step body is one basic block.  Sums run in FP32 over 256
+// chunks and are folded into the tile's FP64 partial; slices are reduced in
+// FP64 in a fixed order, so results do not depend on which workgroup ran
+// which tile.
 //
 // Two launch forms share the tile routine: a grid with one tile per
 // workgroup, and a persistent grid that walks the longest-first tile list of
@@ -47,10 +54,11 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <int WPW, int SUB, int CHUNK>
 struct Cfg {
   static constexpr int kWBlock = 4 * WPW;  // frequencies per tile
+  static constexpr int kSub = SUB;
   static constexpr int kCols = 16 * SUB;   // G' per tile
   static constexpr int kChunk = CHUNK;
   static constexpr int kSteps = CHUNK / 16;
-  static constexpr int kBWords = kSteps * SUB * 4 * 64 * 4;  // [step][sub][comp][lane][4]
+  static constexpr int kBWords = kSteps * SUB * 2 * 64 * 4;  // [step][sub][comp][lane][4]
   static constexpr int kRhoWords = CHUNK * 16 * 2;           // [t][row] float2
   static constexpr int kWtWords = CHUNK * kWBlock * 2;       // [t][w] float2
   static constexpr int kBufWords = kBWords + kRhoWords + kWtWords;
@@ -68,6 +76,14 @@ __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, 
 
 __device__ inline unsigned int cvt_pk(float a, float b) {
   return __builtin_bit_cast(unsigned int, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
+
+// cvt_pk(a, -b) with the negation as a source modifier of the conversion
+// (the compiler would spend a separate sign flip on it)
+__device__ inline unsigned int cvt_pk_neg_b(float a, float b) {
+  unsigned int r;
+  asm("v_cvt_pk_bf16_f32 %0, %1, -%2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
 }
 
 __device__ inline float lo_f(unsigned int w) { return __uint_as_float(w << 16); }
@@ -95,38 +111,60 @@ __device__ inline void dma16(const void *src, unsigned int *dst) {
 // Wait for this wave's outstanding global loads, LDS transfers included.
 __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0f70); }  // vmcnt(0)
 
-// Stage the B fragments and the FP32 rho rows of the chunk starting at
-// transition tc (a multiple of 16) into buf by LDS DMA.  The pair-density
-// buffer carries a zero chunk past its last transition, so whole chunks are
-// read without clamping; each transfer is a wave-uniform base plus a
-// per-lane offset fixed for the tile (lane_b, lane_r).
+// LDS DMA of one chunk: the B fragments and the FP32 rho rows of CHUNK
+// transitions.  The pair-density buffer carries a zero chunk past its last
+// transition, so whole chunks are read without clamping.  The 1 KB transfers
+// of a chunk are numbered B first, then rho, and dealt to the four waves in
+// turn (transfer x = 4 slot + wave).
 //  - B: block (s, b, comp) is the lane-ordered fragment of K-step s,
-//    16-column block b and component comp (hi, lo, rot hi, rot lo); wave w
-//    stages comp = w of every block.  Lane (kq = l/16, c16 = l%16) copies the
-//    16-byte word group of transitions tc + 16 s + 4 kq .. +3 at column
-//    col0 + 16 b + c16: lane_b = (4 kq ld + c16) * 16 bytes.
+//    16-column block b and component comp (hi, lo).  Lane (kq = l/16,
+//    c16 = l%16) copies the 16-byte word group of transitions
+//    tc + 16 s + 4 kq .. +3 at column col0 + 16 b + c16.
 //  - rho: block d holds float2 slots 64 d .. 64 d + 63 of the layout
 //    rho_index; lane l copies rows row0 + 2 m, +1 (m = l & 7) of transition
-//    tc + 16 (d/2) + 2 (d&1) + h + 4 kq2 (h = l/32, kq2 = l/8 & 3):
-//    lane_r = ((h + 4 kq2) ld + 2 m) * 8 bytes.
-template <class C>
-__device__ inline void dma_chunk(const unsigned char *P4, const unsigned char *R, int ld,
-                                 long long tc, int col0, int row0, int nsub, unsigned int *buf,
-                                 int wave, unsigned lane_b, unsigned lane_r) {
+//    tc + 16 (d/2) + 2 (d&1) + h + 4 kq2 (h = l/32, kq2 = l/8 & 3).
+// Both kinds of source advance by 8 CHUNK ld bytes per chunk (CHUNK/4 quads
+// of 2 x ld 16-byte groups, or CHUNK rows of ld 8-byte values), so each slot
+// keeps the lane's address for the tile's first chunk and adds one uniform
+// offset per chunk; the LDS destination of a slot is fixed.
+template <class C, int NSUB>
+struct DmaPlan {
+  static constexpr int kB = C::kSteps * NSUB * 2, kT = kB + C::kChunk / 8;
+  static constexpr int kSlots = (kT + 3) / 4;
+  const unsigned char *src[kSlots];
+  int dst[kSlots];  // word offset in a buffer
+  bool last_ok;     // the last slot holds a transfer for this wave
+
+  __device__ inline DmaPlan(const unsigned char *P2, const unsigned char *R, int ld,
+                            long long t0, int col0, int row0, int wave, int lane) {
+    const int kq = lane >> 4;
+    const size_t lane_b = (size_t)(2 * kq * ld + (lane & 15)) * 16;
+    const size_t lane_r = (size_t)(((lane >> 5) + 4 * ((lane >> 3) & 3)) * ld + 2 * (lane & 7)) * 8;
 #pragma unroll
-  for (int m = 0; m < C::kSteps * (C::kCols / 16); ++m) {
-    const int s = m / (C::kCols / 16), b = m % (C::kCols / 16);
-    if (b >= nsub) continue;  // uniform across the workgroup
-    const unsigned char *base =
-        P4 + ((((size_t)(tc >> 2) + 4 * s) * 4 + wave) * ld + col0 + 16 * b) * 16;
-    dma16(base + lane_b, buf + (m * 4 + wave) * 256);
+    for (int i = 0; i < kSlots; ++i) {
+      const int x = 4 * i + wave;  // uniform across the wave
+      if (x < kB) {
+        const int m = x >> 1, comp = x & 1;
+        const int st = m / NSUB, b = m % NSUB;
+        src[i] = P2 + ((((size_t)(t0 >> 2) + 4 * st) * 2 + comp) * ld + col0 + 16 * b) * 16 +
+                 lane_b;
+        dst[i] = ((st * C::kSub + b) * 2 + comp) * 256;
+      } else {
+        const int d = std::min(x, kT - 1) - kB;
+        src[i] = R + ((size_t)(t0 + 16 * (d >> 1) + 2 * (d & 1)) * ld + row0) * 8 + lane_r;
+        dst[i] = C::kBWords + d * 256;
+      }
+    }
+    last_ok = 4 * (kSlots - 1) + wave < kT;
   }
-  for (int d = wave; d < C::kChunk / 8; d += 4) {
-    const unsigned char *base =
-        R + ((size_t)(tc + 16 * (d >> 1) + 2 * (d & 1)) * ld + row0) * 8;
-    dma16(base + lane_r, buf + C::kBWords + d * 256);
+
+  // the chunk `off` bytes (8 CHUNK ld per chunk) past the first one
+  __device__ inline void issue(size_t off, unsigned int *buf) const {
+#pragma unroll
+    for (int i = 0; i < kSlots; ++i)
+      if (i < kSlots - 1 || (kT % 4 == 0) || last_ok) dma16(src[i] + off, buf + dst[i]);
   }
-}
+};
 
 // Weights df / (w - delta + i eta) of one chunk: loads into registers ...
 template <class C>
@@ -199,11 +237,11 @@ __device__ inline void fold(f32x4 (&ar)[WPW][SUB], f32x4 (&ai)[WPW][SUB], double
   }
 }
 
-// One tile: rows row0..row0+15, columns col0..col0+kCols-1, frequencies
+// One tile: rows row0..row0+15, columns col0..col0+16*NSUB-1, frequencies
 // w0..w0+kWBlock-1, transitions [t_lo, t_hi).  Sums run in FP32 for at most
 // kFoldChunks chunks and are folded into part (the slice's [n_w][n_g][n_g]
 // block, FP64) between runs.
-template <int WPW, int SUB, int CHUNK>
+template <int WPW, int SUB, int CHUNK, int NSUB>
 __device__ __attribute__((always_inline)) void chi0_tile(
     unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
@@ -213,28 +251,25 @@ __device__ __attribute__((always_inline)) void chi0_tile(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int kq = lane >> 4;
 
-  f32x4 ar[WPW][SUB], ai[WPW][SUB];
+  f32x4 ar[WPW][NSUB], ai[WPW][NSUB];
 #pragma unroll
   for (int i = 0; i < WPW; ++i)
 #pragma unroll
-    for (int b = 0; b < SUB; ++b) {
+    for (int b = 0; b < NSUB; ++b) {
       ar[i][b] = f32x4{0, 0, 0, 0};
       ai[i][b] = f32x4{0, 0, 0, 0};
     }
 
-  const unsigned char *P4 = (const unsigned char *)P, *Rr = (const unsigned char *)R;
   const long long t_max = n_trans - 1;
-  const unsigned lane_b = (unsigned)(4 * kq * ld + (lane & 15)) * 16u;
-  const unsigned lane_r = (unsigned)(((lane >> 5) + 4 * ((lane >> 3) & 3)) * ld + 2 * (lane & 7)) * 8u;
+  const DmaPlan<C, NSUB> dma((const unsigned char *)P, (const unsigned char *)R, ld, t_lo, col0,
+                             row0, wave, lane);
+  const size_t chunk_bytes = (size_t)8 * CHUNK * ld;
   Weights<C> pw;
   const int wi = w0 + tid % C::kWBlock;
   const bool w_ok = wi < n_w;
   const double om = omega[std::min(wi, n_w - 1)];
   const float etaf = (float)eta;
-  // 16-column blocks of this tile inside the padded basis (ld is a multiple
-  // of 16); blocks past it are neither staged nor multiplied
-  const int nsub = std::min(SUB, (ld - col0) / 16);
-  dma_chunk<C>(P4, Rr, ld, t_lo, col0, row0, nsub, lds, wave, lane_b, lane_r);
+  dma.issue(0, lds);
   load_weights<C>(pw, delta, df, t_lo, t_max, tid);
   store_weights<C>(pw, lds, om, w_ok, etaf, tid, t_lo, t_hi);
   wait_vm();
@@ -248,51 +283,51 @@ __device__ __attribute__((always_inline)) void chi0_tile(
       const long long nx = tc + CHUNK;
       const bool more = nx < t_hi;
       if (more) {
-        dma_chunk<C>(P4, Rr, ld, nx, col0, row0, nsub, lds + (cur ^ 1) * C::kBufWords, wave,
-                     lane_b, lane_r);
+        dma.issue((size_t)((nx - t_lo) / CHUNK) * chunk_bytes, lds + (cur ^ 1) * C::kBufWords);
         load_weights<C>(pw, delta, df, nx, t_max, tid);
       }
       const unsigned int *buf = lds + cur * C::kBufWords;
       const u32x4 *bfr = (const u32x4 *)buf;
       const float2 *rq = (const float2 *)(buf + C::kBWords);
       const float2 *wt = (const float2 *)(buf + C::kBWords + C::kRhoWords);
-  #pragma unroll
+#pragma unroll
       for (int s = 0; s < C::kSteps; ++s) {
         float2 rho[4];
-  #pragma unroll
+#pragma unroll
         for (int j = 0; j < 4; ++j) rho[j] = rq[(s * 4 + j) * 64 + lane];
-        u32x4 ah[WPW], al[WPW];
-  #pragma unroll
+        // A and A_rot of the WPW frequencies, split: (hi, lo) words per
+        // transition j of the lane's quad
+        u32x4 ah[WPW], al[WPW], rh[WPW], rl[WPW];
+#pragma unroll
         for (int i = 0; i < WPW; ++i) {
-  #pragma unroll
+#pragma unroll
           for (int j = 0; j < 4; ++j) {
             const float2 w = wt[((s * 4 + j) * C::kWBlock + wave * WPW + i) * 4 + kq];
             const float are = fmaf(w.x, rho[j].x, -w.y * rho[j].y);
             const float aim = fmaf(w.x, rho[j].y, w.y * rho[j].x);
             const unsigned int h = cvt_pk(are, aim);
+            const float dre = are - lo_f(h), dim = aim - hi_f(h);
             ah[i][j] = h;
-            al[i][j] = cvt_pk(are - lo_f(h), aim - hi_f(h));
+            al[i][j] = cvt_pk(dre, dim);
+            rh[i][j] = cvt_pk_neg_b(aim, are);
+            rl[i][j] = cvt_pk_neg_b(dim, dre);
           }
         }
-  #pragma unroll
-        for (int b = 0; b < SUB; ++b) {
-          if (b < nsub) {  // uniform across the workgroup
-          const u32x4 *bp = bfr + ((s * SUB + b) * 4) * 64 + lane;
-          const bf16x8 bhr = as_bf16x8(bp[0]), blr = as_bf16x8(bp[64]);
-          const bf16x8 bhi = as_bf16x8(bp[128]), bli = as_bf16x8(bp[192]);
-  #pragma unroll
+#pragma unroll
+        for (int b = 0; b < NSUB; ++b) {
+          const u32x4 *bp = bfr + ((s * SUB + b) * 2) * 64 + lane;
+          const bf16x8 bh = as_bf16x8(bp[0]), bl = as_bf16x8(bp[64]);
+#pragma unroll
           for (int i = 0; i < WPW; ++i) {
-            const bf16x8 Ah = as_bf16x8(ah[i]), Al = as_bf16x8(al[i]);
             f32x4 cr = ar[i][b], ci = ai[i][b];
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bhr, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bhi, ci, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, blr, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, bli, ci, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, bhr, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, bhi, ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah[i]), bh, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(rh[i]), bh, ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah[i]), bl, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(rh[i]), bl, ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al[i]), bh, cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(rl[i]), bh, ci, 0, 0, 0);
             ar[i][b] = cr;
             ai[i][b] = ci;
-          }
           }
         }
       }
@@ -301,9 +336,28 @@ __device__ __attribute__((always_inline)) void chi0_tile(
       __syncthreads();
       cur ^= 1;
     }
-    fold<WPW, SUB>(ar, ai, part, n_w, n_g, w0, row0, col0, lane, wave, first);
+    fold<WPW, NSUB>(ar, ai, part, n_w, n_g, w0, row0, col0, lane, wave, first);
     first = false;
   }
+}
+
+// The tile routine for the tile's number of 16-column blocks inside the
+// padded basis (ld is a multiple of 16): full tiles run NSUB = SUB, the last
+// tile of a row may run fewer.
+template <int WPW, int SUB, int CHUNK, int NSUB = SUB>
+__device__ __attribute__((always_inline)) void chi0_tile_n(
+    int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
+    const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
+    int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
+  if constexpr (NSUB > 1) {
+    if (nsub < NSUB) {
+      chi0_tile_n<WPW, SUB, CHUNK, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi,
+                                              omega, n_w, eta, n_g, w0, row0, col0, part);
+      return;
+    }
+  }
+  chi0_tile<WPW, SUB, CHUNK, NSUB>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega, n_w,
+                                   eta, n_g, w0, row0, col0, part);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (id % 8), each with
@@ -335,9 +389,10 @@ __global__ void __launch_bounds__(256, OCC)
   const int gb = by / ncb, gc = by % ncb;
   const long long t_lo = (long long)bz * slice_len;
   const long long t_hi = std::min(n_trans, t_lo + slice_len);
-  chi0_tile<WPW, SUB, CHUNK>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega, n_w, eta, n_g,
-                             bx * C::kWBlock, gb * 16, gc * C::kCols,
-                             part + (size_t)bz * n_w * n_g * n_g);
+  const int col0 = gc * C::kCols;
+  chi0_tile_n<WPW, SUB, CHUNK>(std::min(SUB, (ld - col0) / 16), lds, P, R, ld, delta, df, n_trans,
+                               t_lo, t_hi, omega, n_w, eta, n_g, bx * C::kWBlock, gb * 16, col0,
+                               part + (size_t)bz * n_w * n_g * n_g);
 }
 
 // Persistent form: a fixed grid (OCC workgroups per CU) walks the
@@ -359,10 +414,11 @@ __global__ void __launch_bounds__(256, OCC)
     const BatchItem it = items[tl.item];
     const long long t_lo = tl.slice * it.slice_len;
     const long long t_hi = std::min(it.n_trans, t_lo + it.slice_len);
-    chi0_tile<WPW, SUB, CHUNK>(lds, it.P, it.R, it.ld, it.delta, it.df, it.n_trans,
-                               t_lo, t_hi, it.omega, it.n_w, it.eta, it.n_g,
-                               tl.wblk * C::kWBlock, tl.gb * 16, tl.gc * C::kCols,
-                               it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
+    const int col0 = tl.gc * C::kCols;
+    chi0_tile_n<WPW, SUB, CHUNK>(std::min(SUB, (it.ld - col0) / 16), lds, it.P, it.R, it.ld,
+                                 it.delta, it.df, it.n_trans, t_lo, t_hi, it.omega, it.n_w,
+                                 it.eta, it.n_g, tl.wblk * C::kWBlock, tl.gb * 16, col0,
+                                 it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
     __syncthreads();  // the next tile's prologue rewrites the LDS buffers
   }
 }
@@ -380,7 +436,7 @@ struct Variant {
         (const void *)k_chi0_bf16x3_persistent<W, S, K, O>                               \
   }
 const Variant kVariants[] = {TDX_V(4, 4, 32, 2), TDX_V(2, 8, 16, 2), TDX_V(4, 2, 32, 2),
-                             TDX_V(2, 4, 32, 2)};
+                             TDX_V(2, 4, 32, 2), TDX_V(2, 9, 16, 2), TDX_V(2, 8, 32, 2)};
 #undef TDX_V
 
 }  // namespace

@@ -31,9 +31,6 @@ __device__ inline unsigned int rne_bf16(float x) {
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
-// (re | im << 16) -> (-im | re << 16)
-__device__ inline unsigned int rot_neg(unsigned int w) { return ((w >> 16) ^ 0x8000u) | (w << 16); }
-
 template <int FMT>
 __device__ inline void store(void *P, long long t, int g, int ld, long long n_trans, double re,
                              double im) {
@@ -43,20 +40,16 @@ __device__ inline void store(void *P, long long t, int g, int ld, long long n_tr
   } else if (FMT == TDX_PREC_FP32) {
     ((float2 *)P)[i] = make_float2((float)re, (float)im);
   } else {
-    // fragment words [t/4][comp][ld][t%4] with comp = hi, lo, rot(hi), rot(lo)
-    // and each word = (re, im) as two bf16, followed by rho in FP32 [T][ld]
+    // fragment words [t/4][comp][ld][t%4] with comp = hi, lo and each word
+    // = (re, im) as two bf16, followed by rho in FP32 [T][ld]
     const float r32 = (float)re, i32 = (float)im;
     const unsigned int rh = rne_bf16(r32), ih = rne_bf16(i32);
     const unsigned int rl = rne_bf16(r32 - __uint_as_float(rh << 16));
     const unsigned int il = rne_bf16(i32 - __uint_as_float(ih << 16));
-    const unsigned int whi = rh | (ih << 16), wlo = rl | (il << 16);
-    unsigned int *w = (unsigned int *)P + (((size_t)(t >> 2) * 4) * ld + g) * 4 + (t & 3);
-    const size_t comp = (size_t)ld * 4;
-    w[0] = whi;
-    w[comp] = wlo;
-    w[2 * comp] = rot_neg(whi);
-    w[3 * comp] = rot_neg(wlo);
-    float2 *R = (float2 *)((char *)P + (size_t)pad_rows(n_trans) * ld * 16);
+    unsigned int *w = (unsigned int *)P + (((size_t)(t >> 2) * 2) * ld + g) * 4 + (t & 3);
+    w[0] = rh | (ih << 16);
+    w[(size_t)ld * 4] = rl | (il << 16);
+    float2 *R = (float2 *)((char *)P + (size_t)pad_rows(n_trans) * ld * 8);
     R[i] = make_float2(r32, i32);
   }
 }
@@ -68,14 +61,14 @@ __global__ void k_zero_pad(unsigned int *P, long long n_trans, int ld) {
   const long long q0 = n_trans >> 2;
   const int r0 = (int)(n_trans & 3);
   const long long nq = rows / 4 - q0;
-  const long long nfrag = nq * 16 * ld;
+  const long long nfrag = nq * 8 * ld;  // words per quad: 2 components x ld x 4
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nfrag;
        e += (long long)gridDim.x * blockDim.x) {
     const int jj = (int)(e & 3);
-    if (e < 16LL * ld && jj < r0) continue;  // live rows of the partial quad
-    P[(size_t)q0 * 16 * ld + e] = 0u;
+    if (e < 8LL * ld && jj < r0) continue;  // live rows of the partial quad
+    P[(size_t)q0 * 8 * ld + e] = 0u;
   }
-  float2 *R = (float2 *)((char *)P + (size_t)rows * ld * 16);
+  float2 *R = (float2 *)((char *)P + (size_t)rows * ld * 8);
   const long long nrho = (rows - n_trans) * ld;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nrho;
        e += (long long)gridDim.x * blockDim.x)
@@ -190,7 +183,7 @@ using namespace tdx;
 extern "C" {
 
 size_t tdx_pair_density_bytes(int64_t n_trans, int n_g, int prec) {
-  if (prec == TDX_PREC_BF16X3) return (size_t)pad_rows(n_trans) * ld_of(n_g) * 24;
+  if (prec == TDX_PREC_BF16X3) return (size_t)pad_rows(n_trans) * ld_of(n_g) * 16;
   const size_t per = prec == TDX_PREC_FP64 ? 16 : 8;
   return (size_t)n_trans * ld_of(n_g) * per;
 }

@@ -104,7 +104,7 @@ def test_pair_density_bytes(tdx):
     assert tdx.pair_density_bytes(10, 17, "fp64") == 10 * 32 * 16
     assert tdx.pair_density_bytes(10, 17, "fp32") == 10 * 32 * 8
     # split-BF16: rows padded to a multiple of 32 plus one zero chunk of 32
-    # (64 rows here) x 32 columns x (16 bytes of fragment words + 8 of FP32 rho)
-    assert tdx.pair_density_bytes(10, 17, "bf16x3") == 64 * 32 * 24
-    assert tdx.pair_density_bytes(32, 17, "bf16x3") == 64 * 32 * 24
-    assert tdx.pair_density_bytes(33, 17, "bf16x3") == 96 * 32 * 24
+    # (64 rows here) x 32 columns x (8 bytes of fragment words + 8 of FP32 rho)
+    assert tdx.pair_density_bytes(10, 17, "bf16x3") == 64 * 32 * 16
+    assert tdx.pair_density_bytes(32, 17, "bf16x3") == 64 * 32 * 16
+    assert tdx.pair_density_bytes(33, 17, "bf16x3") == 96 * 32 * 16

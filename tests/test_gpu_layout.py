@@ -1,9 +1,8 @@
 """The split-BF16 pair-density buffer, decoded word by word and compared bit
 for bit with the FP64 pair densities of the same transitions rounded the
 documented way: x32 = fp32(x), hi = RNE_bf16(x32), lo = RNE_bf16(x32 - hi);
-fragment words [t/4][comp][ld][t%4] with comp = hi, lo, rot(hi), rot(lo),
-word = (re, im) as bf16 (low half re), rot(re, im) = (-im, re); then the FP32
-rows x32 [T][ld]; rows are padded to a multiple of 32 plus one chunk of 32,
+fragment words [t/4][comp][ld][t%4] with comp = hi, lo, word = (re, im) as
+bf16 (low half re); then the FP32 rows x32 [T][ld]; rows are padded to a multiple of 32 plus one chunk of 32,
 all zero past T.  The crystal with screening at 1e-4 has a transition count
 that is not a multiple of 4, which checks the zeroed tail quad; chi0 from that
 buffer is checked against the FP64 path on the same transitions."""
@@ -48,9 +47,9 @@ def test_split_bf16_layout_is_bit_exact(tdx):
     buf = tdx.pair_density(ctx, st, q, tr, gb, "bf16x3")
     torch.cuda.synchronize()
     T4 = ((T + 31) // 32 + 1) * 32          # rows padded to 32 plus one zero chunk
-    assert buf.numel() >= T4 * ld * 24
-    words = buf[: T4 * ld * 16].view(torch.int32).view(T4 // 4, 4, ld, 4)
-    Rall = buf[T4 * ld * 16: T4 * ld * 24].view(torch.float32).view(T4, ld, 2)
+    assert buf.numel() >= T4 * ld * 16
+    words = buf[: T4 * ld * 8].view(torch.int32).view(T4 // 4, 2, ld, 4)
+    Rall = buf[T4 * ld * 8: T4 * ld * 16].view(torch.float32).view(T4, ld, 2)
     R = Rall[:T]
     assert int((Rall[T:] != 0).sum()) == 0
     x = torch.zeros((T4, ld), dtype=torch.complex128, device="cuda")
@@ -60,9 +59,7 @@ def test_split_bf16_layout_is_bit_exact(tdx):
     rh, ih = re32.to(torch.bfloat16).to(torch.float32), im32.to(torch.bfloat16).to(torch.float32)
     hi = _bits16(re32) | (_bits16(im32) << 16)
     lo = _bits16(re32 - rh) | (_bits16(im32 - ih) << 16)
-    neg = lambda b: b ^ 0x8000
-    rot = lambda wd: neg((wd >> 16) & 0xFFFF) | ((wd & 0xFFFF) << 16)
-    for comp, ref in enumerate((hi, lo, rot(hi), rot(lo))):
+    for comp, ref in enumerate((hi, lo)):
         # words [T4/4][ld][4] -> rows t = 4 q + j
         got = words[:, comp].permute(0, 2, 1).reshape(T4, ld)
         assert torch.equal(got[:T], ref[:T].to(torch.int32)), f"component {comp}"
