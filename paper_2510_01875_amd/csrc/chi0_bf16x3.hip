@@ -62,7 +62,6 @@ struct Cfg {
   static constexpr int kRhoWords = CHUNK * 16 * 2;           // [t][row] float2
   static constexpr int kWtWords = CHUNK * kWBlock * 2;       // [t][w] float2
   static constexpr int kBufWords = kBWords + kRhoWords + kWtWords;
-  static constexpr size_t kLds = 2 * (size_t)kBufWords * 4;
   // weights per thread; when the chunk holds fewer than 256 weights only the
   // first CHUNK * kWBlock threads store one
   static constexpr bool kWPart = CHUNK * kWBlock < 256;
@@ -111,6 +110,14 @@ __device__ inline void dma16(const void *src, unsigned int *dst) {
 // Wait for this wave's outstanding global loads, LDS transfers included.
 __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0f70); }  // vmcnt(0)
 
+// Wait until at most N of them are outstanding (they complete in issue
+// order): vmcnt is split over bits 3:0 and 15:14 of the immediate.
+template <int N>
+__device__ inline void wait_vm_n() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 // LDS DMA of one chunk: the B fragments and the FP32 rho rows of CHUNK
 // transitions.  The pair-density buffer carries a zero chunk past its last
 // transition, so whole chunks are read without clamping.  The 1 KB transfers
@@ -131,6 +138,7 @@ template <class C, int NSUB>
 struct DmaPlan {
   static constexpr int kB = C::kSteps * NSUB * 2, kT = kB + C::kChunk / 8;
   static constexpr int kSlots = (kT + 3) / 4;
+  static constexpr int kIssued = kT / 4;  // transfers every wave issues per chunk
   const unsigned char *src[kSlots];
   int dst[kSlots];  // word offset in a buffer
   bool last_ok;     // the last slot holds a transfer for this wave
@@ -189,10 +197,8 @@ __device__ inline void load_weights(Weights<C> &pw, const double *delta, const d
 // (relative error ~1e-7, far below the 2^-16 of the split products); zero
 // past the end of the slice or of the frequency grid.
 template <class C>
-__device__ inline void store_weights(const Weights<C> &pw, unsigned int *buf, double om,
-                                     bool w_ok, float eta, int tid, long long tc,
-                                     long long t_hi) {
-  float2 *wt = (float2 *)(buf + C::kBWords + C::kRhoWords);
+__device__ inline void store_weights(const Weights<C> &pw, float2 *wt, double om, bool w_ok,
+                                     float eta, int tid, long long tc, long long t_hi) {
   const int tw = tid / C::kWBlock, wi = tid % C::kWBlock;
 #pragma unroll
   for (int i = 0; i < C::kNW; ++i) {
@@ -240,8 +246,10 @@ __device__ inline void fold(f32x4 (&ar)[WPW][SUB], f32x4 (&ai)[WPW][SUB], double
 // One tile: rows row0..row0+15, columns col0..col0+16*NSUB-1, frequencies
 // w0..w0+kWBlock-1, transitions [t_lo, t_hi).  Sums run in FP32 for at most
 // kFoldChunks chunks and are folded into part (the slice's [n_w][n_g][n_g]
-// block, FP64) between runs.
-template <int WPW, int SUB, int CHUNK, int NSUB>
+// block, FP64) between runs.  DEPTH LDS buffers: the transfers of chunk
+// c + DEPTH - 1 are issued in iteration c; with three buffers the wait at the
+// end of an iteration leaves that iteration's transfers in flight.
+template <int WPW, int SUB, int CHUNK, int NSUB, int DEPTH>
 __device__ __attribute__((always_inline)) void chi0_tile(
     unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
@@ -269,22 +277,28 @@ __device__ __attribute__((always_inline)) void chi0_tile(
   const bool w_ok = wi < n_w;
   const double om = omega[std::min(wi, n_w - 1)];
   const float etaf = (float)eta;
-  dma.issue(0, lds);
-  load_weights<C>(pw, delta, df, t_lo, t_max, tid);
-  store_weights<C>(pw, lds, om, w_ok, etaf, tid, t_lo, t_hi);
+#pragma unroll
+  for (int k = 0; k < DEPTH - 1; ++k) {
+    if (t_lo + k * CHUNK >= t_hi) break;
+    dma.issue((size_t)k * chunk_bytes, lds + k * C::kBufWords);
+    load_weights<C>(pw, delta, df, t_lo + k * CHUNK, t_max, tid);
+    store_weights<C>(pw, (float2 *)(lds + k * C::kBufWords + C::kBWords + C::kRhoWords), om, w_ok,
+                     etaf, tid, t_lo + k * CHUNK, t_hi);
+  }
   wait_vm();
   __syncthreads();
-  int cur = 0;
+  int cur = 0, ahead = DEPTH - 1;  // buffers of chunk c and of chunk c + DEPTH - 1
   bool first = true;
   constexpr long long kRun = (long long)kFoldChunks * CHUNK;
   for (long long rs = t_lo; rs < t_hi; rs += kRun) {
     const long long re = std::min(t_hi, rs + kRun);
     for (long long tc = rs; tc < re; tc += CHUNK) {
-      const long long nx = tc + CHUNK;
+      const long long nx = tc + (DEPTH - 1) * CHUNK;
       const bool more = nx < t_hi;
       if (more) {
-        dma.issue((size_t)((nx - t_lo) / CHUNK) * chunk_bytes, lds + (cur ^ 1) * C::kBufWords);
+        // weights first: a partial wait below leaves the transfers in flight
         load_weights<C>(pw, delta, df, nx, t_max, tid);
+        dma.issue((size_t)((nx - t_lo) / CHUNK) * chunk_bytes, lds + ahead * C::kBufWords);
       }
       const unsigned int *buf = lds + cur * C::kBufWords;
       const u32x4 *bfr = (const u32x4 *)buf;
@@ -313,28 +327,47 @@ __device__ __attribute__((always_inline)) void chi0_tile(
             rl[i][j] = cvt_pk_neg_b(dim, dre);
           }
         }
+        // B fragments one column block ahead: the reads of block b + 1 are
+        // in flight while the MFMAs of block b run (a fence per block keeps
+        // that order)
+        bf16x8 bh[2], bl[2];
+        {
+          const u32x4 *bp = bfr + ((s * SUB) * 2) * 64 + lane;
+          bh[0] = as_bf16x8(bp[0]);
+          bl[0] = as_bf16x8(bp[64]);
+        }
 #pragma unroll
         for (int b = 0; b < NSUB; ++b) {
-          const u32x4 *bp = bfr + ((s * SUB + b) * 2) * 64 + lane;
-          const bf16x8 bh = as_bf16x8(bp[0]), bl = as_bf16x8(bp[64]);
+          if (b + 1 < NSUB) {
+            const u32x4 *bp = bfr + ((s * SUB + b + 1) * 2) * 64 + lane;
+            bh[(b + 1) & 1] = as_bf16x8(bp[0]);
+            bl[(b + 1) & 1] = as_bf16x8(bp[64]);
+          }
 #pragma unroll
           for (int i = 0; i < WPW; ++i) {
             f32x4 cr = ar[i][b], ci = ai[i][b];
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah[i]), bh, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(rh[i]), bh, ci, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah[i]), bl, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(rh[i]), bl, ci, 0, 0, 0);
-            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al[i]), bh, cr, 0, 0, 0);
-            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(rl[i]), bh, ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah[i]), bh[b & 1], cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(rh[i]), bh[b & 1], ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah[i]), bl[b & 1], cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(rh[i]), bl[b & 1], ci, 0, 0, 0);
+            cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al[i]), bh[b & 1], cr, 0, 0, 0);
+            ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(rl[i]), bh[b & 1], ci, 0, 0, 0);
             ar[i][b] = cr;
             ai[i][b] = ci;
           }
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
-      if (more) store_weights<C>(pw, lds + (cur ^ 1) * C::kBufWords, om, w_ok, etaf, tid, nx, t_hi);
-      wait_vm();
+      if (more)
+        store_weights<C>(pw, (float2 *)(lds + ahead * C::kBufWords + C::kBWords + C::kRhoWords),
+                         om, w_ok, etaf, tid, nx, t_hi);
+      if (DEPTH > 2 && more)
+        wait_vm_n<DmaPlan<C, NSUB>::kIssued>();
+      else
+        wait_vm();
       __syncthreads();
-      cur ^= 1;
+      cur = cur == DEPTH - 1 ? 0 : cur + 1;
+      ahead = ahead == DEPTH - 1 ? 0 : ahead + 1;
     }
     fold<WPW, NSUB>(ar, ai, part, n_w, n_g, w0, row0, col0, lane, wave, first);
     first = false;
@@ -344,20 +377,304 @@ __device__ __attribute__((always_inline)) void chi0_tile(
 // The tile routine for the tile's number of 16-column blocks inside the
 // padded basis (ld is a multiple of 16): full tiles run NSUB = SUB, the last
 // tile of a row may run fewer.
-template <int WPW, int SUB, int CHUNK, int NSUB = SUB>
+template <int WPW, int SUB, int CHUNK, int DEPTH, int NSUB = SUB>
 __device__ __attribute__((always_inline)) void chi0_tile_n(
     int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
     int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
   if constexpr (NSUB > 1) {
     if (nsub < NSUB) {
-      chi0_tile_n<WPW, SUB, CHUNK, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi,
-                                              omega, n_w, eta, n_g, w0, row0, col0, part);
+      chi0_tile_n<WPW, SUB, CHUNK, DEPTH, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo,
+                                                     t_hi, omega, n_w, eta, n_g, w0, row0, col0,
+                                                     part);
       return;
     }
   }
-  chi0_tile<WPW, SUB, CHUNK, NSUB>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega, n_w,
-                                   eta, n_g, w0, row0, col0, part);
+  chi0_tile<WPW, SUB, CHUNK, NSUB, DEPTH>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
+                                          n_w, eta, n_g, w0, row0, col0, part);
+}
+
+// ---------------------------------------------------------------------------
+// Software-pipelined tile (one wave per SIMD).  While the MFMAs of K-step g
+// run, the same wave forms the split left operand of step g + 1 in the VALU,
+// so the two pipes overlap inside one wave.  With no second wave on the SIMD
+// to cover a late transfer, the transfers run further ahead: B fragments in
+// three buffers filled two chunks ahead, rho rows and weights (needed one
+// chunk before their B, for the formation) in four slots filled three chunks
+// ahead.  In iteration c:
+//   load the weights of c+3; issue B(c+2) -> buffer (c+2)%3 and rho(c+3) ->
+//   slot (c+3)%4; per K-step: MFMAs on A(g) and B(c) || form A(g+1) from
+//   slot c%4 (slot (c+1)%4 for the last step); store the weights of c+3;
+//   wait for this wave's transfers of iteration c-1 and older; barrier.
+// Every buffer or slot written in iteration c was last read in iteration
+// c-1, before the barrier that ends it, and every transfer read in iteration
+// c was issued in iteration c-2 or earlier and waited for at the end of c-1.
+// Two register sets hold A(g) and A(g+1), which needs the 512 registers of a
+// lone wave.
+
+// The split left operand of one K-step for the WPW frequencies of the wave:
+// A[i][0..3] = hi, lo of (Re a, Im a) and of (Im a, -Re a).
+template <class C, int WPW>
+__device__ inline void form_a(u32x4 (&A)[WPW][4], const float2 *rq, const float2 *wt, int s,
+                              int lane, int kq, int wave) {
+  float2 rho[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) rho[j] = rq[(s * 4 + j) * 64 + lane];
+#pragma unroll
+  for (int i = 0; i < WPW; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float2 w = wt[((s * 4 + j) * C::kWBlock + wave * WPW + i) * 4 + kq];
+      const float are = fmaf(w.x, rho[j].x, -w.y * rho[j].y);
+      const float aim = fmaf(w.x, rho[j].y, w.y * rho[j].x);
+      const unsigned int h = cvt_pk(are, aim);
+      const float dre = are - lo_f(h), dim = aim - hi_f(h);
+      A[i][0][j] = h;
+      A[i][1][j] = cvt_pk(dre, dim);
+      A[i][2][j] = cvt_pk_neg_b(aim, are);
+      A[i][3][j] = cvt_pk_neg_b(dim, dre);
+    }
+  }
+}
+
+// One K-step of the pipelined tile: the MFMAs of step s on A (B from bfr)
+// and, interleaved with them, the formation of An for step sn from rqn,
+// wtn.  Per 16-column block: the B reads of the next block, the block's
+// MFMAs, one element (i, j) of the formation; a scheduling fence after each
+// block keeps the pieces in this order, so the VALU work of the formation
+// issues between the MFMAs of the same wave.
+template <class C, int WPW, int NSUB>
+__device__ inline void step_pipe(f32x4 (&ar)[WPW][NSUB], f32x4 (&ai)[WPW][NSUB],
+                                 const u32x4 (&A)[WPW][4], u32x4 (&An)[WPW][4],
+                                 const u32x4 *bfr, int s, const float2 *rqn, const float2 *wtn,
+                                 int sn, int lane, int kq, int wave) {
+  float2 rho[4], w[WPW][4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) rho[j] = rqn[(sn * 4 + j) * 64 + lane];
+#pragma unroll
+  for (int i = 0; i < WPW; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[i][j] = wtn[((sn * 4 + j) * C::kWBlock + wave * WPW + i) * 4 + kq];
+  auto element = [&](int e) {
+    const int i = e / 4, j = e % 4;
+    const float are = fmaf(w[i][j].x, rho[j].x, -w[i][j].y * rho[j].y);
+    const float aim = fmaf(w[i][j].x, rho[j].y, w[i][j].y * rho[j].x);
+    const unsigned int h = cvt_pk(are, aim);
+    const float dre = are - lo_f(h), dim = aim - hi_f(h);
+    An[i][0][j] = h;
+    An[i][1][j] = cvt_pk(dre, dim);
+    An[i][2][j] = cvt_pk_neg_b(aim, are);
+    An[i][3][j] = cvt_pk_neg_b(dim, dre);
+  };
+  bf16x8 bh[2], bl[2];
+  {
+    const u32x4 *bp = bfr + ((s * C::kSub) * 2) * 64 + lane;
+    bh[0] = as_bf16x8(bp[0]);
+    bl[0] = as_bf16x8(bp[64]);
+  }
+#pragma unroll
+  for (int b = 0; b < NSUB; ++b) {
+    if (b + 1 < NSUB) {
+      const u32x4 *bp = bfr + ((s * C::kSub + b + 1) * 2) * 64 + lane;
+      bh[(b + 1) & 1] = as_bf16x8(bp[0]);
+      bl[(b + 1) & 1] = as_bf16x8(bp[64]);
+    }
+#pragma unroll
+    for (int i = 0; i < WPW; ++i) {
+      f32x4 cr = ar[i][b], ci = ai[i][b];
+      cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A[i][0]), bh[b & 1], cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A[i][2]), bh[b & 1], ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A[i][0]), bl[b & 1], cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A[i][2]), bl[b & 1], ci, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A[i][1]), bh[b & 1], cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(A[i][3]), bh[b & 1], ci, 0, 0, 0);
+      ar[i][b] = cr;
+      ai[i][b] = ci;
+    }
+    if (b < 4 * WPW) element(b);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int e = NSUB; e < 4 * WPW; ++e) element(e);
+}
+
+// LDS DMA of the pipelined tile.  Transfers are dealt to the waves per
+// kind: B transfer x = 4 slot + wave (slots 0 .. kSB-1), rho transfer
+// d = 4 slot' + wave (the kSR slots after them), so every slot's kind is
+// fixed at compile time; a slot is empty for a wave only when its kind's
+// count is not a multiple of four.
+template <class C, int NSUB>
+struct DmaPlanPipe {
+  static constexpr int kB = C::kSteps * NSUB * 2, kR = C::kChunk / 8;
+  static constexpr int kSB = (kB + 3) / 4, kSR = (kR + 3) / 4;
+  // B and rho transfers that every wave issues per chunk (a lower bound for
+  // the waves that also fill a last, partial slot)
+  static constexpr int kIssuedB = kB / 4, kIssuedR = kR / 4;
+  const unsigned char *base_b, *base_r;  // the tile's first chunk (uniform)
+  unsigned off[kSB + kSR];               // the lane's byte offset per slot
+  int dst[kSB + kSR];                    // word offset in a B buffer or a rho slot
+  bool lastb_ok, lastr_ok;
+
+  __device__ inline DmaPlanPipe(const unsigned char *P2, const unsigned char *R, int ld,
+                                long long t0, int col0, int row0, int wave, int lane) {
+    const int kq = lane >> 4;
+    base_b = P2 + ((size_t)(t0 >> 2) * 2 * ld + col0) * 16;
+    base_r = R + ((size_t)t0 * ld + row0) * 8;
+    const unsigned lane_b = (unsigned)(2 * kq * ld + (lane & 15)) * 16u;
+    const unsigned lane_r = (unsigned)(((lane >> 5) + 4 * ((lane >> 3) & 3)) * ld + 2 * (lane & 7)) * 8u;
+#pragma unroll
+    for (int i = 0; i < kSB; ++i) {
+      const int x = std::min(4 * i + wave, kB - 1);
+      const int m = x >> 1, comp = x & 1;
+      const int st = m / NSUB, b = m % NSUB;
+      off[i] = (unsigned)(((4 * st) * 2 + comp) * ld + 16 * b) * 16u + lane_b;
+      dst[i] = ((st * C::kSub + b) * 2 + comp) * 256;
+    }
+#pragma unroll
+    for (int i = 0; i < kSR; ++i) {
+      const int d = std::min(4 * i + wave, kR - 1);
+      off[kSB + i] = (unsigned)((16 * (d >> 1) + 2 * (d & 1)) * ld) * 8u + lane_r;
+      dst[kSB + i] = d * 256;
+    }
+    lastb_ok = 4 * (kSB - 1) + wave < kB;
+    lastr_ok = 4 * (kSR - 1) + wave < kR;
+  }
+
+  // B / rho of the chunk `pos` bytes past the tile's first one into buf
+  __device__ inline void issue_b(size_t pos, unsigned int *buf) const {
+    const unsigned char *b = base_b + pos;
+#pragma unroll
+    for (int i = 0; i < kSB; ++i)
+      if (i < kSB - 1 || kB % 4 == 0 || lastb_ok) dma16(b + off[i], buf + dst[i]);
+  }
+  __device__ inline void issue_r(size_t pos, unsigned int *buf) const {
+    const unsigned char *r = base_r + pos;
+#pragma unroll
+    for (int i = 0; i < kSR; ++i)
+      if (i < kSR - 1 || kR % 4 == 0 || lastr_ok) dma16(r + off[kSB + i], buf + dst[kSB + i]);
+  }
+};
+
+template <int WPW, int SUB, int CHUNK>
+struct PipeLds {
+  typedef Cfg<WPW, SUB, CHUNK> C;
+  static constexpr int kRW = C::kRhoWords + C::kWtWords;  // one rho/weight slot
+  static constexpr int kBBufs = 3, kRWSlots = 4;
+  static constexpr size_t kBytes = (size_t)(kBBufs * C::kBWords + kRWSlots * kRW) * 4;
+};
+
+template <int WPW, int SUB, int CHUNK, int NSUB>
+__device__ __attribute__((always_inline)) void chi0_tile_pipe(
+    unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
+    const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
+    int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
+  typedef Cfg<WPW, SUB, CHUNK> C;
+  typedef PipeLds<WPW, SUB, CHUNK> L;
+  static_assert(C::kSteps % 2 == 0, "the A register sets alternate per K-step");
+  unsigned int *bring = lds, *rwring = lds + L::kBBufs * C::kBWords;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int kq = lane >> 4;
+
+  f32x4 ar[WPW][NSUB], ai[WPW][NSUB];
+#pragma unroll
+  for (int i = 0; i < WPW; ++i)
+#pragma unroll
+    for (int b = 0; b < NSUB; ++b) {
+      ar[i][b] = f32x4{0, 0, 0, 0};
+      ai[i][b] = f32x4{0, 0, 0, 0};
+    }
+
+  typedef DmaPlanPipe<C, NSUB> D;
+  const long long t_max = n_trans - 1;
+  const D dma((const unsigned char *)P, (const unsigned char *)R, ld, t_lo, col0, row0, wave,
+              lane);
+  const size_t chunk_bytes = (size_t)8 * CHUNK * ld;
+  const long long n_chunks = (t_hi - t_lo + CHUNK - 1) / CHUNK;
+  Weights<C> pw;
+  const int wi = w0 + tid % C::kWBlock;
+  const bool w_ok = wi < n_w;
+  const double om = omega[std::min(wi, n_w - 1)];
+  const float etaf = (float)eta;
+  // buffers and slots by index (chunk k uses B buffer k % 3, slot k % 4)
+  auto bbuf = [&](int i) { return bring + i * C::kBWords; };
+  auto rbuf = [&](int i) { return rwring + i * L::kRW; };
+  auto rho_of = [&](int i) { return (const float2 *)(rwring + i * L::kRW); };
+  auto wt_of = [&](int i) { return (float2 *)(rwring + i * L::kRW + C::kRhoWords); };
+
+  // prologue: B of chunks 0, 1; rho and weights of chunks 0, 1, 2
+  for (int k = 0; k < 3 && k < n_chunks; ++k) {
+    if (k < 2) dma.issue_b((size_t)k * chunk_bytes, bbuf(k));
+    dma.issue_r((size_t)k * chunk_bytes, rbuf(k));
+    load_weights<C>(pw, delta, df, t_lo + k * CHUNK, t_max, tid);
+    store_weights<C>(pw, wt_of(k), om, w_ok, etaf, tid, t_lo + k * CHUNK, t_hi);
+  }
+  wait_vm();
+  __syncthreads();
+  u32x4 A0[WPW][4], A1[WPW][4];
+  form_a<C, WPW>(A0, rho_of(0), wt_of(0), 0, lane, kq, wave);
+
+  bool first = true;
+  long long c = 0;
+  int b0 = 0, b2 = 2;          // B buffers of chunks c, c+2
+  int r0 = 0, r1 = 1, r3 = 3;  // rho/weight slots of chunks c, c+1, c+3
+  for (long long run = 0; run < n_chunks; run += kFoldChunks) {
+    const long long run_end = std::min(n_chunks, run + kFoldChunks);
+    for (; c < run_end; ++c) {
+      const bool more2 = c + 2 < n_chunks, more3 = c + 3 < n_chunks;
+      // weights first: the wait at the end of the iteration may leave the
+      // transfers issued after them in flight
+      if (more3) load_weights<C>(pw, delta, df, t_lo + (c + 3) * CHUNK, t_max, tid);
+      if (more2) dma.issue_b((size_t)(c + 2) * chunk_bytes, bbuf(b2));
+      if (more3) dma.issue_r((size_t)(c + 3) * chunk_bytes, rbuf(r3));
+      const u32x4 *bfr = (const u32x4 *)bbuf(b0);
+#pragma unroll
+      for (int s = 0; s < C::kSteps; s += 2) {
+        // step s on A0 forming A1 (step s + 1 of this chunk); step s + 1 on
+        // A1 forming A0 (the next step: of this chunk, or step 0 of the next)
+        step_pipe<C, WPW, NSUB>(ar, ai, A0, A1, bfr, s, rho_of(r0), wt_of(r0), s + 1, lane, kq,
+                                wave);
+        if (s + 2 < C::kSteps)
+          step_pipe<C, WPW, NSUB>(ar, ai, A1, A0, bfr, s + 1, rho_of(r0), wt_of(r0), s + 2, lane,
+                                  kq, wave);
+        else
+          step_pipe<C, WPW, NSUB>(ar, ai, A1, A0, bfr, s + 1, rho_of(r1), wt_of(r1), 0, lane, kq,
+                                  wave);
+      }
+      if (more3)
+        store_weights<C>(pw, wt_of(r3), om, w_ok, etaf, tid, t_lo + (c + 3) * CHUNK, t_hi);
+      // this iteration's transfers may stay in flight; older ones are done
+      if (more2 && more3)
+        wait_vm_n<D::kIssuedB + D::kIssuedR>();
+      else
+        wait_vm();
+      __syncthreads();
+      b0 = b0 == 2 ? 0 : b0 + 1;
+      b2 = b2 == 2 ? 0 : b2 + 1;
+      r0 = r1;
+      r1 = (r1 + 1) & 3;
+      r3 = (r3 + 1) & 3;
+    }
+    fold<WPW, NSUB>(ar, ai, part, n_w, n_g, w0, row0, col0, lane, wave, first);
+    first = false;
+  }
+}
+
+template <int WPW, int SUB, int CHUNK, int NSUB = SUB>
+__device__ __attribute__((always_inline)) void chi0_tile_pipe_n(
+    int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
+    const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
+    int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
+  if constexpr (NSUB > 1) {
+    if (nsub < NSUB) {
+      chi0_tile_pipe_n<WPW, SUB, CHUNK, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo,
+                                                   t_hi, omega, n_w, eta, n_g, w0, row0, col0,
+                                                   part);
+      return;
+    }
+  }
+  chi0_tile_pipe<WPW, SUB, CHUNK, NSUB>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
+                                        n_w, eta, n_g, w0, row0, col0, part);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (id % 8), each with
@@ -370,12 +687,28 @@ __device__ inline int xcd_logical(int id, int total) {
   return (id % 8) * per + id / 8;
 }
 
+// The tile routine of a variant: plain (PIPE false, DEPTH buffers) or
+// software-pipelined.
+template <int WPW, int SUB, int CHUNK, bool PIPE, int DEPTH>
+__device__ __attribute__((always_inline)) void run_tile(
+    int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
+    const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
+    int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
+  if constexpr (PIPE)
+    chi0_tile_pipe_n<WPW, SUB, CHUNK>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
+                                      n_w, eta, n_g, w0, row0, col0, part);
+  else
+    chi0_tile_n<WPW, SUB, CHUNK, DEPTH>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi,
+                                        omega, n_w, eta, n_g, w0, row0, col0, part);
+}
+
 // One tile per workgroup; logical tile = (frequency block fastest, then
-// (G block, G' block), then slice).  OCC = workgroups per CU (2 for every
-// listed shape: one wave per SIMD leaves LDS and dependency latency exposed,
-// measured at about 60 % of the two-wave rate for 16 x 128 and 16 x 144
-// tiles that fill the 512-entry register file).
-template <int WPW, int SUB, int CHUNK, int OCC>
+// (G block, G' block), then slice).  OCC = workgroups per CU: 2 for the
+// plain tile (one wave per SIMD without pipelining leaves LDS and dependency
+// latency exposed: about 60 % of the two-wave rate for 16 x 128 and 16 x 144
+// tiles), 1 for the pipelined tile, whose two operand register sets need the
+// 512 registers of a lone wave.
+template <int WPW, int SUB, int CHUNK, int OCC, bool PIPE, int DEPTH>
 __global__ void __launch_bounds__(256, OCC)
     k_chi0_bf16x3(const void *P, const void *R, int ld, const double *delta, const double *df,
                   long long n_trans, long long slice_len, const double *omega, int n_w,
@@ -390,9 +723,9 @@ __global__ void __launch_bounds__(256, OCC)
   const long long t_lo = (long long)bz * slice_len;
   const long long t_hi = std::min(n_trans, t_lo + slice_len);
   const int col0 = gc * C::kCols;
-  chi0_tile_n<WPW, SUB, CHUNK>(std::min(SUB, (ld - col0) / 16), lds, P, R, ld, delta, df, n_trans,
-                               t_lo, t_hi, omega, n_w, eta, n_g, bx * C::kWBlock, gb * 16, col0,
-                               part + (size_t)bz * n_w * n_g * n_g);
+  run_tile<WPW, SUB, CHUNK, PIPE, DEPTH>(std::min(SUB, (ld - col0) / 16), lds, P, R, ld, delta, df,
+                                  n_trans, t_lo, t_hi, omega, n_w, eta, n_g, bx * C::kWBlock,
+                                  gb * 16, col0, part + (size_t)bz * n_w * n_g * n_g);
 }
 
 // Persistent form: a fixed grid (OCC workgroups per CU) walks the
@@ -400,7 +733,7 @@ __global__ void __launch_bounds__(256, OCC)
 // round), so every workgroup runs a similar amount of work and leaves when it
 // passes the end.  No LDS beyond the tile's double buffer (two workgroups still fit per
 // CU) and no atomics; the assignment is deterministic.
-template <int WPW, int SUB, int CHUNK, int OCC>
+template <int WPW, int SUB, int CHUNK, int OCC, bool PIPE, int DEPTH>
 __global__ void __launch_bounds__(256, OCC)
     k_chi0_bf16x3_persistent(const BatchItem *items, const BatchTile *tiles, int n_tiles) {
   typedef Cfg<WPW, SUB, CHUNK> C;
@@ -415,12 +748,20 @@ __global__ void __launch_bounds__(256, OCC)
     const long long t_lo = tl.slice * it.slice_len;
     const long long t_hi = std::min(it.n_trans, t_lo + it.slice_len);
     const int col0 = tl.gc * C::kCols;
-    chi0_tile_n<WPW, SUB, CHUNK>(std::min(SUB, (it.ld - col0) / 16), lds, it.P, it.R, it.ld,
-                                 it.delta, it.df, it.n_trans, t_lo, t_hi, it.omega, it.n_w,
-                                 it.eta, it.n_g, tl.wblk * C::kWBlock, tl.gb * 16, col0,
-                                 it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
+    run_tile<WPW, SUB, CHUNK, PIPE, DEPTH>(std::min(SUB, (it.ld - col0) / 16), lds, it.P, it.R, it.ld,
+                                    it.delta, it.df, it.n_trans, t_lo, t_hi, it.omega, it.n_w,
+                                    it.eta, it.n_g, tl.wblk * C::kWBlock, tl.gb * 16, col0,
+                                    it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
     __syncthreads();  // the next tile's prologue rewrites the LDS buffers
   }
+}
+
+template <int W, int S, int K, bool PIPE, int DEPTH>
+constexpr size_t variant_lds() {
+  if constexpr (PIPE)
+    return PipeLds<W, S, K>::kBytes;
+  else
+    return (size_t)DEPTH * Cfg<W, S, K>::kBufWords * 4;
 }
 
 struct Variant {
@@ -430,13 +771,16 @@ struct Variant {
   const void *pers_fn;
 };
 
-#define TDX_V(W, S, K, O)                                                                \
+#define TDX_V(W, S, K, O, PIPE, DEPTH)                                                   \
   Variant {                                                                              \
-    W, S, K, O, Cfg<W, S, K>::kLds, (const void *)k_chi0_bf16x3<W, S, K, O>,             \
-        (const void *)k_chi0_bf16x3_persistent<W, S, K, O>                               \
+    W, S, K, O, variant_lds<W, S, K, PIPE, DEPTH>(),                                     \
+        (const void *)k_chi0_bf16x3<W, S, K, O, PIPE, DEPTH>,                            \
+        (const void *)k_chi0_bf16x3_persistent<W, S, K, O, PIPE, DEPTH>                  \
   }
-const Variant kVariants[] = {TDX_V(4, 4, 32, 2), TDX_V(2, 8, 16, 2), TDX_V(4, 2, 32, 2),
-                             TDX_V(2, 4, 32, 2), TDX_V(2, 9, 16, 2), TDX_V(2, 8, 32, 2)};
+const Variant kVariants[] = {TDX_V(4, 4, 32, 2, false, 2), TDX_V(2, 8, 16, 2, false, 2),
+                             TDX_V(4, 2, 32, 2, false, 2), TDX_V(2, 4, 32, 2, false, 2),
+                             TDX_V(2, 9, 16, 2, false, 2), TDX_V(2, 8, 32, 2, false, 2),
+                             TDX_V(2, 9, 32, 1, true, 0),  TDX_V(2, 9, 16, 2, false, 3)};
 #undef TDX_V
 
 }  // namespace
