@@ -38,7 +38,7 @@ def f_alg(n_w, n_g, n_t):
     return 8.0 * n_w * n_g * n_g * n_t
 
 
-def run_step(tdx, ctx, w, st, setup, prec, qs, torch, keep=False):
+def run_step(tdx, ctx, w, st, setup, prec, qs, torch, keep=False, paired=True):
     """One pass of the path over the q indices `qs`, one chi0 launch per q,
     chi0 bracketed by events (used for the comparison legs)."""
     stream = torch.cuda.current_stream()
@@ -49,7 +49,7 @@ def run_step(tdx, ctx, w, st, setup, prec, qs, torch, keep=False):
             tdx.occupations(ctx, st, T, w.n_electrons, w.f_trunc)
         gb, i_g0, om, tau = setup[iq]
         qj = tuple(w.qs[iq])
-        tr = tdx.transitions(ctx, st, qj, w.f_trans_thr)
+        tr = tdx.transitions(ctx, st, qj, w.f_trans_thr, paired=paired)
         P = tdx.pair_density(ctx, st, qj, tr, gb, prec)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -72,17 +72,18 @@ class BatchedStep:
     """The benchmark step: transitions and pair densities of every q into
     fixed buffers, chi0 for every q (one grid launch per q, or with
     persistent=True ONE persistent launch for all q from a plan built once),
-    then K, Dyson, S and F per q."""
+    then K, Dyson, S and F per q.  paired: time-reversal paired transition
+    lists (half the transitions contracted)."""
 
-    def __init__(self, tdx, ctx, w, st, setup, prec, torch, persistent=False):
+    def __init__(self, tdx, ctx, w, st, setup, prec, torch, persistent=False, paired=True):
         self.tdx, self.ctx, self.w, self.st, self.setup, self.prec = tdx, ctx, w, st, setup, prec
-        self.torch, self.persistent = torch, persistent
+        self.torch, self.persistent, self.paired = torch, persistent, paired
         self.tr, self.P, self.items = [], [], []
         pref = 2.0 / (st.n_k * st.omega_cell)
         for iq in range(len(w.qs)):
             self._occ(iq)
             gb, i_g0, om, tau = setup[iq]
-            tr = tdx.transitions(ctx, st, w.qs[iq], w.f_trans_thr)
+            tr = tdx.transitions(ctx, st, w.qs[iq], w.f_trans_thr, paired=paired)
             P = tdx.pair_density(ctx, st, w.qs[iq], tr, gb, prec)
             self.tr.append(tr)
             self.P.append(P)
@@ -100,7 +101,8 @@ class BatchedStep:
             self._occ(iq)
             gb = self.setup[iq][0]
             n0 = len(self.tr[iq])
-            tr = tdx.transitions(ctx, st, w.qs[iq], w.f_trans_thr, out=self.tr[iq])
+            tr = tdx.transitions(ctx, st, w.qs[iq], w.f_trans_thr, out=self.tr[iq],
+                                 paired=self.paired)
             assert tr is self.tr[iq] and len(tr) == n0
             tdx.pair_density(ctx, st, w.qs[iq], tr, gb, self.prec, out=self.P[iq])
         stream = torch.cuda.current_stream()
@@ -208,6 +210,9 @@ def main():
     ap.add_argument("--compare", default="fp64,fp32",
                     help="precisions timed on the first q for comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pairing", action="store_true",
+                    help="contract the full transition list instead of one transition per "
+                         "time-reversal pair")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the split-BF16 tile shape on q0 first and save the cache")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2510_01875_amd",
@@ -252,11 +257,12 @@ def main():
                       torch.as_tensor(w.omega_grid(iq), device="cuda"),
                       torch.as_tensor(w.tau_grid(iq), device="cuda")))
     qs = list(range(len(w.qs)))
+    paired = not args.no_pairing
     tuned = None
     if args.prec == "bf16x3":
         if args.autotune:
             b0 = setup[0][0]
-            tr0 = tdx.transitions(ctx, st, w.qs[0], w.f_trans_thr)
+            tr0 = tdx.transitions(ctx, st, w.qs[0], w.f_trans_thr, paired=paired)
             P0 = tdx.pair_density(ctx, st, w.qs[0], tr0, b0, "bf16x3")
             probe = tdx.Chi0Item(tr0, P0, b0.shape[0], setup[0][2], w.eta,
                                  2.0 / (st.n_k * st.omega_cell))
@@ -272,7 +278,7 @@ def main():
         v, sl = tdx.chi0_get_config(ctx, setup[0][0].shape[0])
         tuned = dict(tuned or {"source": "default"}, variant=v, slice_log2=sl)
 
-    step = BatchedStep(tdx, ctx, w, st, setup, args.prec, torch)
+    step = BatchedStep(tdx, ctx, w, st, setup, args.prec, torch, paired=paired)
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -308,7 +314,7 @@ def main():
     legs = {}
     for prec in [p for p in args.compare.split(",") if p and p != args.prec]:
         torch.cuda.synchronize()
-        r = run_step(tdx, ctx, w, st, setup, prec, [0], torch, keep=True)[0]
+        r = run_step(tdx, ctx, w, st, setup, prec, [0], torch, keep=True, paired=paired)[0]
         torch.cuda.synchronize()
         ms = r["ev"][0].elapsed_time(r["ev"][1])
         legs[prec] = {"chi0_tflops": f_alg(r["n_w"], r["n_g"], r["n_t"]) / (ms * 1e-3) / 1e12,
@@ -340,7 +346,10 @@ def main():
         "config": {"workload": w.name, "kgrid": list(w.kgrid), "n_bands": w.n_bands,
                    "n_q": len(w.qs), "n_omega": w.n_omega,
                    "n_g": [int(s_[0].shape[0]) for s_ in setup],
-                   "n_trans": [r["n_t"] for r in recs[: len(qs)]], "xc": w.xc,
+                   "n_trans": [r["n_t"] for r in recs[: len(qs)]],
+                   "transitions": ("one per time-reversal pair (n_trans contracted, about "
+                                   "half the screened set)" if paired else "full screened set"),
+                   "xc": w.xc,
                    "chi0_launch": "one grid launch per q", "tile": tuned},
         "s_eval_per_s": n_eval / t_total,
         "chi0_ms_per_step": launch_ms,

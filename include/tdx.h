@@ -181,12 +181,27 @@ int tdx_response_basis(const double cell[9], const int kgrid[3], const int qj[3]
  * capacity 0 to size the buffers.  A call whose pointers are all null is
  * such a count query and returns OK when the set is empty.  Otherwise
  * k_offsets must be given, and the five per-transition arrays too unless
- * the set is empty (INVALID_ARG).  Synchronises. */
+ * the set is empty (INVALID_ARG).  Synchronises.
+ *
+ * paired (input, 0 or 1): with 1 the list keeps one transition of each
+ * time-reversal pair.  For a real local potential without spin-orbit
+ * coupling on an inversion-symmetric k-grid, the transition
+ * (k, n -> k+q, m) and its partner (-k-q, m -> -k, n) have the same rho rho^H
+ * (summed over degenerate multiplets), opposite delta and opposite df, so
+ * the two Adler-Wiser terms combine into one with the weight
+ *   df [1/(w - delta + i eta) - 1/(w + delta + i eta)]
+ *     = 2 df delta / ((w + i eta)^2 - delta^2).
+ * The kept k are those whose partner index (-k-q on the grid) is larger;
+ * a k that is its own partner keeps n < m.  tdx_chi0 and the batch plans
+ * then apply the combined weight (chi0 equals that of the full list up to
+ * rounding); pair densities are computed for the kept transitions only.
+ * The reverse-mode entry points need the full list (INVALID_ARG). */
 typedef struct {
   int64_t capacity;
   int *k, *n, *m;
   double *delta, *df;
   int64_t *k_offsets;
+  int32_t paired;
 } tdx_translist;
 
 int tdx_transitions(tdx_ctx *ctx, const tdx_states *st, const int qj[3],

@@ -70,7 +70,7 @@ class StatesC(C.Structure):
 class TransC(C.Structure):
     _fields_ = [("capacity", C.c_int64), ("k", C.c_void_p), ("n", C.c_void_p),
                 ("m", C.c_void_p), ("delta", C.c_void_p), ("df", C.c_void_p),
-                ("k_offsets", C.c_void_p)]
+                ("k_offsets", C.c_void_p), ("paired", C.c_int32)]
 
 
 def _sig(name, args):
@@ -319,10 +319,11 @@ def response_basis(cell, kgrid, qj, ecut_chi):
 
 # ------------------------------------------------------------- transitions
 class Transitions:
-    def __init__(self, count, device):
+    def __init__(self, count, device, paired=False):
         dev = torch.device("cuda", device)
         cap = max(int(count), 1)
         self.count = int(count)
+        self.paired = bool(paired)
         self.k = torch.zeros(cap, dtype=torch.int32, device=dev)
         self.n = torch.zeros(cap, dtype=torch.int32, device=dev)
         self.m = torch.zeros(cap, dtype=torch.int32, device=dev)
@@ -333,6 +334,7 @@ class Transitions:
         c.capacity = self.count
         c.k, c.n, c.m = self.k.data_ptr(), self.n.data_ptr(), self.m.data_ptr()
         c.delta, c.df = self.delta.data_ptr(), self.df.data_ptr()
+        c.paired = int(self.paired)
         self.c = c
 
     def __len__(self):
@@ -340,19 +342,22 @@ class Transitions:
 
 
 def transitions(ctx: Context, st: States, qj, thr: float, stream=None,
-                out: Optional[Transitions] = None) -> Transitions:
-    """Screened transition list; `out` (same size) is refilled in place."""
+                out: Optional[Transitions] = None, paired: bool = False) -> Transitions:
+    """Screened transition list; `out` (same size and form) is refilled in
+    place.  paired=True keeps one transition of each time-reversal pair
+    (tdx.h); chi0 then applies the combined weight."""
     q = (C.c_int * 3)(*qj)
     probe = TransC()
     probe.capacity = 0
+    probe.paired = int(paired)
     cnt = C.c_int64()
     code = _trans(ctx.handle, C.byref(st.c), q, thr, C.byref(probe), C.byref(cnt), _stream(stream))
     if code not in (OK, ERR_SHAPE):
         check(code)
-    if out is not None and out.count == cnt.value:
+    if out is not None and out.count == cnt.value and out.paired == bool(paired):
         tr = out
     else:
-        tr = Transitions(cnt.value, ctx.device)
+        tr = Transitions(cnt.value, ctx.device, paired)
         tr.k_offsets = torch.zeros(st.n_k + 1, dtype=torch.int64, device=st.eps.device)
         tr.c.k_offsets = tr.k_offsets.data_ptr()
     check(_trans(ctx.handle, C.byref(st.c), q, thr, C.byref(tr.c), C.byref(cnt), _stream(stream)))
@@ -561,8 +566,9 @@ class QOut:
 
 
 def run_q(ctx: Context, w, st: States, iq: int, prec: str = "fp64", omega=None,
-          keep_chi0: bool = True, stream=None) -> QOut:
-    """transitions -> pair densities -> chi0 -> K -> Dyson -> S -> F for one q."""
+          keep_chi0: bool = True, stream=None, paired: bool = True) -> QOut:
+    """transitions -> pair densities -> chi0 -> K -> Dyson -> S -> F for one q
+    (over the time-reversal paired transition list unless paired=False)."""
     dev = st.eps.device
     qj = tuple(w.qs[iq])
     T = w.temperatures[iq]
@@ -570,7 +576,7 @@ def run_q(ctx: Context, w, st: States, iq: int, prec: str = "fp64", omega=None,
         occupations(ctx, st, T, w.n_electrons, w.f_trunc, stream)
     basis, i_g0 = response_basis(w.cell, w.kgrid, qj, w.ecut_chi[iq])
     gb = torch.from_numpy(basis).to(dev)
-    tr = transitions(ctx, st, qj, w.f_trans_thr, stream)
+    tr = transitions(ctx, st, qj, w.f_trans_thr, stream, paired=paired)
     P = pair_density(ctx, st, qj, tr, gb, prec, stream)
     om = torch.as_tensor(w.omega_grid(iq) if omega is None else np.asarray(omega, dtype=np.float64),
                          device=dev)

@@ -575,6 +575,8 @@ int tdx_chi0_vjp(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, const d
                  const double *v, double *w_bar, double *rho_bar, tdx_stream stream) {
   clear_error();
   TDX_REQUIRE(ctx && tl && P && omega && u && v && w_bar, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(!tl->paired, TDX_ERR_INVALID_ARG,
+              "reverse mode needs the full (unpaired) transition list");
   TDX_REQUIRE(n_g > 0 && n_w > 0 && n_trans >= 0 && n_trans <= tl->capacity, TDX_ERR_SHAPE,
               "bad sizes");
   TDX_REQUIRE(std::isfinite(eta) && std::isfinite(pref), TDX_ERR_INVALID_ARG, "bad eta or pref");
@@ -596,6 +598,8 @@ int tdx_weights_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const t
   clear_error();
   TDX_REQUIRE(ctx && st && qj && tl && w_bar && occ_bar && eps_bar && eta_bar,
               TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(!tl->paired, TDX_ERR_INVALID_ARG,
+              "reverse mode needs the full (unpaired) transition list");
   TDX_REQUIRE(n_trans >= 0 && n_trans <= tl->capacity, TDX_ERR_SHAPE, "bad sizes");
   TDX_TRY(check_device(ctx));
   if (n_trans == 0) return TDX_OK;
@@ -635,6 +639,8 @@ int tdx_pair_density_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
   clear_error();
   TDX_REQUIRE(ctx && st && qj && tl && gbasis && rho_bar && coef_bar, TDX_ERR_INVALID_ARG,
               "null argument");
+  TDX_REQUIRE(!tl->paired, TDX_ERR_INVALID_ARG,
+              "reverse mode needs the full (unpaired) transition list");
   TDX_REQUIRE(n_g > 0 && n_trans >= 0 && n_trans <= tl->capacity, TDX_ERR_SHAPE, "bad sizes");
   TDX_REQUIRE((size_t)st->nb_max * sizeof(long long) <= 64 * 1024, TDX_ERR_SHAPE,
               "band capacity %d too large for the adjoint kernel", st->nb_max);

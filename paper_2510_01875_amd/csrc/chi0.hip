@@ -1,4 +1,6 @@
 // chi0_GG'(q,w) = pref * sum_t df_t / (w - delta_t + i eta) rho_t(G) conj(rho_t(G'))
+// (for a time-reversal-paired list each kept t carries its partner too, with
+// the weight df_t [1/(w - delta_t + i eta) - 1/(w + delta_t + i eta)])
 //
 // A complex contraction over transitions t, run as a real GEMM on MFMA:
 // for every (w, G, G') with the left operand A = w_t(w) rho_t(G) formed in
@@ -50,9 +52,9 @@ struct Elem<TDX_PREC_FP32> {
 // Partial sums part[slice][w][G][G'] (complex FP64), unscaled.
 template <int PREC>
 __global__ void __launch_bounds__(256)
-    k_chi0_mfma(const void *P, int ld, const double *delta, const double *df, long long n_trans,
-                long long slice_len, const double *omega, int n_w, double eta, int n_g,
-                double2 *part) {
+    k_chi0_mfma(const void *P, int ld, const double *delta, const double *df, int paired,
+                long long n_trans, long long slice_len, const double *omega, int n_w, double eta,
+                int n_g, double2 *part) {
   __shared__ double2 rg[kTChunk][16];       // rho_t(G) of the row block
   __shared__ double2 rgp[kTChunk][16];      // rho_t(G') of the column block
   __shared__ double2 wt[kTChunk][kWBlock];  // weights
@@ -95,10 +97,18 @@ __global__ void __launch_bounds__(256)
       const long long t = tc + tl;
       double2 w = make_double2(0, 0);
       if (t < t_hi && w0 + wi < n_w) {
-        // df / (x + i eta) = df (x - i eta) / (x^2 + eta^2), x = w - delta
-        const double x = omega[w0 + wi] - delta[t];
-        const double s = df[t] / fma(x, x, eta * eta);
-        w = make_double2(s * x, -s * eta);
+        const double om = omega[w0 + wi], d = delta[t];
+        if (paired) {
+          // 2 df delta / D, D = (w + i eta)^2 - delta^2 = (w - delta)(w + delta) - eta^2 + 2 i w eta
+          const double dr = (om - d) * (om + d) - eta * eta, di = 2.0 * om * eta;
+          const double s = 2.0 * df[t] * d / fma(dr, dr, di * di);
+          w = make_double2(s * dr, -s * di);
+        } else {
+          // df / (x + i eta) = df (x - i eta) / (x^2 + eta^2), x = w - delta
+          const double x = om - d;
+          const double s = df[t] / fma(x, x, eta * eta);
+          w = make_double2(s * x, -s * eta);
+        }
       }
       wt[tl][wi] = w;
     }
@@ -185,7 +195,7 @@ __global__ void k_reduce_slices(const double2 *part, int n_slices, size_t per_sl
 
 // Split-BF16 path (chi0_bf16x3.hip).
 int chi0_bf16x3(tdx_ctx *ctx, const void *P, int ld, const double *delta, const double *df,
-                long long n_trans, const double *omega, int n_w, double eta, int n_g,
+                int paired, long long n_trans, const double *omega, int n_w, double eta, int n_g,
                 double pref, double2 *chi0, hipStream_t s);
 
 }  // namespace tdx
@@ -216,7 +226,8 @@ extern "C" int tdx_chi0(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, 
     return TDX_OK;
   }
   if (prec == TDX_PREC_BF16X3)
-    return chi0_bf16x3(ctx, P, ld, tl->delta, tl->df, n_trans, omega, n_w, eta, n_g, pref,
+    return chi0_bf16x3(ctx, P, ld, tl->delta, tl->df, tl->paired, n_trans, omega, n_w, eta, n_g,
+                       pref,
                        (double2 *)chi0, s);
   const int nblk = ld / 16;
   const long long base = (long long)((n_w + kWBlock - 1) / kWBlock) * nblk * nblk;
@@ -233,10 +244,12 @@ extern "C" int tdx_chi0(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, 
   dim3 grid((n_w + kWBlock - 1) / kWBlock, nblk * nblk, (unsigned)slices);
   if (prec == TDX_PREC_FP64)
     hipLaunchKernelGGL(k_chi0_mfma<TDX_PREC_FP64>, grid, dim3(256), 0, s, P, ld, tl->delta,
-                       tl->df, (long long)n_trans, slice_len, omega, n_w, eta, n_g, part);
+                       tl->df, (int)tl->paired, (long long)n_trans, slice_len, omega, n_w, eta,
+                       n_g, part);
   else
     hipLaunchKernelGGL(k_chi0_mfma<TDX_PREC_FP32>, grid, dim3(256), 0, s, P, ld, tl->delta,
-                       tl->df, (long long)n_trans, slice_len, omega, n_w, eta, n_g, part);
+                       tl->df, (int)tl->paired, (long long)n_trans, slice_len, omega, n_w, eta,
+                       n_g, part);
   TDX_HIP(hipGetLastError());
   const unsigned rb = (unsigned)std::min<size_t>((out_elems + 255) / 256, 8192);
   hipLaunchKernelGGL(k_reduce_slices, dim3(rb), dim3(256), 0, s, part, (int)slices, out_elems,

@@ -15,6 +15,7 @@ struct BatchItem {
   const double *omega;
   int n_w;
   double eta;
+  int paired;  // time-reversal paired transition list
   int n_g;
   double2 *part;  // [slices][n_w][n_g][n_g]
 };
@@ -38,7 +39,7 @@ inline const void *bf16x3_rho(const void *P, long long p_rows, int ld) {
 int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double *delta,
                        const double *df,
                        long long n_trans, long long slice_len, int slices, const double *omega,
-                       int n_w, double eta, int n_g, double2 *part, hipStream_t s);
+                       int n_w, double eta, int paired, int n_g, double2 *part, hipStream_t s);
 int bf16x3_launch_persistent(int v, const BatchItem *items, const BatchTile *tiles, int n_tiles,
                              int n_blocks, hipStream_t s);
 

@@ -85,9 +85,9 @@ long long tiles_per_slice(int v, int n_w, int ld) {
 }  // namespace
 
 int chi0_bf16x3_with(tdx_ctx *ctx, int v, int slice_log2, const void *P, long long p_rows,
-                     int ld, const double *delta, const double *df, long long n_trans,
-                     const double *omega, int n_w, double eta, int n_g, double pref,
-                     double2 *chi0, hipStream_t s) {
+                     int ld, const double *delta, const double *df, int paired,
+                     long long n_trans, const double *omega, int n_w, double eta, int n_g,
+                     double pref, double2 *chi0, hipStream_t s) {
   long long slice_len;
   int slices;
   slicing(n_trans, slice_log2, tiles_per_slice(v, n_w, ld), &slice_len, &slices);
@@ -96,7 +96,7 @@ int chi0_bf16x3_with(tdx_ctx *ctx, int v, int slice_log2, const void *P, long lo
   TDX_TRY(ws_get(ctx, WS_PARTIAL, sizeof(double2) * out_elems * slices, &w));
   double2 *part = (double2 *)w;
   TDX_TRY(bf16x3_launch_grid(v, P, bf16x3_rho(P, p_rows, ld), ld, delta, df, n_trans, slice_len,
-                             slices, omega, n_w, eta, n_g, part, s));
+                             slices, omega, n_w, eta, paired, n_g, part, s));
   const unsigned rb = (unsigned)std::min<size_t>((out_elems + 255) / 256, 8192);
   hipLaunchKernelGGL(k_reduce_slices, dim3(rb), dim3(256), 0, s, part, slices, out_elems, pref,
                      chi0);
@@ -105,12 +105,12 @@ int chi0_bf16x3_with(tdx_ctx *ctx, int v, int slice_log2, const void *P, long lo
 }
 
 int chi0_bf16x3(tdx_ctx *ctx, const void *P, int ld, const double *delta, const double *df,
-                long long n_trans, const double *omega, int n_w, double eta, int n_g,
+                int paired, long long n_trans, const double *omega, int n_w, double eta, int n_g,
                 double pref, double2 *chi0, hipStream_t s) {
   int v, sl;
   pick(ctx, ld, &v, &sl);
-  return chi0_bf16x3_with(ctx, v, sl, P, n_trans, ld, delta, df, n_trans, omega, n_w, eta, n_g,
-                          pref, chi0, s);
+  return chi0_bf16x3_with(ctx, v, sl, P, n_trans, ld, delta, df, paired, n_trans, omega, n_w,
+                          eta, n_g, pref, chi0, s);
 }
 
 }  // namespace tdx
@@ -212,8 +212,10 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
     part_off[i] = part_bytes;
     part_bytes += per * slices * sizeof(double2);
     p->max_per_slice = std::max(p->max_per_slice, per);
-    bi[i] = BatchItem{it.P, bf16x3_rho(it.P, it.n_trans, ld), ld, it.tl->delta, it.tl->df, (long long)it.n_trans, slice_len,
-                      it.omega, it.n_w, it.eta, it.n_g, nullptr};
+    bi[i] = BatchItem{it.P,        bf16x3_rho(it.P, it.n_trans, ld), ld, it.tl->delta,
+                      it.tl->df,   (long long)it.n_trans, slice_len, it.omega,
+                      it.n_w,      it.eta,      (int)it.tl->paired,   it.n_g,
+                      nullptr};
     ri[i] = ReduceItem{nullptr, slices, per, it.pref, (double2 *)it.chi0};
     const int nwb = (it.n_w + wb - 1) / wb, ngb = ld / 16, ncb = (ld + cols - 1) / cols;
     // frequency block fastest: consecutive tiles read the same rho rows
@@ -335,7 +337,7 @@ int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_
       for (int rep = 0; rep < 3 && rc == TDX_OK; ++rep) {
         hipEventRecord(e0, s);
         rc = chi0_bf16x3_with(ctx, v, sl, probe->P, probe->n_trans, ld, probe->tl->delta,
-                              probe->tl->df, nt,
+                              probe->tl->df, (int)probe->tl->paired, nt,
                               probe->omega, probe->n_w, probe->eta, probe->n_g, probe->pref,
                               (double2 *)probe->chi0, s);
         hipEventRecord(e1, s);

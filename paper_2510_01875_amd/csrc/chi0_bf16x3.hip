@@ -195,19 +195,33 @@ __device__ inline void load_weights(Weights<C> &pw, const double *delta, const d
 
 // ... and into LDS: w - delta in FP64 (it may cancel), the rest in FP32
 // (relative error ~1e-7, far below the 2^-16 of the split products); zero
-// past the end of the slice or of the frequency grid.
+// past the end of the slice or of the frequency grid.  For a time-reversal
+// paired list the weight is 2 df delta / D with
+// D = (w + i eta)^2 - delta^2 = (w - delta)(w + delta) - eta^2 + 2 i w eta,
+// whose real part is formed in FP64 for the same reason.
 template <class C>
 __device__ inline void store_weights(const Weights<C> &pw, float2 *wt, double om, bool w_ok,
-                                     float eta, int tid, long long tc, long long t_hi) {
+                                     double eta, int paired, int tid, long long tc,
+                                     long long t_hi) {
   const int tw = tid / C::kWBlock, wi = tid % C::kWBlock;
+  const float etaf = (float)eta;
 #pragma unroll
   for (int i = 0; i < C::kNW; ++i) {
     const int tl = tw + (256 / C::kWBlock) * i;
     if (C::kWPart && tl >= C::kChunk) break;
     const bool ok = tc + tl < t_hi && w_ok;
-    const float x = (float)(om - pw.d[i]);
-    const float sc = (float)pw.f[i] * __builtin_amdgcn_rcpf(fmaf(x, x, eta * eta));
-    wt[wt_index<C>(tl, wi)] = ok ? make_float2(sc * x, -sc * eta) : make_float2(0.f, 0.f);
+    float2 v;
+    if (paired) {
+      const float dr = (float)((om - pw.d[i]) * (om + pw.d[i]) - eta * eta);
+      const float di = (float)(2.0 * om * eta);
+      const float sc = (float)(2.0 * pw.f[i] * pw.d[i]) * __builtin_amdgcn_rcpf(fmaf(dr, dr, di * di));
+      v = make_float2(sc * dr, -sc * di);
+    } else {
+      const float x = (float)(om - pw.d[i]);
+      const float sc = (float)pw.f[i] * __builtin_amdgcn_rcpf(fmaf(x, x, etaf * etaf));
+      v = make_float2(sc * x, -sc * etaf);
+    }
+    wt[wt_index<C>(tl, wi)] = ok ? v : make_float2(0.f, 0.f);
   }
 }
 
@@ -253,7 +267,7 @@ template <int WPW, int SUB, int CHUNK, int NSUB, int DEPTH>
 __device__ __attribute__((always_inline)) void chi0_tile(
     unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
-    int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
+    int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
   typedef Cfg<WPW, SUB, CHUNK> C;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -276,14 +290,13 @@ __device__ __attribute__((always_inline)) void chi0_tile(
   const int wi = w0 + tid % C::kWBlock;
   const bool w_ok = wi < n_w;
   const double om = omega[std::min(wi, n_w - 1)];
-  const float etaf = (float)eta;
 #pragma unroll
   for (int k = 0; k < DEPTH - 1; ++k) {
     if (t_lo + k * CHUNK >= t_hi) break;
     dma.issue((size_t)k * chunk_bytes, lds + k * C::kBufWords);
     load_weights<C>(pw, delta, df, t_lo + k * CHUNK, t_max, tid);
     store_weights<C>(pw, (float2 *)(lds + k * C::kBufWords + C::kBWords + C::kRhoWords), om, w_ok,
-                     etaf, tid, t_lo + k * CHUNK, t_hi);
+                     eta, paired, tid, t_lo + k * CHUNK, t_hi);
   }
   wait_vm();
   __syncthreads();
@@ -360,7 +373,7 @@ __device__ __attribute__((always_inline)) void chi0_tile(
       }
       if (more)
         store_weights<C>(pw, (float2 *)(lds + ahead * C::kBufWords + C::kBWords + C::kRhoWords),
-                         om, w_ok, etaf, tid, nx, t_hi);
+                         om, w_ok, eta, paired, tid, nx, t_hi);
       if (DEPTH > 2 && more)
         wait_vm_n<DmaPlan<C, NSUB>::kIssued>();
       else
@@ -381,17 +394,17 @@ template <int WPW, int SUB, int CHUNK, int DEPTH, int NSUB = SUB>
 __device__ __attribute__((always_inline)) void chi0_tile_n(
     int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
-    int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
+    int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
   if constexpr (NSUB > 1) {
     if (nsub < NSUB) {
       chi0_tile_n<WPW, SUB, CHUNK, DEPTH, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo,
-                                                     t_hi, omega, n_w, eta, n_g, w0, row0, col0,
+                                                     t_hi, omega, n_w, eta, paired, n_g, w0, row0, col0,
                                                      part);
       return;
     }
   }
   chi0_tile<WPW, SUB, CHUNK, NSUB, DEPTH>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
-                                          n_w, eta, n_g, w0, row0, col0, part);
+                                          n_w, eta, paired, n_g, w0, row0, col0, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -567,7 +580,7 @@ template <int WPW, int SUB, int CHUNK, int NSUB>
 __device__ __attribute__((always_inline)) void chi0_tile_pipe(
     unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
-    int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
+    int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
   typedef Cfg<WPW, SUB, CHUNK> C;
   typedef PipeLds<WPW, SUB, CHUNK> L;
   static_assert(C::kSteps % 2 == 0, "the A register sets alternate per K-step");
@@ -595,7 +608,6 @@ __device__ __attribute__((always_inline)) void chi0_tile_pipe(
   const int wi = w0 + tid % C::kWBlock;
   const bool w_ok = wi < n_w;
   const double om = omega[std::min(wi, n_w - 1)];
-  const float etaf = (float)eta;
   // buffers and slots by index (chunk k uses B buffer k % 3, slot k % 4)
   auto bbuf = [&](int i) { return bring + i * C::kBWords; };
   auto rbuf = [&](int i) { return rwring + i * L::kRW; };
@@ -607,7 +619,7 @@ __device__ __attribute__((always_inline)) void chi0_tile_pipe(
     if (k < 2) dma.issue_b((size_t)k * chunk_bytes, bbuf(k));
     dma.issue_r((size_t)k * chunk_bytes, rbuf(k));
     load_weights<C>(pw, delta, df, t_lo + k * CHUNK, t_max, tid);
-    store_weights<C>(pw, wt_of(k), om, w_ok, etaf, tid, t_lo + k * CHUNK, t_hi);
+    store_weights<C>(pw, wt_of(k), om, w_ok, eta, paired, tid, t_lo + k * CHUNK, t_hi);
   }
   wait_vm();
   __syncthreads();
@@ -642,7 +654,7 @@ __device__ __attribute__((always_inline)) void chi0_tile_pipe(
                                   wave);
       }
       if (more3)
-        store_weights<C>(pw, wt_of(r3), om, w_ok, etaf, tid, t_lo + (c + 3) * CHUNK, t_hi);
+        store_weights<C>(pw, wt_of(r3), om, w_ok, eta, paired, tid, t_lo + (c + 3) * CHUNK, t_hi);
       // this iteration's transfers may stay in flight; older ones are done
       if (more2 && more3)
         wait_vm_n<D::kIssuedB + D::kIssuedR>();
@@ -664,17 +676,17 @@ template <int WPW, int SUB, int CHUNK, int NSUB = SUB>
 __device__ __attribute__((always_inline)) void chi0_tile_pipe_n(
     int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
-    int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
+    int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
   if constexpr (NSUB > 1) {
     if (nsub < NSUB) {
       chi0_tile_pipe_n<WPW, SUB, CHUNK, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo,
-                                                   t_hi, omega, n_w, eta, n_g, w0, row0, col0,
+                                                   t_hi, omega, n_w, eta, paired, n_g, w0, row0, col0,
                                                    part);
       return;
     }
   }
   chi0_tile_pipe<WPW, SUB, CHUNK, NSUB>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
-                                        n_w, eta, n_g, w0, row0, col0, part);
+                                        n_w, eta, paired, n_g, w0, row0, col0, part);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (id % 8), each with
@@ -693,13 +705,13 @@ template <int WPW, int SUB, int CHUNK, bool PIPE, int DEPTH>
 __device__ __attribute__((always_inline)) void run_tile(
     int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
-    int n_w, double eta, int n_g, int w0, int row0, int col0, double2 *part) {
+    int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
   if constexpr (PIPE)
     chi0_tile_pipe_n<WPW, SUB, CHUNK>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
-                                      n_w, eta, n_g, w0, row0, col0, part);
+                                      n_w, eta, paired, n_g, w0, row0, col0, part);
   else
     chi0_tile_n<WPW, SUB, CHUNK, DEPTH>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi,
-                                        omega, n_w, eta, n_g, w0, row0, col0, part);
+                                        omega, n_w, eta, paired, n_g, w0, row0, col0, part);
 }
 
 // One tile per workgroup; logical tile = (frequency block fastest, then
@@ -712,7 +724,7 @@ template <int WPW, int SUB, int CHUNK, int OCC, bool PIPE, int DEPTH>
 __global__ void __launch_bounds__(256, OCC)
     k_chi0_bf16x3(const void *P, const void *R, int ld, const double *delta, const double *df,
                   long long n_trans, long long slice_len, const double *omega, int n_w,
-                  double eta, int n_g, int ncb, double2 *part) {
+                  double eta, int paired, int n_g, int ncb, double2 *part) {
   typedef Cfg<WPW, SUB, CHUNK> C;
   extern __shared__ unsigned int lds[];
   const int nx = gridDim.x, ny = gridDim.y;
@@ -724,7 +736,7 @@ __global__ void __launch_bounds__(256, OCC)
   const long long t_hi = std::min(n_trans, t_lo + slice_len);
   const int col0 = gc * C::kCols;
   run_tile<WPW, SUB, CHUNK, PIPE, DEPTH>(std::min(SUB, (ld - col0) / 16), lds, P, R, ld, delta, df,
-                                  n_trans, t_lo, t_hi, omega, n_w, eta, n_g, bx * C::kWBlock,
+                                  n_trans, t_lo, t_hi, omega, n_w, eta, paired, n_g, bx * C::kWBlock,
                                   gb * 16, col0, part + (size_t)bz * n_w * n_g * n_g);
 }
 
@@ -750,7 +762,7 @@ __global__ void __launch_bounds__(256, OCC)
     const int col0 = tl.gc * C::kCols;
     run_tile<WPW, SUB, CHUNK, PIPE, DEPTH>(std::min(SUB, (it.ld - col0) / 16), lds, it.P, it.R, it.ld,
                                     it.delta, it.df, it.n_trans, t_lo, t_hi, it.omega, it.n_w,
-                                    it.eta, it.n_g, tl.wblk * C::kWBlock, tl.gb * 16, col0,
+                                    it.eta, it.paired, it.n_g, tl.wblk * C::kWBlock, tl.gb * 16, col0,
                                     it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
     __syncthreads();  // the next tile's prologue rewrites the LDS buffers
   }
@@ -797,7 +809,7 @@ int bf16x3_variant_occupancy(int v) { return kVariants[v].occ; }
 int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double *delta,
                        const double *df,
                        long long n_trans, long long slice_len, int slices, const double *omega,
-                       int n_w, double eta, int n_g, double2 *part, hipStream_t s) {
+                       int n_w, double eta, int paired, int n_g, double2 *part, hipStream_t s) {
   const Variant &V = kVariants[v];
   const int nblk = ld / 16;
   int ncb = (ld + 16 * V.sub - 1) / (16 * V.sub);
@@ -806,7 +818,8 @@ int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double
   void *args[] = {(void *)&P,       (void *)&R,         (void *)&ld,
                   (void *)&delta,   (void *)&df,
                   (void *)&n_trans, (void *)&slice_len, (void *)&omega, (void *)&n_w,
-                  (void *)&eta,     (void *)&n_g,       (void *)&ncb,   (void *)&part};
+                  (void *)&eta,     (void *)&paired,    (void *)&n_g,   (void *)&ncb,
+                  (void *)&part};
   TDX_HIP(hipLaunchKernel(V.grid_fn, grid, dim3(256), args, V.lds, s));
   return TDX_OK;
 }

@@ -12,6 +12,7 @@ import sys
 import numpy as np
 import pytest
 
+import pairing_rule
 import workloads
 
 pytestmark = pytest.mark.gpu
@@ -102,17 +103,49 @@ def test_transitions_match_oracle_exactly(tdx, ctx, name):
         assert off[-1] == n and np.all(np.diff(off) >= 0)
 
 
-@pytest.mark.parametrize("name,prec", [("feg_tiny", "fp64"), ("fcc_small", "fp64"),
-                                       ("h_tiny", "fp64"), ("fcc_small", "fp32"),
-                                       ("fcc_small", "bf16x3"), ("h_tiny", "fp32"),
-                                       ("h_tiny", "bf16x3")])
-def test_pipeline_matches_oracle(tdx, ctx, name, prec):
-    _say("pipeline", name, prec)
+@pytest.mark.parametrize("name", ["feg_tiny", "fcc_small", "h_tiny"])
+def test_paired_transitions_are_the_oracle_list_filtered(tdx, ctx, name):
+    """The paired list is the oracle's full list restricted by the pairing
+    rule, in the same order, bit for bit in the integers."""
+    _say("paired transitions", name)
+    w, ost, ores = oracle_run(name)
+    st = tdx.build_states(ctx, w, w.temperatures[0])
+    for iq, r in enumerate(ores):
+        if w.temperatures[iq] != st.temperature:
+            tdx.occupations(ctx, st, w.temperatures[iq], w.n_electrons, w.f_trunc)
+        tr = tdx.transitions(ctx, st, w.qs[iq], w.f_trans_thr, paired=True)
+        kt = pairing_rule.partner(w.kgrid, w.qs[iq])
+        sel = pairing_rule.keep(r.tr.k, r.tr.n, r.tr.m, kt)
+        n = len(tr)
+        _say(f"  q{iq}: {len(r.tr)} -> {n}")
+        assert n == int(sel.sum())
+        assert np.array_equal(tr.k[:n].cpu().numpy(), r.tr.k[sel])
+        assert np.array_equal(tr.n[:n].cpu().numpy(), r.tr.n[sel])
+        assert np.array_equal(tr.m[:n].cpu().numpy(), r.tr.m[sel])
+        assert np.max(np.abs(tr.delta[:n].cpu().numpy() - r.tr.delta[sel]), initial=0) < 1e-11
+        assert np.max(np.abs(tr.df[:n].cpu().numpy() - r.tr.df[sel]), initial=0) < 1e-12
+        off = tr.k_offsets.cpu().numpy()
+        assert off[-1] == n and np.all(np.diff(off) >= 0)
+
+
+@pytest.mark.parametrize("name,prec,paired", [("feg_tiny", "fp64", True),
+                                              ("fcc_small", "fp64", True),
+                                              ("h_tiny", "fp64", True),
+                                              ("fcc_small", "fp64", False),
+                                              ("fcc_small", "fp32", True),
+                                              ("fcc_small", "bf16x3", True),
+                                              ("fcc_small", "bf16x3", False),
+                                              ("h_tiny", "fp32", True),
+                                              ("h_tiny", "bf16x3", True)])
+def test_pipeline_matches_oracle(tdx, ctx, name, prec, paired):
+    """The oracle sums over the full screened set; the paired path contracts
+    one transition per time-reversal pair with the combined weight."""
+    _say("pipeline", name, prec, "paired" if paired else "full")
     w, ost, ores = oracle_run(name)
     st = tdx.build_states(ctx, w, w.temperatures[0])
     tol = TOL[prec]
     for iq, r in enumerate(ores):
-        g = tdx.run_q(ctx, w, st, iq, prec=prec)
+        g = tdx.run_q(ctx, w, st, iq, prec=prec, paired=paired)
         p = _perm(g.basis, r.basis)
         ref = r.chi0[:, p][:, :, p]
         c0 = g.chi0.cpu().numpy()
@@ -125,7 +158,11 @@ def test_pipeline_matches_oracle(tdx, ctx, name, prec):
         _say(f"  q{iq} T={g.n_trans} NG={len(g.basis)} chi0 {err_c0:.2e} K {err_k:.2e} "
              f"S {norm:.2e}/{point:.2e} F {ferr:.2e}")
         assert err_k < 1e-12
-        assert g.n_trans == len(r.tr)
+        if paired:
+            kt = pairing_rule.partner(w.kgrid, w.qs[iq])
+            assert g.n_trans == int(pairing_rule.keep(r.tr.k, r.tr.n, r.tr.m, kt).sum())
+        else:
+            assert g.n_trans == len(r.tr)
         if prec == "fp64":
             assert err_c0 < 1e-12
         assert norm < tol and point < tol * 10
