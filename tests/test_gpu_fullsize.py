@@ -1,0 +1,157 @@
+"""The benchmark workload (fcc_c2, q0) at full size, in the launch
+configuration bench.py times (time-reversal paired lists, the tuned split-BF16
+tile): sampled outputs the oracle can compute one at a time, and properties
+that hold at any size.
+
+- eigenvalues at sampled k-points against the oracle's dense eigensolve;
+- pair densities of sampled transitions (non-degenerate bands, so each row is
+  unique up to one phase) against the oracle's direct sum, phase-aligned;
+- chi0 on every 20th frequency: paired FP64 against the full-list FP64 sum
+  (the pairing identity, 1e-12), split-BF16 against FP64 (1e-4), and the
+  anti-Hermitian part of chi0(w > 0) negative semidefinite;
+- S(q, w) through Dyson: split-BF16 against FP64 (1e-4).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tdx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_01875_amd as m
+    return m
+
+
+def _oracle_states_at(w, ks):
+    """oracle States with orbitals only at the k indices ks"""
+    from oracle.lattice import gsphere, mp_kpoints, reciprocal, volume
+    from oracle.states import States, hamiltonian, snap_band_count
+    cell = np.asarray(w.cell, dtype=np.float64)
+    B = reciprocal(cell)
+    omega = volume(cell)
+    kred, _ = mp_kpoints(w.kgrid)
+    n_k = len(kred)
+    millers, eps, coef = [None] * n_k, [None] * n_k, [None] * n_k
+    for k in ks:
+        m = gsphere(B, kred[k], w.ecut_wf)
+        e, V = np.linalg.eigh(hamiltonian(kred[k], m, B, w.potential, omega))
+        nb = snap_band_count(e, w.n_bands)
+        millers[k], eps[k], coef[k] = m, e[:nb].copy(), np.ascontiguousarray(V[:, :nb].T)
+    return States(cell, B, omega, tuple(w.kgrid), kred, millers, eps, coef, [None] * n_k, 0.0,
+                  w.temperatures[0], w.n_electrons)
+
+
+def _isolated(e, i, gap=1e-5):
+    lo = e[i] - e[i - 1] if i > 0 else np.inf
+    hi = e[i + 1] - e[i] if i + 1 < len(e) else np.inf
+    return min(lo, hi) > gap
+
+
+def test_fcc_c2_q0_full_size(tdx):
+    import torch
+    from oracle.lattice import kq_map, response_basis as o_basis
+    from oracle.response import Transitions, pair_densities
+
+    w = workloads.fcc_c2()
+    ctx = tdx.Context(0)
+    cache = os.path.join(ROOT, "paper_2510_01875_amd", "tune_gfx950.json")
+    if os.path.exists(cache):
+        tdx.tune_load(ctx, cache)
+    _say("fcc_c2 full size: states")
+    st = tdx.build_states(ctx, w, w.temperatures[0])
+    qj = tuple(w.qs[0])
+    basis, i_g0 = tdx.response_basis(w.cell, w.kgrid, qj, w.ecut_chi[0])
+    n_g = len(basis)
+    gb = torch.from_numpy(basis).cuda()
+    om_all = w.omega_grid(0)
+    om = torch.as_tensor(om_all[::20], device="cuda")
+    pref = 2.0 / (st.n_k * st.omega_cell)
+
+    # --- sampled states and pair densities against the oracle
+    kp, _ = kq_map(w.kgrid, qj)
+    tr = tdx.transitions(ctx, st, qj, w.f_trans_thr, paired=True)
+    off = tr.k_offsets.cpu().numpy()
+    ks = [k for k in (0, 1000, 2345) if off[k + 1] > off[k]]
+    assert ks, "no kept transitions at the sampled k-points"
+    ost = _oracle_states_at(w, sorted(set(ks) | {int(kp[k]) for k in ks}))
+    eps = st.eps.cpu().numpy()
+    nb = st.nb.cpu().numpy()
+    for k in ks:
+        assert nb[k] == len(ost.eps[k])
+        assert np.max(np.abs(eps[k, : nb[k]] - ost.eps[k])) < 1e-10
+    P64 = tdx.pair_density(ctx, st, qj, tr, gb, "fp64")
+    view = tdx.pair_density_view(P64, len(tr), n_g, "fp64")
+    tk, tn, tm = (x.cpu().numpy() for x in (tr.k, tr.n, tr.m))
+    rows = []
+    rng = np.random.default_rng(7)
+    for k in ks:
+        cand = [t for t in range(off[k], off[k + 1])
+                if _isolated(ost.eps[k], tn[t]) and _isolated(ost.eps[kp[k]], tm[t])]
+        rows += list(rng.choice(cand, size=min(8, len(cand)), replace=False))
+    rows = np.sort(np.array(rows))
+    qred = np.asarray(qj, dtype=np.float64) / np.asarray(w.kgrid)
+    obasis, _ = o_basis(ost.B, qred, w.ecut_chi[0])
+    pos = {tuple(x): i for i, x in enumerate(obasis)}
+    perm = np.array([pos[tuple(x)] for x in basis])
+    z = np.zeros(len(rows))
+    sub = Transitions(tk[rows].astype(np.int64), kp[tk[rows]].astype(np.int64),
+                      tn[rows].astype(np.int64), tm[rows].astype(np.int64), z, z)
+    ref = pair_densities(ost, sub, qj, obasis)[:, perm]
+    got = view[torch.as_tensor(rows, device="cuda")].cpu().numpy()
+    for a, b in zip(got, ref):
+        g = int(np.argmax(np.abs(b)))
+        phase = b[g] / a[g]
+        assert abs(abs(phase) - 1.0) < 1e-9
+        assert np.max(np.abs(a * phase - b)) < 1e-10 * np.max(np.abs(b))
+    _say(f"  states at {len(ks)} k and {len(rows)} pair-density rows match the oracle")
+
+    # --- chi0 in the bench configuration, and properties
+    c64 = tdx.chi0(ctx, tr, P64, n_g, "fp64", om, w.eta, pref)
+    del P64, view
+    trf = tdx.transitions(ctx, st, qj, w.f_trans_thr, paired=False)
+    Pf = tdx.pair_density(ctx, st, qj, trf, gb, "fp64")
+    cfull = tdx.chi0(ctx, trf, Pf, n_g, "fp64", om, w.eta, pref)
+    del Pf
+    scale = float(cfull.abs().max())
+    e_pair = float((c64 - cfull).abs().max()) / scale
+    P16 = tdx.pair_density(ctx, st, qj, tr, gb, "bf16x3")
+    c16 = tdx.chi0(ctx, tr, P16, n_g, "bf16x3", om, w.eta, pref)
+    del P16
+    e_16 = float((c16 - c64).abs().max()) / scale
+    _say(f"  T = {len(trf)} full, {len(tr)} paired; chi0 paired vs full {e_pair:.1e}, "
+         f"split-BF16 vs FP64 {e_16:.1e}")
+    assert e_pair < 1e-12
+    assert e_16 < 1e-4
+    c = c64.cpu().numpy()
+    worst = 0.0
+    for i in range(1, c.shape[0]):
+        a = (c[i] - c[i].conj().T) / 2j
+        worst = max(worst, float(np.linalg.eigvalsh(a).max()))
+    _say(f"  largest eigenvalue of the anti-Hermitian part: {worst:.1e} (scale {scale:.1e})")
+    assert worst < 1e-12 * scale
+
+    # --- S through Dyson, split-BF16 against FP64
+    K = tdx.kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid)
+    beta, n = 1.0 / w.temperatures[0], w.n_electrons / st.omega_cell
+    S64 = tdx.dsf(ctx, tdx.dyson(ctx, c64, K, i_g0), om, beta, n).cpu().numpy()
+    S16 = tdx.dsf(ctx, tdx.dyson(ctx, c16, K, i_g0), om, beta, n).cpu().numpy()
+    e_s = np.max(np.abs(S16 - S64)) / np.max(np.abs(S64))
+    _say(f"  S split-BF16 vs FP64 {e_s:.1e}")
+    assert e_s < 1e-4
+    ctx.close()
