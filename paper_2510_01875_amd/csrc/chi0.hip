@@ -9,6 +9,10 @@
 //   Im chi0 = sum_t [Re A, Im A] . [-Im rho', Re rho']
 // so that a K-step of 4 in the 16x16x4 MFMA covers two transitions.
 //
+// This file holds the FP64 form (16x16x4 FP64 MFMA) and the entry point;
+// the FP32 form is in chi0_f32.hip and the split-BF16 form in
+// chi0_bf16x3.hip.
+//
 // Work split: a workgroup owns a 16 (G) x 16 (G') block for 32 frequencies
 // (4 waves x 8) and one fixed slice of the transition list; per chunk of 32
 // transitions the rho rows of both blocks and the FP64 weights of the 32
@@ -25,34 +29,15 @@ namespace tdx {
 namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 4;
 constexpr int kWPerWave = 8;                 // frequencies per wave
 constexpr int kWBlock = kWaves * kWPerWave;  // frequencies per workgroup
 constexpr int kTChunk = 32;                  // transitions per LDS chunk
-constexpr int kF32Flush = 512;               // FP32 partials folded into FP64 every n transitions
-
-template <int PREC>
-struct Elem;
-template <>
-struct Elem<TDX_PREC_FP64> {
-  typedef double2 T;
-  __device__ static double2 ld(const void *P, size_t i) { return ((const double2 *)P)[i]; }
-};
-template <>
-struct Elem<TDX_PREC_FP32> {
-  typedef float2 T;
-  __device__ static double2 ld(const void *P, size_t i) {
-    const float2 v = ((const float2 *)P)[i];
-    return make_double2(v.x, v.y);
-  }
-};
 
 // Partial sums part[slice][w][G][G'] (complex FP64), unscaled.
-template <int PREC>
 __global__ void __launch_bounds__(256)
-    k_chi0_mfma(const void *P, int ld, const double *delta, const double *df, int paired,
+    k_chi0_f64(const double2 *P, int ld, const double *delta, const double *df, int paired,
                 long long n_trans, long long slice_len, const double *omega, int n_w, double eta,
                 int n_g, double2 *part) {
   __shared__ double2 rg[kTChunk][16];       // rho_t(G) of the row block
@@ -68,15 +53,11 @@ __global__ void __launch_bounds__(256)
   const int r = lane & 15, kk = lane >> 4, part_sel = kk & 1, tsub = kk >> 1;
 
   f64x4 accr[kWPerWave], acci[kWPerWave];
-  f32x4 fr[kWPerWave], fi[kWPerWave];
 #pragma unroll
   for (int i = 0; i < kWPerWave; ++i) {
     accr[i] = f64x4{0, 0, 0, 0};
     acci[i] = f64x4{0, 0, 0, 0};
-    fr[i] = f32x4{0, 0, 0, 0};
-    fi[i] = f32x4{0, 0, 0, 0};
   }
-  int since_flush = 0;
 
   for (long long tc = t_lo; tc < t_hi; tc += kTChunk) {
     __syncthreads();
@@ -86,8 +67,8 @@ __global__ void __launch_bounds__(256)
       const long long t = tc + tl;
       double2 a = make_double2(0, 0), b = make_double2(0, 0);
       if (t < t_hi) {
-        a = Elem<PREC>::ld(P, (size_t)t * ld + gb * 16 + c);
-        b = Elem<PREC>::ld(P, (size_t)t * ld + gbp * 16 + c);
+        a = P[(size_t)t * ld + gb * 16 + c];
+        b = P[(size_t)t * ld + gbp * 16 + c];
       }
       rg[tl][c] = a;
       rgp[tl][c] = b;
@@ -125,43 +106,13 @@ __global__ void __launch_bounds__(256)
       for (int i = 0; i < kWPerWave; ++i) {
         const double2 w = wt[tl][wave * kWPerWave + i];
         const double a = part_sel ? fma(w.x, ra.y, w.y * ra.x) : fma(w.x, ra.x, -w.y * ra.y);
-        if constexpr (PREC == TDX_PREC_FP64) {
-          accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, br, accr[i], 0, 0, 0);
-          acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bi, acci[i], 0, 0, 0);
-        } else {
-          fr[i] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)br, fr[i], 0, 0, 0);
-          fi[i] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)bi, fi[i], 0, 0, 0);
-        }
-      }
-    }
-    if constexpr (PREC == TDX_PREC_FP32) {
-      since_flush += kTChunk;
-      if (since_flush >= kF32Flush) {
-        since_flush = 0;
-#pragma unroll
-        for (int i = 0; i < kWPerWave; ++i) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            accr[i][j] += fr[i][j];
-            acci[i][j] += fi[i][j];
-          }
-          fr[i] = f32x4{0, 0, 0, 0};
-          fi[i] = f32x4{0, 0, 0, 0};
-        }
+        accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, br, accr[i], 0, 0, 0);
+        acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bi, acci[i], 0, 0, 0);
       }
     }
   }
-  if constexpr (PREC == TDX_PREC_FP32) {
-#pragma unroll
-    for (int i = 0; i < kWPerWave; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        accr[i][j] += fr[i][j];
-        acci[i][j] += fi[i][j];
-      }
-  }
-  // D[row][col], column lane%16; element j is row 4*(lane/16)+j for the
-  // f32 16x16x4 MFMA and row lane/16 + 4j for the f64 one
+  // D[row][col], column lane%16; element j is row lane/16 + 4j for the f64
+  // 16x16x4 MFMA
   const int col = gbp * 16 + (lane & 15);
 #pragma unroll
   for (int i = 0; i < kWPerWave; ++i) {
@@ -169,7 +120,7 @@ __global__ void __launch_bounds__(256)
     if (w >= n_w) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int row = gb * 16 + (PREC == TDX_PREC_FP64 ? (lane >> 4) + 4 * j : 4 * (lane >> 4) + j);
+      const int row = gb * 16 + (lane >> 4) + 4 * j;
       if (row < n_g && col < n_g)
         part[(((size_t)blockIdx.z * n_w + w) * n_g + row) * n_g + col] =
             make_double2(accr[i][j], acci[i][j]);
@@ -192,6 +143,12 @@ __global__ void k_reduce_slices(const double2 *part, int n_slices, size_t per_sl
 }
 
 }  // namespace
+
+// FP32 path (chi0_f32.hip).
+void chi0_f32_shape(int *wblock, int *cols, int *chunk);
+int chi0_f32_launch(const void *P, int ld, const double *delta, const double *df, int paired,
+                    long long n_trans, long long slice_len, int slices, const double *omega,
+                    int n_w, double eta, int n_g, double2 *part, hipStream_t s);
 
 // Split-BF16 path (chi0_bf16x3.hip).
 int chi0_bf16x3(tdx_ctx *ctx, const void *P, int ld, const double *delta, const double *df,
@@ -230,26 +187,29 @@ extern "C" int tdx_chi0(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, 
                        pref,
                        (double2 *)chi0, s);
   const int nblk = ld / 16;
-  const long long base = (long long)((n_w + kWBlock - 1) / kWBlock) * nblk * nblk;
+  int wblock = kWBlock, cols = 16, chunk = kTChunk;
+  if (prec == TDX_PREC_FP32) chi0_f32_shape(&wblock, &cols, &chunk);
+  const long long base =
+      (long long)((n_w + wblock - 1) / wblock) * nblk * ((ld + cols - 1) / cols);
   // enough slices to fill the chip; each slice a multiple of the chunk
   long long slices = std::max<long long>(1, (4096 + base - 1) / base);
-  slices = std::min<long long>(slices, (n_trans + kTChunk - 1) / kTChunk);
+  slices = std::min<long long>(slices, (n_trans + chunk - 1) / chunk);
   slices = std::min<long long>(slices, 512);
   long long slice_len = (n_trans + slices - 1) / slices;
-  slice_len = (slice_len + kTChunk - 1) / kTChunk * kTChunk;
+  slice_len = (slice_len + chunk - 1) / chunk * chunk;
   slices = (n_trans + slice_len - 1) / slice_len;
   void *w;
   TDX_TRY(ws_get(ctx, WS_PARTIAL, sizeof(double2) * out_elems * slices, &w));
   double2 *part = (double2 *)w;
-  dim3 grid((n_w + kWBlock - 1) / kWBlock, nblk * nblk, (unsigned)slices);
-  if (prec == TDX_PREC_FP64)
-    hipLaunchKernelGGL(k_chi0_mfma<TDX_PREC_FP64>, grid, dim3(256), 0, s, P, ld, tl->delta,
+  if (prec == TDX_PREC_FP64) {
+    dim3 grid((n_w + kWBlock - 1) / kWBlock, nblk * nblk, (unsigned)slices);
+    hipLaunchKernelGGL(k_chi0_f64, grid, dim3(256), 0, s, (const double2 *)P, ld, tl->delta,
                        tl->df, (int)tl->paired, (long long)n_trans, slice_len, omega, n_w, eta,
                        n_g, part);
-  else
-    hipLaunchKernelGGL(k_chi0_mfma<TDX_PREC_FP32>, grid, dim3(256), 0, s, P, ld, tl->delta,
-                       tl->df, (int)tl->paired, (long long)n_trans, slice_len, omega, n_w, eta,
-                       n_g, part);
+  } else {
+    TDX_TRY(chi0_f32_launch(P, ld, tl->delta, tl->df, (int)tl->paired, (long long)n_trans,
+                            slice_len, (int)slices, omega, n_w, eta, n_g, part, s));
+  }
   TDX_HIP(hipGetLastError());
   const unsigned rb = (unsigned)std::min<size_t>((out_elems + 255) / 256, 8192);
   hipLaunchKernelGGL(k_reduce_slices, dim3(rb), dim3(256), 0, s, part, (int)slices, out_elems,

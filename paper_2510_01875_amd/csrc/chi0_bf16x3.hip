@@ -40,12 +40,12 @@
 #include <cmath>
 
 #include "chi0_batch.h"
+#include "chi0_tile.h"
 #include "internal.h"
 
 namespace tdx {
 namespace {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -69,8 +69,6 @@ struct Cfg {
   static_assert(256 % kWBlock == 0 && CHUNK % 16 == 0, "tile must divide the block");
 };
 
-constexpr int kFoldChunks = 256;  // chunks summed in FP32 between folds
-
 __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 __device__ inline unsigned int cvt_pk(float a, float b) {
@@ -88,36 +86,12 @@ __device__ inline unsigned int cvt_pk_neg_b(float a, float b) {
 __device__ inline float lo_f(unsigned int w) { return __uint_as_float(w << 16); }
 __device__ inline float hi_f(unsigned int w) { return __uint_as_float(w & 0xffff0000u); }
 
-// LDS index (float2 units) of rho(tl, row) and of the weight (tl, w): the
-// four transition groups kq that one MFMA K-step reads side by side are
-// adjacent, so a read instruction touches consecutive words.
+// LDS index (float2 units) of rho(tl, row): the four transition groups kq
+// that one MFMA K-step reads side by side are adjacent, so a read
+// instruction touches consecutive words.
 __device__ inline int rho_index(int tl, int row) {
   return (((tl >> 4) * 4 + (tl & 3)) * 4 + ((tl & 15) >> 2)) * 16 + row;
 }
-template <class C>
-__device__ inline int wt_index(int tl, int w) {
-  return (((tl >> 4) * 4 + (tl & 3)) * C::kWBlock + w) * 4 + ((tl & 15) >> 2);
-}
-
-typedef __attribute__((address_space(3))) void lds_void;
-
-// 16 bytes per lane from global memory straight into LDS: lane l writes
-// dst + 16 l (dst uniform across the wave).  No registers are involved.
-__device__ inline void dma16(const void *src, unsigned int *dst) {
-  __builtin_amdgcn_global_load_lds(src, (lds_void *)dst, 16, 0, 0);
-}
-
-// Wait for this wave's outstanding global loads, LDS transfers included.
-__device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0f70); }  // vmcnt(0)
-
-// Wait until at most N of them are outstanding (they complete in issue
-// order): vmcnt is split over bits 3:0 and 15:14 of the immediate.
-template <int N>
-__device__ inline void wait_vm_n() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-
 // LDS DMA of one chunk: the B fragments and the FP32 rho rows of CHUNK
 // transitions.  The pair-density buffer carries a zero chunk past its last
 // transition, so whole chunks are read without clamping.  The 1 KB transfers
@@ -173,89 +147,6 @@ struct DmaPlan {
       if (i < kSlots - 1 || (kT % 4 == 0) || last_ok) dma16(src[i] + off, buf + dst[i]);
   }
 };
-
-// Weights df / (w - delta + i eta) of one chunk: loads into registers ...
-template <class C>
-struct Weights {
-  double d[C::kNW], f[C::kNW];
-};
-
-template <class C>
-__device__ inline void load_weights(Weights<C> &pw, const double *delta, const double *df,
-                                    long long tc, long long t_max, int tid) {
-  const int tw = tid / C::kWBlock;
-#pragma unroll
-  for (int i = 0; i < C::kNW; ++i) {
-    const int tl = std::min(tw + (256 / C::kWBlock) * i, C::kChunk - 1);
-    const long long t = std::min(tc + tl, t_max);
-    pw.d[i] = delta[t];
-    pw.f[i] = df[t];
-  }
-}
-
-// ... and into LDS: w - delta in FP64 (it may cancel), the rest in FP32
-// (relative error ~1e-7, far below the 2^-16 of the split products); zero
-// past the end of the slice or of the frequency grid.  For a time-reversal
-// paired list the weight is 2 df delta / D with
-// D = (w + i eta)^2 - delta^2 = (w - delta)(w + delta) - eta^2 + 2 i w eta,
-// whose real part is formed in FP64 for the same reason.
-template <class C>
-__device__ inline void store_weights(const Weights<C> &pw, float2 *wt, double om, bool w_ok,
-                                     double eta, int paired, int tid, long long tc,
-                                     long long t_hi) {
-  const int tw = tid / C::kWBlock, wi = tid % C::kWBlock;
-  const float etaf = (float)eta;
-#pragma unroll
-  for (int i = 0; i < C::kNW; ++i) {
-    const int tl = tw + (256 / C::kWBlock) * i;
-    if (C::kWPart && tl >= C::kChunk) break;
-    const bool ok = tc + tl < t_hi && w_ok;
-    float2 v;
-    if (paired) {
-      const float dr = (float)((om - pw.d[i]) * (om + pw.d[i]) - eta * eta);
-      const float di = (float)(2.0 * om * eta);
-      const float sc = (float)(2.0 * pw.f[i] * pw.d[i]) * __builtin_amdgcn_rcpf(fmaf(dr, dr, di * di));
-      v = make_float2(sc * dr, -sc * di);
-    } else {
-      const float x = (float)(om - pw.d[i]);
-      const float sc = (float)pw.f[i] * __builtin_amdgcn_rcpf(fmaf(x, x, etaf * etaf));
-      v = make_float2(sc * x, -sc * etaf);
-    }
-    wt[wt_index<C>(tl, wi)] = ok ? v : make_float2(0.f, 0.f);
-  }
-}
-
-// Fold the FP32 accumulators into the tile's FP64 partial in global memory
-// (the workgroup owns that region): the first fold stores, later ones add.
-template <int WPW, int SUB>
-__device__ inline void fold(f32x4 (&ar)[WPW][SUB], f32x4 (&ai)[WPW][SUB], double2 *part, int n_w,
-                            int n_g, int w0, int row0, int col0, int lane, int wave, bool first) {
-#pragma unroll
-  for (int i = 0; i < WPW; ++i) {
-    const int w = w0 + wave * WPW + i;
-#pragma unroll
-    for (int b = 0; b < SUB; ++b) {
-      const int col = col0 + b * 16 + (lane & 15);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        // D[row][col]: element j of lane l is row 4*(l/16)+j, column l%16
-        const int row = row0 + 4 * (lane >> 4) + j;
-        if (w < n_w && row < n_g && col < n_g) {
-          double2 *d = part + ((size_t)w * n_g + row) * n_g + col;
-          double2 v = make_double2((double)ar[i][b][j], (double)ai[i][b][j]);
-          if (!first) {
-            const double2 o = *d;
-            v.x += o.x;
-            v.y += o.y;
-          }
-          *d = v;
-        }
-      }
-      ar[i][b] = f32x4{0, 0, 0, 0};
-      ai[i][b] = f32x4{0, 0, 0, 0};
-    }
-  }
-}
 
 // One tile: rows row0..row0+15, columns col0..col0+16*NSUB-1, frequencies
 // w0..w0+kWBlock-1, transitions [t_lo, t_hi).  Sums run in FP32 for at most
@@ -687,16 +578,6 @@ __device__ __attribute__((always_inline)) void chi0_tile_pipe_n(
   }
   chi0_tile_pipe<WPW, SUB, CHUNK, NSUB>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
                                         n_w, eta, paired, n_g, w0, row0, col0, part);
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (id % 8), each with
-// its own L2.  Logical tile L runs on workgroup (L % per) * 8 + L / per with
-// per = total / 8, so every XCD runs a contiguous range of logical tiles and
-// neighbouring tiles, which read the same pair-density rows, share an L2.
-__device__ inline int xcd_logical(int id, int total) {
-  const int per = total / 8;
-  if (id >= per * 8) return id;  // ragged tail keeps its place
-  return (id % 8) * per + id / 8;
 }
 
 // The tile routine of a variant: plain (PIPE false, DEPTH buffers) or
