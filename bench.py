@@ -363,8 +363,8 @@ def main():
                      "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
                      "frac": per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],
                      "traffic": measured_traffic(w.name, args.prec),
-                     "kernel": {"bf16x3": "k_chi0_bf16x3", "fp32": "k_chi0_f32",
-                                "fp64": "k_chi0_f64"}[args.prec],
+                     "kernel": {"bf16x3": "k_chi0_bf16x3", "fp32": "k_chi0_fp<float>",
+                                "fp64": "k_chi0_fp<double>"}[args.prec],
                      "issued_mfma_frac": (3.0 if args.prec == "bf16x3" else 1.0)
                      * per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec]},
     }

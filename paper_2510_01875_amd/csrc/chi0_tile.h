@@ -1,6 +1,6 @@
-// Pieces shared by the FP32 and split-BF16 chi0 tiles (internal): LDS
-// DMA, waits, the per-chunk weights, the FP32 -> FP64 fold of the
-// accumulators and the XCD-aware workgroup order.  A tile configuration C
+// Pieces shared by the chi0 tiles (internal): LDS DMA, waits, the per-chunk
+// weights, the fold of the accumulators into FP64 partials and the
+// XCD-aware workgroup order.  A tile configuration C
 // provides kWBlock (frequencies per workgroup), kChunk (transitions per
 // chunk), kNW (weights per thread) and kWPart (fewer weights than threads).
 #pragma once
@@ -94,10 +94,13 @@ __device__ inline void store_weights(const Weights<C> &pw, float2 *wt, double om
   }
 }
 
-// Fold the FP32 accumulators into the tile's FP64 partial in global memory
-// (the workgroup owns that region): the first fold stores, later ones add.
-template <int WPW, int SUB>
-__device__ inline void fold(f32x4 (&ar)[WPW][SUB], f32x4 (&ai)[WPW][SUB], double2 *part, int n_w,
+// Fold the accumulators (FP32, or FP64 for the FP64 tile) into the tile's
+// FP64 partial in global memory (the workgroup owns that region): the first
+// fold stores, later ones add.  D[row][col] of a 16x16 MFMA: element j of
+// lane l is column l%16 and row 4(l/16) + j (FP32 and bf16 forms) or
+// l/16 + 4j (FP64 form, F64_ROWS).
+template <int WPW, int SUB, class V = f32x4, bool F64_ROWS = false>
+__device__ inline void fold(V (&ar)[WPW][SUB], V (&ai)[WPW][SUB], double2 *part, int n_w,
                             int n_g, int w0, int row0, int col0, int lane, int wave, bool first) {
 #pragma unroll
   for (int i = 0; i < WPW; ++i) {
@@ -107,8 +110,7 @@ __device__ inline void fold(f32x4 (&ar)[WPW][SUB], f32x4 (&ai)[WPW][SUB], double
       const int col = col0 + b * 16 + (lane & 15);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        // D[row][col]: element j of lane l is row 4*(l/16)+j, column l%16
-        const int row = row0 + 4 * (lane >> 4) + j;
+        const int row = row0 + (F64_ROWS ? (lane >> 4) + 4 * j : 4 * (lane >> 4) + j);
         if (w < n_w && row < n_g && col < n_g) {
           double2 *d = part + ((size_t)w * n_g + row) * n_g + col;
           double2 v = make_double2((double)ar[i][b][j], (double)ai[i][b][j]);
@@ -120,8 +122,8 @@ __device__ inline void fold(f32x4 (&ar)[WPW][SUB], f32x4 (&ai)[WPW][SUB], double
           *d = v;
         }
       }
-      ar[i][b] = f32x4{0, 0, 0, 0};
-      ai[i][b] = f32x4{0, 0, 0, 0};
+      ar[i][b] = V{0, 0, 0, 0};
+      ai[i][b] = V{0, 0, 0, 0};
     }
   }
 }
