@@ -7,8 +7,6 @@
 // chi0_batch.hip).  The transition axis is cut into slices whose FP64
 // partials are summed here in a fixed order (no atomics: bitwise
 // reproducible).
-#include <hip/hip_bf16.h>
-
 #include <algorithm>
 #include <cmath>
 
