@@ -133,6 +133,7 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "counters_k_chi0_bf16x3_fcc_c2.
 TRAFFIC_SOURCES = ["paper_2510_01875_amd/csrc/chi0_bf16x3.hip",
                    "paper_2510_01875_amd/csrc/chi0_batch.hip",
                    "paper_2510_01875_amd/csrc/chi0_batch.h",
+                   "paper_2510_01875_amd/csrc/chi0_tile.h",
                    "paper_2510_01875_amd/csrc/pair_density.hip"]
 
 

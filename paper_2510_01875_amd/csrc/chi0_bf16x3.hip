@@ -51,9 +51,11 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <int WPW, int SUB, int CHUNK>
+template <int WPW, int SUB, int CHUNK, int NW = 4>
 struct Cfg {
-  static constexpr int kWBlock = 4 * WPW;  // frequencies per tile
+  static constexpr int kWaves = NW;        // waves per workgroup
+  static constexpr int kThreads = 64 * NW;
+  static constexpr int kWBlock = NW * WPW;  // frequencies per tile
   static constexpr int kSub = SUB;
   static constexpr int kCols = 16 * SUB;   // G' per tile
   static constexpr int kChunk = CHUNK;
@@ -62,11 +64,11 @@ struct Cfg {
   static constexpr int kRhoWords = CHUNK * 16 * 2;           // [t][row] float2
   static constexpr int kWtWords = CHUNK * kWBlock * 2;       // [t][w] float2
   static constexpr int kBufWords = kBWords + kRhoWords + kWtWords;
-  // weights per thread; when the chunk holds fewer than 256 weights only the
-  // first CHUNK * kWBlock threads store one
-  static constexpr bool kWPart = CHUNK * kWBlock < 256;
-  static constexpr int kNW = kWPart ? 1 : CHUNK * kWBlock / 256;
-  static_assert(256 % kWBlock == 0 && CHUNK % 16 == 0, "tile must divide the block");
+  // weights per thread; when the chunk holds fewer weights than threads only
+  // the first CHUNK * kWBlock threads store one
+  static constexpr bool kWPart = CHUNK * kWBlock < kThreads;
+  static constexpr int kNW = kWPart ? 1 : CHUNK * kWBlock / kThreads;
+  static_assert(kThreads % kWBlock == 0 && CHUNK % 16 == 0, "tile must divide the block");
 };
 
 __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
@@ -111,8 +113,8 @@ __device__ inline int rho_index(int tl, int row) {
 template <class C, int NSUB>
 struct DmaPlan {
   static constexpr int kB = C::kSteps * NSUB * 2, kT = kB + C::kChunk / 8;
-  static constexpr int kSlots = (kT + 3) / 4;
-  static constexpr int kIssued = kT / 4;  // transfers every wave issues per chunk
+  static constexpr int kSlots = (kT + C::kWaves - 1) / C::kWaves;
+  static constexpr int kIssued = kT / C::kWaves;  // transfers every wave issues per chunk
   const unsigned char *src[kSlots];
   int dst[kSlots];  // word offset in a buffer
   bool last_ok;     // the last slot holds a transfer for this wave
@@ -124,7 +126,7 @@ struct DmaPlan {
     const size_t lane_r = (size_t)(((lane >> 5) + 4 * ((lane >> 3) & 3)) * ld + 2 * (lane & 7)) * 8;
 #pragma unroll
     for (int i = 0; i < kSlots; ++i) {
-      const int x = 4 * i + wave;  // uniform across the wave
+      const int x = C::kWaves * i + wave;  // uniform across the wave
       if (x < kB) {
         const int m = x >> 1, comp = x & 1;
         const int st = m / NSUB, b = m % NSUB;
@@ -137,14 +139,14 @@ struct DmaPlan {
         dst[i] = C::kBWords + d * 256;
       }
     }
-    last_ok = 4 * (kSlots - 1) + wave < kT;
+    last_ok = C::kWaves * (kSlots - 1) + wave < kT;
   }
 
   // the chunk `off` bytes (8 CHUNK ld per chunk) past the first one
   __device__ inline void issue(size_t off, unsigned int *buf) const {
 #pragma unroll
     for (int i = 0; i < kSlots; ++i)
-      if (i < kSlots - 1 || (kT % 4 == 0) || last_ok) dma16(src[i] + off, buf + dst[i]);
+      if (i < kSlots - 1 || (kT % C::kWaves == 0) || last_ok) dma16(src[i] + off, buf + dst[i]);
   }
 };
 
@@ -154,12 +156,12 @@ struct DmaPlan {
 // block, FP64) between runs.  DEPTH LDS buffers: the transfers of chunk
 // c + DEPTH - 1 are issued in iteration c; with three buffers the wait at the
 // end of an iteration leaves that iteration's transfers in flight.
-template <int WPW, int SUB, int CHUNK, int NSUB, int DEPTH>
+template <int WPW, int SUB, int CHUNK, int NSUB, int DEPTH, int NW>
 __device__ __attribute__((always_inline)) void chi0_tile(
     unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
     int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
-  typedef Cfg<WPW, SUB, CHUNK> C;
+  typedef Cfg<WPW, SUB, CHUNK, NW> C;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int kq = lane >> 4;
@@ -281,20 +283,20 @@ __device__ __attribute__((always_inline)) void chi0_tile(
 // The tile routine for the tile's number of 16-column blocks inside the
 // padded basis (ld is a multiple of 16): full tiles run NSUB = SUB, the last
 // tile of a row may run fewer.
-template <int WPW, int SUB, int CHUNK, int DEPTH, int NSUB = SUB>
+template <int WPW, int SUB, int CHUNK, int DEPTH, int NW, int NSUB = SUB>
 __device__ __attribute__((always_inline)) void chi0_tile_n(
     int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
     int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
   if constexpr (NSUB > 1) {
     if (nsub < NSUB) {
-      chi0_tile_n<WPW, SUB, CHUNK, DEPTH, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo,
+      chi0_tile_n<WPW, SUB, CHUNK, DEPTH, NW, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo,
                                                      t_hi, omega, n_w, eta, paired, n_g, w0, row0, col0,
                                                      part);
       return;
     }
   }
-  chi0_tile<WPW, SUB, CHUNK, NSUB, DEPTH>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
+  chi0_tile<WPW, SUB, CHUNK, NSUB, DEPTH, NW>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
                                           n_w, eta, paired, n_g, w0, row0, col0, part);
 }
 
@@ -582,16 +584,17 @@ __device__ __attribute__((always_inline)) void chi0_tile_pipe_n(
 
 // The tile routine of a variant: plain (PIPE false, DEPTH buffers) or
 // software-pipelined.
-template <int WPW, int SUB, int CHUNK, bool PIPE, int DEPTH>
+template <int WPW, int SUB, int CHUNK, bool PIPE, int DEPTH, int NW>
 __device__ __attribute__((always_inline)) void run_tile(
     int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
     int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
+  static_assert(NW == 4 || !PIPE, "8-wave workgroups: plain tile only");
   if constexpr (PIPE)
     chi0_tile_pipe_n<WPW, SUB, CHUNK>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
                                       n_w, eta, paired, n_g, w0, row0, col0, part);
   else
-    chi0_tile_n<WPW, SUB, CHUNK, DEPTH>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi,
+    chi0_tile_n<WPW, SUB, CHUNK, DEPTH, NW>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi,
                                         omega, n_w, eta, paired, n_g, w0, row0, col0, part);
 }
 
@@ -601,12 +604,12 @@ __device__ __attribute__((always_inline)) void run_tile(
 // latency exposed: about 60 % of the two-wave rate for 16 x 128 and 16 x 144
 // tiles), 1 for the pipelined tile, whose two operand register sets need the
 // 512 registers of a lone wave.
-template <int WPW, int SUB, int CHUNK, int OCC, bool PIPE, int DEPTH>
-__global__ void __launch_bounds__(256, OCC)
+template <int WPW, int SUB, int CHUNK, int OCC, bool PIPE, int DEPTH, int NW>
+__global__ void __launch_bounds__(64 * NW, OCC)
     k_chi0_bf16x3(const void *P, const void *R, int ld, const double *delta, const double *df,
                   long long n_trans, long long slice_len, const double *omega, int n_w,
                   double eta, int paired, int n_g, int ncb, double2 *part) {
-  typedef Cfg<WPW, SUB, CHUNK> C;
+  typedef Cfg<WPW, SUB, CHUNK, NW> C;
   extern __shared__ unsigned int lds[];
   const int nx = gridDim.x, ny = gridDim.y;
   const int id = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
@@ -616,7 +619,7 @@ __global__ void __launch_bounds__(256, OCC)
   const long long t_lo = (long long)bz * slice_len;
   const long long t_hi = std::min(n_trans, t_lo + slice_len);
   const int col0 = gc * C::kCols;
-  run_tile<WPW, SUB, CHUNK, PIPE, DEPTH>(std::min(SUB, (ld - col0) / 16), lds, P, R, ld, delta, df,
+  run_tile<WPW, SUB, CHUNK, PIPE, DEPTH, NW>(std::min(SUB, (ld - col0) / 16), lds, P, R, ld, delta, df,
                                   n_trans, t_lo, t_hi, omega, n_w, eta, paired, n_g, bx * C::kWBlock,
                                   gb * 16, col0, part + (size_t)bz * n_w * n_g * n_g);
 }
@@ -626,10 +629,10 @@ __global__ void __launch_bounds__(256, OCC)
 // round), so every workgroup runs a similar amount of work and leaves when it
 // passes the end.  No LDS beyond the tile's double buffer (two workgroups still fit per
 // CU) and no atomics; the assignment is deterministic.
-template <int WPW, int SUB, int CHUNK, int OCC, bool PIPE, int DEPTH>
-__global__ void __launch_bounds__(256, OCC)
+template <int WPW, int SUB, int CHUNK, int OCC, bool PIPE, int DEPTH, int NW>
+__global__ void __launch_bounds__(64 * NW, OCC)
     k_chi0_bf16x3_persistent(const BatchItem *items, const BatchTile *tiles, int n_tiles) {
-  typedef Cfg<WPW, SUB, CHUNK> C;
+  typedef Cfg<WPW, SUB, CHUNK, NW> C;
   extern __shared__ unsigned int lds[];
   const int G = gridDim.x;
   for (int base = 0; base < n_tiles; base += G) {
@@ -641,7 +644,7 @@ __global__ void __launch_bounds__(256, OCC)
     const long long t_lo = tl.slice * it.slice_len;
     const long long t_hi = std::min(it.n_trans, t_lo + it.slice_len);
     const int col0 = tl.gc * C::kCols;
-    run_tile<WPW, SUB, CHUNK, PIPE, DEPTH>(std::min(SUB, (it.ld - col0) / 16), lds, it.P, it.R, it.ld,
+    run_tile<WPW, SUB, CHUNK, PIPE, DEPTH, NW>(std::min(SUB, (it.ld - col0) / 16), lds, it.P, it.R, it.ld,
                                     it.delta, it.df, it.n_trans, t_lo, t_hi, it.omega, it.n_w,
                                     it.eta, it.paired, it.n_g, tl.wblk * C::kWBlock, tl.gb * 16, col0,
                                     it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
@@ -649,31 +652,32 @@ __global__ void __launch_bounds__(256, OCC)
   }
 }
 
-template <int W, int S, int K, bool PIPE, int DEPTH>
+template <int W, int S, int K, bool PIPE, int DEPTH, int NW>
 constexpr size_t variant_lds() {
   if constexpr (PIPE)
     return PipeLds<W, S, K>::kBytes;
   else
-    return (size_t)DEPTH * Cfg<W, S, K>::kBufWords * 4;
+    return (size_t)DEPTH * Cfg<W, S, K, NW>::kBufWords * 4;
 }
 
 struct Variant {
-  int wpw, sub, chunk, occ;
+  int wpw, sub, chunk, occ, waves;
   size_t lds;
   const void *grid_fn;
   const void *pers_fn;
 };
 
-#define TDX_V(W, S, K, O, PIPE, DEPTH)                                                   \
+#define TDX_V(W, S, K, O, PIPE, DEPTH, NW)                                               \
   Variant {                                                                              \
-    W, S, K, O, variant_lds<W, S, K, PIPE, DEPTH>(),                                     \
-        (const void *)k_chi0_bf16x3<W, S, K, O, PIPE, DEPTH>,                            \
-        (const void *)k_chi0_bf16x3_persistent<W, S, K, O, PIPE, DEPTH>                  \
+    W, S, K, O, NW, variant_lds<W, S, K, PIPE, DEPTH, NW>(),                             \
+        (const void *)k_chi0_bf16x3<W, S, K, O, PIPE, DEPTH, NW>,                        \
+        (const void *)k_chi0_bf16x3_persistent<W, S, K, O, PIPE, DEPTH, NW>              \
   }
-const Variant kVariants[] = {TDX_V(4, 4, 32, 2, false, 2), TDX_V(2, 8, 16, 2, false, 2),
-                             TDX_V(4, 2, 32, 2, false, 2), TDX_V(2, 4, 32, 2, false, 2),
-                             TDX_V(2, 9, 16, 2, false, 2), TDX_V(2, 8, 32, 2, false, 2),
-                             TDX_V(2, 9, 32, 1, true, 0),  TDX_V(2, 9, 16, 2, false, 3)};
+const Variant kVariants[] = {TDX_V(4, 4, 32, 2, false, 2, 4), TDX_V(2, 8, 16, 2, false, 2, 4),
+                             TDX_V(4, 2, 32, 2, false, 2, 4), TDX_V(2, 4, 32, 2, false, 2, 4),
+                             TDX_V(2, 9, 16, 2, false, 2, 4), TDX_V(2, 8, 32, 2, false, 2, 4),
+                             TDX_V(2, 9, 32, 1, true, 0, 4),  TDX_V(2, 9, 16, 2, false, 3, 4),
+                             TDX_V(2, 9, 32, 1, false, 2, 8)};
 #undef TDX_V
 
 }  // namespace
@@ -681,7 +685,7 @@ const Variant kVariants[] = {TDX_V(4, 4, 32, 2, false, 2), TDX_V(2, 8, 16, 2, fa
 int bf16x3_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 
 void bf16x3_variant_shape(int v, int *wblock, int *cols) {
-  *wblock = 4 * kVariants[v].wpw;
+  *wblock = kVariants[v].waves * kVariants[v].wpw;
   *cols = 16 * kVariants[v].sub;
 }
 
@@ -694,14 +698,15 @@ int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double
   const Variant &V = kVariants[v];
   const int nblk = ld / 16;
   int ncb = (ld + 16 * V.sub - 1) / (16 * V.sub);
-  dim3 grid((n_w + 4 * V.wpw - 1) / (4 * V.wpw), nblk * ncb, (unsigned)slices);
+  const int wb = V.waves * V.wpw;
+  dim3 grid((n_w + wb - 1) / wb, nblk * ncb, (unsigned)slices);
   TDX_HIP(hipFuncSetAttribute(V.grid_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)V.lds));
   void *args[] = {(void *)&P,       (void *)&R,         (void *)&ld,
                   (void *)&delta,   (void *)&df,
                   (void *)&n_trans, (void *)&slice_len, (void *)&omega, (void *)&n_w,
                   (void *)&eta,     (void *)&paired,    (void *)&n_g,   (void *)&ncb,
                   (void *)&part};
-  TDX_HIP(hipLaunchKernel(V.grid_fn, grid, dim3(256), args, V.lds, s));
+  TDX_HIP(hipLaunchKernel(V.grid_fn, grid, dim3(64 * V.waves), args, V.lds, s));
   return TDX_OK;
 }
 
@@ -710,7 +715,7 @@ int bf16x3_launch_persistent(int v, const BatchItem *items, const BatchTile *til
   const Variant &V = kVariants[v];
   TDX_HIP(hipFuncSetAttribute(V.pers_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)V.lds));
   void *args[] = {(void *)&items, (void *)&tiles, (void *)&n_tiles};
-  TDX_HIP(hipLaunchKernel(V.pers_fn, dim3(n_blocks), dim3(256), args, V.lds, s));
+  TDX_HIP(hipLaunchKernel(V.pers_fn, dim3(n_blocks), dim3(64 * V.waves), args, V.lds, s));
   return TDX_OK;
 }
 

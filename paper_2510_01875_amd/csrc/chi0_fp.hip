@@ -44,6 +44,7 @@ struct Vec4<double> {
 template <class E, int WPW, int SUB, int CHUNK>
 struct CfgFp {
   static constexpr int kW = sizeof(E) / 4;          // 32-bit words per real
+  static constexpr int kThreads = 256;
   static constexpr int kWBlock = 4 * WPW;           // frequencies per workgroup
   static constexpr int kSub = SUB;
   static constexpr int kCols = 16 * SUB;            // G' per tile
@@ -69,7 +70,7 @@ __device__ inline void store_weights_f64(const Weights<C> &pw, double2 *wt, doub
   const int tw = tid / C::kWBlock, wi = tid % C::kWBlock;
 #pragma unroll
   for (int i = 0; i < C::kNW; ++i) {
-    const int tl = tw + (256 / C::kWBlock) * i;
+    const int tl = tw + (C::kThreads / C::kWBlock) * i;
     if (C::kWPart && tl >= C::kChunk) break;
     const bool ok = tc + tl < t_hi && w_ok;
     const double d = pw.d[i];

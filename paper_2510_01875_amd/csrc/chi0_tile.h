@@ -1,8 +1,9 @@
 // Pieces shared by the chi0 tiles (internal): LDS DMA, waits, the per-chunk
 // weights, the fold of the accumulators into FP64 partials and the
 // XCD-aware workgroup order.  A tile configuration C
-// provides kWBlock (frequencies per workgroup), kChunk (transitions per
-// chunk), kNW (weights per thread) and kWPart (fewer weights than threads).
+// provides kThreads (threads per workgroup), kWBlock (frequencies per
+// workgroup), kChunk (transitions per chunk), kNW (weights per thread) and
+// kWPart (fewer weights than threads).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,7 +56,7 @@ __device__ inline void load_weights(Weights<C> &pw, const double *delta, const d
   const int tw = tid / C::kWBlock;
 #pragma unroll
   for (int i = 0; i < C::kNW; ++i) {
-    const int tl = std::min(tw + (256 / C::kWBlock) * i, C::kChunk - 1);
+    const int tl = std::min(tw + (C::kThreads / C::kWBlock) * i, C::kChunk - 1);
     const long long t = std::min(tc + tl, t_max);
     pw.d[i] = delta[t];
     pw.f[i] = df[t];
@@ -76,7 +77,7 @@ __device__ inline void store_weights(const Weights<C> &pw, float2 *wt, double om
   const float etaf = (float)eta;
 #pragma unroll
   for (int i = 0; i < C::kNW; ++i) {
-    const int tl = tw + (256 / C::kWBlock) * i;
+    const int tl = tw + (C::kThreads / C::kWBlock) * i;
     if (C::kWPart && tl >= C::kChunk) break;
     const bool ok = tc + tl < t_hi && w_ok;
     float2 v;
