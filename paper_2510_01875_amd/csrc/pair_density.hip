@@ -7,6 +7,7 @@
 // Accumulation is FP64; the store converts to the requested layout.
 
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 #include "tables.h"
@@ -120,54 +121,91 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     // this lane's A row: transition tm0 + r (zero past the row)
     const bool row_ok = tm0 + r < t1;
     const double2 *crow = cj + (size_t)(row_ok ? tm[tm0 + r] : 0) * npw_max;
-    for (int gt0 = 0; gt0 < n_gt; gt0 += kPdGT) {
-      f64x4 acr[kPdGT], aci[kPdGT];
+    // NQ tiles of 16 G starting at tile gt0 (NQ a compile-time count, so the
+    // K-step below is straight-line code)
+    auto tiles = [&](int gt0, auto nq_c) {
+      constexpr int NQ = decltype(nq_c)::value;
+      f64x4 acr[NQ], aci[NQ];
       // G + G_s of this lane's column in each tile, packed as three 10-bit
       // fields offset by 512
-      unsigned gp[kPdGT];
+      unsigned gp[NQ];
 #pragma unroll
-      for (int q = 0; q < kPdGT; ++q) {
+      for (int q = 0; q < NQ; ++q) {
         acr[q] = aci[q] = f64x4{0.0, 0.0, 0.0, 0.0};
         const int g = std::min((gt0 + q) * 16 + r, n_g - 1);
         gp[q] = (unsigned)(gbasis[3 * g] + gs0 + 512) |
                 ((unsigned)(gbasis[3 * g + 1] + gs1 + 512) << 10) |
                 ((unsigned)(gbasis[3 * g + 2] + gs2 + 512) << 20);
       }
+      // A operand one K-step ahead (a global load whose latency the current
+      // step's MFMAs cover)
+      auto load_a = [&](int j0) {
+        const int j = j0 + kq;
+        return j < npj && row_ok ? crow[j] : make_double2(0.0, 0.0);
+      };
+      double2 a_next = load_a(0);
       for (int j0 = 0; j0 < npj; j0 += 4) {
         const int j = j0 + kq;
-        const bool j_ok = j < npj && row_ok;
-        const double2 a = j_ok ? crow[j] : make_double2(0.0, 0.0);
+        const double2 a = a_next;
+        a_next = load_a(j0 + 4);
         const int jc = std::min(j, npj - 1);
         const int m0 = mj[3 * jc] + M0, m1 = mj[3 * jc + 1] + M1, m2 = mj[3 * jc + 2] + M2;
+        // B operands of every tile: all lookups first, then all values, with
+        // no branches (out-of-range entries read slot 0 and are zeroed)
+        int li[NQ];
+        bool ok[NQ];
 #pragma unroll
-        for (int q = 0; q < kPdGT; ++q) {
-          if (gt0 + q < n_gt) {  // uniform across the wave
-            const int g = (gt0 + q) * 16 + r;
-            const int x0 = m0 + 512 - (int)(gp[q] & 1023u);
-            const int x1 = m1 + 512 - (int)((gp[q] >> 10) & 1023u);
-            const int x2 = m2 + 512 - (int)(gp[q] >> 20);
-            double2 u = make_double2(0.0, 0.0);
-            if (j < npj && g < n_g && x0 >= 0 && x0 <= 2 * M0 && x1 >= 0 && x1 < W1 && x2 >= 0 &&
-                x2 < W2) {
-              const int idx = lutk[((long)x0 * W1 + x1) * W2 + x2];
-              if (idx >= 0) u = ckn[idx];
-            }
-            acr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, u.x, acr[q], 0, 0, 0);
-            acr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, u.y, acr[q], 0, 0, 0);
-            aci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, u.y, aci[q], 0, 0, 0);
-            aci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, u.x, aci[q], 0, 0, 0);
-          }
+        for (int q = 0; q < NQ; ++q) {
+          const int g = (gt0 + q) * 16 + r;
+          const int x0 = m0 + 512 - (int)(gp[q] & 1023u);
+          const int x1 = m1 + 512 - (int)((gp[q] >> 10) & 1023u);
+          const int x2 = m2 + 512 - (int)(gp[q] >> 20);
+          ok[q] = j < npj && g < n_g && x0 >= 0 && x0 <= 2 * M0 && x1 >= 0 && x1 < W1 &&
+                  x2 >= 0 && x2 < W2;
+          li[q] = ok[q] ? ((x0 * W1 + x1) * W2 + x2) : 0;
+        }
+        int idx[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) idx[q] = lutk[li[q]];
+        double2 u[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const bool hit = ok[q] && idx[q] >= 0;
+          const double2 v = ckn[hit ? idx[q] : 0];
+          u[q] = hit ? v : make_double2(0.0, 0.0);
+        }
+        // per accumulator the same order of products as one tile at a time
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          acr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, u[q].x, acr[q], 0, 0, 0);
+          aci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, u[q].y, aci[q], 0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          acr[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, u[q].y, acr[q], 0, 0, 0);
+          aci[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, u[q].x, aci[q], 0, 0, 0);
         }
       }
 #pragma unroll
-      for (int q = 0; q < kPdGT; ++q) {
-        if (gt0 + q < n_gt) {
+      for (int q = 0; q < NQ; ++q) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const long long t = tm0 + kq + 4 * e;
-            if (t < t1) store<FMT>(P, t, (gt0 + q) * 16 + r, ld, n_trans, acr[q][e], aci[q][e]);
-          }
+        for (int e = 0; e < 4; ++e) {
+          const long long t = tm0 + kq + 4 * e;
+          if (t < t1) store<FMT>(P, t, (gt0 + q) * 16 + r, ld, n_trans, acr[q][e], aci[q][e]);
         }
+      }
+    };
+    for (int gt0 = 0; gt0 < n_gt; gt0 += kPdGT) {
+      switch (std::min(kPdGT, n_gt - gt0)) {  // uniform across the wave
+        case 1: tiles(gt0, std::integral_constant<int, 1>{}); break;
+        case 2: tiles(gt0, std::integral_constant<int, 2>{}); break;
+        case 3: tiles(gt0, std::integral_constant<int, 3>{}); break;
+        case 4: tiles(gt0, std::integral_constant<int, 4>{}); break;
+        case 5: tiles(gt0, std::integral_constant<int, 5>{}); break;
+        case 6: tiles(gt0, std::integral_constant<int, 6>{}); break;
+        case 7: tiles(gt0, std::integral_constant<int, 7>{}); break;
+        case 8: tiles(gt0, std::integral_constant<int, 8>{}); break;
+        default: tiles(gt0, std::integral_constant<int, kPdGT>{}); break;
       }
     }
   }
