@@ -32,7 +32,7 @@ def ctx(tdx):
     c.close()
 
 
-def _prepare(tdx, ctx, w, st, prec):
+def _prepare(tdx, ctx, w, st, prec, paired=False):
     """Per-q transitions, pair densities and batch items (occupations at each
     q's temperature are taken before its transitions)."""
     import torch
@@ -42,7 +42,7 @@ def _prepare(tdx, ctx, w, st, prec):
         tdx.occupations(ctx, st, T, w.n_electrons, w.f_trunc)
         basis, g0 = tdx.response_basis(w.cell, w.kgrid, w.qs[iq], w.ecut_chi[iq])
         gb = torch.from_numpy(basis).cuda()
-        tr = tdx.transitions(ctx, st, w.qs[iq], w.f_trans_thr)
+        tr = tdx.transitions(ctx, st, w.qs[iq], w.f_trans_thr, paired=paired)
         P = tdx.pair_density(ctx, st, w.qs[iq], tr, gb, prec)
         om = torch.as_tensor(w.omega_grid(iq), device="cuda")
         K = tdx.kernel_matrix(ctx, st, w.qs[iq], gb, w.xc, w.dens_grid)
@@ -51,16 +51,18 @@ def _prepare(tdx, ctx, w, st, prec):
     return out
 
 
-def test_batched_persistent_matches_single_and_oracle(tdx, ctx):
+@pytest.mark.parametrize("paired", [False, True])
+def test_batched_persistent_matches_single_and_oracle(tdx, ctx, paired):
     """Six q with ragged transition counts (T from 1 to 8 eV) in one
     persistent launch: bitwise equal to one launch per q with the same tile
-    configuration, and within the split-BF16 bar of the oracle."""
+    configuration, and within the split-BF16 bar of the oracle (whose sum is
+    over the full list also when the batch contracts paired lists)."""
     import torch
     import oracle
-    _say("batched")
+    _say("batched", "paired" if paired else "full")
     w = workloads.fcc_c4_small()
     st = tdx.build_states(ctx, w)
-    prep = _prepare(tdx, ctx, w, st, "bf16x3")
+    prep = _prepare(tdx, ctx, w, st, "bf16x3", paired)
     counts = [len(p["tr"]) for p in prep]
     assert max(counts) > 1.5 * min(counts)
     tdx.chi0_batched(ctx, [p["item"] for p in prep], "bf16x3")
