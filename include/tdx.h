@@ -294,8 +294,11 @@ int tdx_chi0_variants(int prec, int *count);
 int tdx_chi0_set_config(tdx_ctx *ctx, int prec, int n_g, int variant, int slice_log2);
 int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slice_log2);
 /* Time every variant and slice length 2^{18,20} on the probe item (its
- * first max_trans transitions; probe->chi0 is overwritten), keep the fastest
- * for the probe's size class in the context and return it.  Synchronises. */
+ * first max_trans transitions; probe->chi0 is overwritten) in both launch
+ * forms, one grid launch and a one-item plan (the persistent kernel), keep
+ * the one with the smallest sum of the two times for the probe's size class
+ * in the context and return it (best_ms is that sum).  Allocates the
+ * one-item plans; synchronises. */
 int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_t max_trans,
                       int *best_variant, int *best_slice_log2, double *best_ms);
 /* Tuning cache as JSON text keyed by the gfx arch. */

@@ -331,21 +331,41 @@ int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_
   double best = 1e300;
   int bv = 0, bs = 18;
   int rc = TDX_OK;
+  // both launch forms of the probe: one grid launch, and a one-item plan
+  // (persistent kernel) built for the variant under test
+  tdx_chi0_item one = *probe;
+  one.n_trans = nt;
+  tdx_chi0_tune &slot = ctx->tune[bucket_of(ld)];
+  const tdx_chi0_tune saved = slot;
+  auto timed = [&](auto &&enqueue) {
+    double ms_best = 1e300;
+    for (int rep = 0; rep < 3 && rc == TDX_OK; ++rep) {
+      hipEventRecord(e0, s);
+      rc = enqueue();
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) ms_best = std::min(ms_best, (double)ms);
+    }
+    return ms_best;
+  };
   for (int v = 0; v < bf16x3_variant_count() && rc == TDX_OK; ++v) {
     for (int sl : slice_opts) {
-      double ms_best = 1e300;
-      for (int rep = 0; rep < 3 && rc == TDX_OK; ++rep) {
-        hipEventRecord(e0, s);
-        rc = chi0_bf16x3_with(ctx, v, sl, probe->P, probe->n_trans, ld, probe->tl->delta,
-                              probe->tl->df, (int)probe->tl->paired, nt,
-                              probe->omega, probe->n_w, probe->eta, probe->n_g, probe->pref,
-                              (double2 *)probe->chi0, s);
-        hipEventRecord(e1, s);
-        hipEventSynchronize(e1);
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0) ms_best = std::min(ms_best, (double)ms);
-      }
+      double ms_best = timed([&] {
+        return chi0_bf16x3_with(ctx, v, sl, probe->P, probe->n_trans, ld, probe->tl->delta,
+                                probe->tl->df, (int)probe->tl->paired, nt, probe->omega,
+                                probe->n_w, probe->eta, probe->n_g, probe->pref,
+                                (double2 *)probe->chi0, s);
+      });
+      if (rc != TDX_OK) break;
+      slot.variant = v;
+      slot.slice_log2 = sl;
+      tdx_chi0_plan *pl = nullptr;
+      rc = tdx_chi0_plan_create(ctx, &one, 1, TDX_PREC_BF16X3, &pl);
+      if (rc == TDX_OK) ms_best += timed([&] { return tdx_chi0_plan_launch(ctx, pl, s); });
+      if (pl) tdx_chi0_plan_destroy(pl);
+      slot = saved;
       if (rc != TDX_OK) break;
       if (ms_best < best) {
         best = ms_best;
