@@ -38,11 +38,21 @@ def f_alg(n_w, n_g, n_t):
     return 8.0 * n_w * n_g * n_g * n_t
 
 
+def kernel(tdx, ctx, w, st, qj, gb, fx):
+    """K for one q; the q-independent f_xc(G) grid is computed once per
+    temperature within one step (fx holds it) and reused for every q."""
+    if w.xc == "rpa":
+        return tdx.kernel_matrix_from_grid(ctx, st, qj, gb, w.xc)
+    if st.temperature not in fx:
+        fx[st.temperature] = tdx.xc_kernel_grid(ctx, st, w.dens_grid)
+    return tdx.kernel_matrix_from_grid(ctx, st, qj, gb, w.xc, w.dens_grid, fx[st.temperature])
+
+
 def run_step(tdx, ctx, w, st, setup, prec, qs, torch, keep=False, paired=True):
     """One pass of the path over the q indices `qs`, one chi0 launch per q,
     chi0 bracketed by events (used for the comparison legs)."""
     stream = torch.cuda.current_stream()
-    out = []
+    out, fx = [], {}
     for iq in qs:
         T = w.temperatures[iq]
         if st.temperature != T:
@@ -57,7 +67,7 @@ def run_step(tdx, ctx, w, st, setup, prec, qs, torch, keep=False, paired=True):
         c0 = tdx.chi0(ctx, tr, P, gb.shape[0], prec, om, w.eta, 2.0 / (st.n_k * st.omega_cell))
         e1.record(stream)
         del P
-        K = tdx.kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid)
+        K = kernel(tdx, ctx, w, st, qj, gb, fx)
         c00 = tdx.dyson(ctx, c0, K, i_g0)
         beta = 1.0 / T
         S = tdx.dsf(ctx, c00, om, beta, w.n_electrons / st.omega_cell)
@@ -116,11 +126,12 @@ class BatchedStep:
                 tdx.chi0(ctx, it.tr, it.P, it.out.shape[1], self.prec, it.omega, w.eta,
                          it.c.pref, out=it.out)
         e1.record(stream)
-        out = []
+        out, fx = [], {}
         for iq in range(len(w.qs)):
+            self._occ(iq)
             gb, i_g0, om, tau = self.setup[iq]
             T = w.temperatures[iq]
-            K = tdx.kernel_matrix(ctx, st, w.qs[iq], gb, w.xc, w.dens_grid)
+            K = kernel(tdx, ctx, w, st, w.qs[iq], gb, fx)
             c00 = tdx.dyson(ctx, self.items[iq].out, K, i_g0)
             S = tdx.dsf(ctx, c00, om, 1.0 / T, w.n_electrons / st.omega_cell)
             F = tdx.itcf(ctx, S, om, 1.0 / T, tau)

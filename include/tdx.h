@@ -317,10 +317,27 @@ int tdx_tune_load(tdx_ctx *ctx, const char *path);
  * local form of the paper's adiabatic kernel, Sec. A.1).  States with
  * f_nk < 1e-20 are skipped (their weight is below FP64 resolution).
  * K: device complex128 [n_g][n_g].  SHAPE if a grid side is smaller than
- * the span of a wavefunction basis.  Synchronises for ALDA. */
+ * the span of a wavefunction basis.  Synchronises for ALDA.  Equal to
+ * tdx_xc_kernel_grid followed by tdx_kernel_matrix_from_grid. */
 int tdx_kernel_matrix(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
                       const int *gbasis, int n_g, int xc, const int dens_grid[3],
                       double *K, tdx_stream stream);
+
+/* The q-independent part of the ALDA kernel: f_xc(G) on the full FFT grid
+ * of dens_grid[3] (as defined above), for the states' current occupations.
+ * fxg: device complex128 [N0][N1][N2], caller-owned, index
+ * ((G_0 mod N0) N1 + (G_1 mod N1)) N2 + (G_2 mod N2).  A grid stays valid
+ * until the occupations change (tdx_occupations).  Same SHAPE errors as
+ * tdx_kernel_matrix; synchronises. */
+int tdx_xc_kernel_grid(tdx_ctx *ctx, const tdx_states *st, const int dens_grid[3], double *fxg,
+                       tdx_stream stream);
+
+/* K for one q from a grid of tdx_xc_kernel_grid (ignored for TDX_XC_RPA,
+ * where fxg may be null).  Bitwise equal to tdx_kernel_matrix on the same
+ * states.  Asynchronous; fxg must stay alive until the stream reaches it. */
+int tdx_kernel_matrix_from_grid(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
+                                const int *gbasis, int n_g, int xc, const int dens_grid[3],
+                                const double *fxg, double *K, tdx_stream stream);
 
 /* chi_{00}(w) for every w: solve (1 - chi0(w) K) x = chi0(w) e_{i_g0} by LU
  * with partial pivoting and return x_{i_g0}.  chi0: device complex128

@@ -36,7 +36,7 @@ class TdxError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_2510_01875_amd.build` (no CPU fallback exists)")
+                          "`python paper_2510_01875_amd/build.py` (no CPU fallback exists)")
     return C.CDLL(LIB_PATH)
 
 
@@ -105,6 +105,11 @@ _chi0 = _sig("tdx_chi0", [C.c_void_p, C.POINTER(TransC), C.c_int64, C.c_void_p, 
                           C.c_void_p])
 _kmat = _sig("tdx_kernel_matrix", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3, C.c_void_p,
                                    C.c_int, C.c_int, C.c_int * 3, C.c_void_p, C.c_void_p])
+_xcgrid = _sig("tdx_xc_kernel_grid", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3, C.c_void_p,
+                                      C.c_void_p])
+_kmat_g = _sig("tdx_kernel_matrix_from_grid", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
+                                               C.c_void_p, C.c_int, C.c_int, C.c_int * 3,
+                                               C.c_void_p, C.c_void_p, C.c_void_p])
 _dyson = _sig("tdx_dyson", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
                             C.c_void_p, C.c_void_p])
 _dsf = _sig("tdx_dsf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_double,
@@ -163,6 +168,7 @@ EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_set_workspace_limit", "tdx_states_query", "tdx_build_states",
             "tdx_occupations", "tdx_response_basis", "tdx_transitions",
             "tdx_pair_density_bytes", "tdx_pair_density", "tdx_chi0", "tdx_kernel_matrix",
+            "tdx_xc_kernel_grid", "tdx_kernel_matrix_from_grid",
             "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
             "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
             "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_autotune_chi0", "tdx_tune_save",
@@ -423,6 +429,25 @@ def kernel_matrix(ctx: Context, st: States, qj, gbasis: torch.Tensor, xc: str,
     dg = (C.c_int * 3)(*dens_grid)
     check(_kmat(ctx.handle, C.byref(st.c), q, _ptr(gbasis), n_g, XC[xc], dg, _ptr(K),
                 _stream(stream)))
+    return K
+
+
+def xc_kernel_grid(ctx: Context, st: States, dens_grid, stream=None) -> torch.Tensor:
+    """f_xc(G) on the FFT grid for the states' current occupations (ALDA)."""
+    fx = torch.empty(tuple(dens_grid), dtype=torch.complex128, device=st.eps.device)
+    check(_xcgrid(ctx.handle, C.byref(st.c), (C.c_int * 3)(*dens_grid), _ptr(fx),
+                  _stream(stream)))
+    return fx
+
+
+def kernel_matrix_from_grid(ctx: Context, st: States, qj, gbasis: torch.Tensor, xc: str,
+                            dens_grid=(0, 0, 0), fxg=None, stream=None) -> torch.Tensor:
+    """K for one q from a grid of xc_kernel_grid (None for RPA)."""
+    n_g = gbasis.shape[0]
+    K = torch.empty((n_g, n_g), dtype=torch.complex128, device=gbasis.device)
+    check(_kmat_g(ctx.handle, C.byref(st.c), (C.c_int * 3)(*qj), _ptr(gbasis), n_g, XC[xc],
+                  (C.c_int * 3)(*dens_grid), _ptr(fxg) if fxg is not None else None, _ptr(K),
+                  _stream(stream)))
     return K
 
 

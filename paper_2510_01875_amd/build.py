@@ -1,6 +1,6 @@
 """Compile the tdx HIP library for gfx950 into paper_2510_01875_amd/libtdx.so.
 
-    python -m paper_2510_01875_amd.build        (or build() from Python)
+    python paper_2510_01875_amd/build.py   (by path: the package import needs the library)
 
 Every source under csrc/ is compiled by hipcc in parallel and linked with
 rocSOLVER/rocBLAS.  Packed FP32 instructions are disabled for all device code.

@@ -76,6 +76,7 @@ enum WsSlot {
   WS_ADJ = 8,       // adjoint: per-frequency vectors, state tables
   WS_ADJ2 = 9,      // adjoint: eigen-adjoint products
   WS_ADJ3 = 10,     // adjoint: reductions
+  WS_FXC = 11,      // f_xc(G) grid of the composed kernel-matrix call
 };
 
 size_t ws_total(const tdx_ctx *ctx);

@@ -518,13 +518,69 @@ using namespace tdx;
 
 extern "C" {
 
-int tdx_kernel_matrix(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const int *gbasis,
-                      int n_g, int xc, const int dens_grid[3], double *K, tdx_stream stream) {
+// Check the density grid against the states and the LDS of the density and
+// FFT kernels.
+static int check_grid(const tdx_states *st, const int dens_grid[3], int *Nr, size_t *lds) {
+  TDX_REQUIRE(dens_grid, TDX_ERR_INVALID_ARG, "ALDA needs a density grid");
+  for (int i = 0; i < 3; ++i)
+    TDX_REQUIRE(dens_grid[i] >= 2 * st->mmax[i] + 1 && dens_grid[i] <= kMaxSide, TDX_ERR_SHAPE,
+                "density grid side %d must lie in [%d, %d]", dens_grid[i], 2 * st->mmax[i] + 1,
+                kMaxSide);
+  *Nr = dens_grid[0] * dens_grid[1] * dens_grid[2];
+  *lds = sizeof(double2) * (*Nr + dens_grid[0] + dens_grid[1] + dens_grid[2]);
+  TDX_REQUIRE(*lds <= 160 * 1024, TDX_ERR_SHAPE, "density grid of %d points exceeds LDS", *Nr);
+  return TDX_OK;
+}
+
+int tdx_xc_kernel_grid(tdx_ctx *ctx, const tdx_states *st, const int dens_grid[3], double *fxg,
+                       tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && st && fxg, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_TRY(check_device(ctx));
+  int Nr;
+  size_t lds;
+  TDX_TRY(check_grid(st, dens_grid, &Nr, &lds));
+  hipStream_t s = as_stream(stream);
+  const int N0 = dens_grid[0], N1 = dens_grid[1], N2 = dens_grid[2];
+  void *w;
+  TDX_TRY(ws_get(ctx, WS_DENS, sizeof(double) * (size_t)st->n_k * Nr, &w));
+  double *dens = (double *)w;
+  TDX_HIP(hipFuncSetAttribute((const void *)k_density, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+  TDX_HIP(hipFuncSetAttribute((const void *)k_fxc_forward,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_density, dim3(st->n_k), dim3(256), lds, s, (const double2 *)st->coef,
+                     st->occ, st->nb, st->npw, st->miller, st->nb_max, st->npw_max, N0, N1, N2,
+                     dens);
+  TDX_HIP(hipGetLastError());
+  const double scale = 2.0 / (st->n_k * st->omega_cell);
+  hipLaunchKernelGGL(k_fxc_real, dim3((Nr + 255) / 256), dim3(256), 0, s, dens, st->n_k, Nr,
+                     scale, (double2 *)fxg);
+  TDX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_fxc_forward, dim3(1), dim3(256), lds, s, (double2 *)fxg, N0, N1, N2);
+  TDX_HIP(hipGetLastError());
+  TDX_HIP(hipStreamSynchronize(s));  // the density workspace may be reused after return
+  return TDX_OK;
+}
+
+int tdx_kernel_matrix_from_grid(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
+                                const int *gbasis, int n_g, int xc, const int dens_grid[3],
+                                const double *fxg, double *K, tdx_stream stream) {
   clear_error();
   TDX_REQUIRE(ctx && st && qj && gbasis && K, TDX_ERR_INVALID_ARG, "null argument");
   TDX_REQUIRE(xc == TDX_XC_RPA || xc == TDX_XC_ALDA, TDX_ERR_INVALID_ARG, "bad xc");
   TDX_REQUIRE(n_g > 0, TDX_ERR_SHAPE, "n_g must be positive");
   TDX_TRY(check_device(ctx));
+  int N0 = 1, N1 = 1, N2 = 1;
+  if (xc == TDX_XC_ALDA) {
+    TDX_REQUIRE(fxg, TDX_ERR_INVALID_ARG, "ALDA needs the kernel grid");
+    int Nr;
+    size_t lds;
+    TDX_TRY(check_grid(st, dens_grid, &Nr, &lds));
+    N0 = dens_grid[0];
+    N1 = dens_grid[1];
+    N2 = dens_grid[2];
+  }
   hipStream_t s = as_stream(stream);
   const double *B = st->bvec;
   const double3 b0 = make_double3(B[0], B[1], B[2]), b1 = make_double3(B[3], B[4], B[5]),
@@ -534,44 +590,30 @@ int tdx_kernel_matrix(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const
   const double3 q = make_double3(qr[0] * B[0] + qr[1] * B[3] + qr[2] * B[6],
                                  qr[0] * B[1] + qr[1] * B[4] + qr[2] * B[7],
                                  qr[0] * B[2] + qr[1] * B[5] + qr[2] * B[8]);
-  int N0 = 1, N1 = 1, N2 = 1;
-  double2 *fxg = nullptr;
-  if (xc == TDX_XC_ALDA) {
-    TDX_REQUIRE(dens_grid, TDX_ERR_INVALID_ARG, "ALDA needs a density grid");
-    N0 = dens_grid[0];
-    N1 = dens_grid[1];
-    N2 = dens_grid[2];
-    for (int i = 0; i < 3; ++i)
-      TDX_REQUIRE(dens_grid[i] >= 2 * st->mmax[i] + 1 && dens_grid[i] <= kMaxSide, TDX_ERR_SHAPE,
-                  "density grid side %d must lie in [%d, %d]", dens_grid[i],
-                  2 * st->mmax[i] + 1, kMaxSide);
-    const int Nr = N0 * N1 * N2;
-    const size_t lds = sizeof(double2) * (Nr + N0 + N1 + N2);
-    TDX_REQUIRE(lds <= 160 * 1024, TDX_ERR_SHAPE, "density grid of %d points exceeds LDS", Nr);
-    void *w;
-    const size_t dens_bytes = sizeof(double) * (size_t)st->n_k * Nr;
-    TDX_TRY(ws_get(ctx, WS_DENS, dens_bytes + sizeof(double2) * Nr, &w));
-    double *dens = (double *)w;
-    fxg = (double2 *)((char *)w + dens_bytes);
-    TDX_HIP(hipFuncSetAttribute((const void *)k_density, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-    TDX_HIP(hipFuncSetAttribute((const void *)k_fxc_forward,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_density, dim3(st->n_k), dim3(256), lds, s, (const double2 *)st->coef,
-                       st->occ, st->nb, st->npw, st->miller, st->nb_max, st->npw_max, N0, N1, N2,
-                       dens);
-    TDX_HIP(hipGetLastError());
-    const double scale = 2.0 / (st->n_k * st->omega_cell);
-    hipLaunchKernelGGL(k_fxc_real, dim3((Nr + 255) / 256), dim3(256), 0, s, dens, st->n_k, Nr,
-                       scale, fxg);
-    TDX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_fxc_forward, dim3(1), dim3(256), lds, s, fxg, N0, N1, N2);
-    TDX_HIP(hipGetLastError());
-  }
   hipLaunchKernelGGL(k_assemble_k, dim3((n_g + 63) / 64, n_g), dim3(64), 0, s, gbasis, n_g, q, b0,
-                     b1, b2, fxg, N0, N1, N2, xc == TDX_XC_ALDA ? 1 : 0, (double2 *)K);
+                     b1, b2, xc == TDX_XC_ALDA ? (const double2 *)fxg : nullptr, N0, N1, N2,
+                     xc == TDX_XC_ALDA ? 1 : 0, (double2 *)K);
   TDX_HIP(hipGetLastError());
-  if (xc == TDX_XC_ALDA) TDX_HIP(hipStreamSynchronize(s));
+  return TDX_OK;
+}
+
+int tdx_kernel_matrix(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const int *gbasis,
+                      int n_g, int xc, const int dens_grid[3], double *K, tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && st && qj && gbasis && K, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(xc == TDX_XC_RPA || xc == TDX_XC_ALDA, TDX_ERR_INVALID_ARG, "bad xc");
+  if (xc == TDX_XC_RPA)
+    return tdx_kernel_matrix_from_grid(ctx, st, qj, gbasis, n_g, xc, dens_grid, nullptr, K,
+                                       stream);
+  int Nr;
+  size_t lds;
+  TDX_TRY(check_grid(st, dens_grid, &Nr, &lds));
+  void *w;
+  TDX_TRY(ws_get(ctx, WS_FXC, sizeof(double2) * (size_t)Nr, &w));
+  TDX_TRY(tdx_xc_kernel_grid(ctx, st, dens_grid, (double *)w, stream));
+  TDX_TRY(tdx_kernel_matrix_from_grid(ctx, st, qj, gbasis, n_g, xc, dens_grid, (const double *)w,
+                                      K, stream));
+  TDX_HIP(hipStreamSynchronize(as_stream(stream)));
   return TDX_OK;
 }
 

@@ -194,6 +194,41 @@ def test_feg_c1_full_size_against_lindhard(tdx, ctx):
     assert np.max(np.abs(g.F.cpu().numpy() - F) / F) < 1e-10
 
 
+def test_kernel_from_shared_xc_grid(tdx, ctx):
+    """K assembled from one f_xc(G) grid per temperature equals the composed
+    call bitwise and the oracle's K; fcc_small has a different temperature
+    for each q, so the grid must follow the occupations."""
+    _say("kernel from shared xc grid")
+    import torch
+    w, ost, ores = oracle_run("fcc_small")
+    st = tdx.build_states(ctx, w, w.temperatures[0])
+    grids = []
+    for iq, r in enumerate(ores):
+        T = w.temperatures[iq]
+        if st.temperature != T:
+            tdx.occupations(ctx, st, T, w.n_electrons, w.f_trunc)
+        basis, _ = tdx.response_basis(w.cell, w.kgrid, w.qs[iq], w.ecut_chi[iq])
+        gb = torch.from_numpy(basis).cuda()
+        fx = tdx.xc_kernel_grid(ctx, st, w.dens_grid)
+        grids.append(fx)
+        for qj in w.qs:   # one grid serves every q at this temperature
+            b2, _ = tdx.response_basis(w.cell, w.kgrid, qj, w.ecut_chi[iq])
+            g2 = torch.from_numpy(b2).cuda()
+            assert torch.equal(tdx.kernel_matrix_from_grid(ctx, st, qj, g2, w.xc, w.dens_grid, fx),
+                               tdx.kernel_matrix(ctx, st, qj, g2, w.xc, w.dens_grid))
+        K = tdx.kernel_matrix_from_grid(ctx, st, w.qs[iq], gb, w.xc, w.dens_grid, fx).cpu().numpy()
+        p = _perm(basis, r.basis)
+        assert np.max(np.abs(K - r.K[p][:, p])) < 1e-12 * np.max(np.abs(r.K))
+    assert not torch.equal(grids[0], grids[1])
+    # RPA needs no grid
+    wr = workloads.h_tiny()
+    sr = tdx.build_states(ctx, wr)
+    basis, _ = tdx.response_basis(wr.cell, wr.kgrid, wr.qs[0], wr.ecut_chi[0])
+    gb = torch.from_numpy(basis).cuda()
+    assert torch.equal(tdx.kernel_matrix_from_grid(ctx, sr, wr.qs[0], gb, "rpa"),
+                       tdx.kernel_matrix(ctx, sr, wr.qs[0], gb, "rpa"))
+
+
 def test_chi0_is_bitwise_reproducible(tdx, ctx):
     _say("determinism")
     import torch
