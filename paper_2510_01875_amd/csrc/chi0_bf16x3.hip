@@ -24,9 +24,11 @@
 // chunk of CHUNK transitions the fragments and rho rows are copied into LDS
 // with no register staging and no arithmetic; only the weights pass through
 // registers.  The next chunk's transfers are in flight while the current
-// chunk runs (two LDS buffers).  The number of 16-column blocks of a tile is
+// chunk runs (two or three LDS buffers); they are issued one per 16-column
+// block of the current chunk, since a burst of them stalls the MFMAs of
+// every wave on the CU.  The number of 16-column blocks of a tile is
 // a compile-time constant (the ragged last tile of a row runs its own
-// instance), so the step body is one basic block.  Sums run in FP32 over 256
+// instance), so the step body is one basic block.  Sums run in FP32 over 1024
 // chunks and are folded into the tile's FP64 partial; slices are reduced in
 // FP64 in a fixed order, so results do not depend on which workgroup ran
 // which tile.
@@ -145,8 +147,12 @@ struct DmaPlan {
   // the chunk `off` bytes (8 CHUNK ld per chunk) past the first one
   __device__ inline void issue(size_t off, unsigned int *buf) const {
 #pragma unroll
-    for (int i = 0; i < kSlots; ++i)
-      if (i < kSlots - 1 || (kT % C::kWaves == 0) || last_ok) dma16(src[i] + off, buf + dst[i]);
+    for (int i = 0; i < kSlots; ++i) issue_slot(i, off, buf);
+  }
+  // one slot of it (i a compile-time constant after unrolling)
+  __device__ inline void issue_slot(int i, size_t off, unsigned int *buf) const {
+    if (i < kSlots && (i < kSlots - 1 || (kT % C::kWaves == 0) || last_ok))
+      dma16(src[i] + off, buf + dst[i]);
   }
 };
 
@@ -201,11 +207,14 @@ __device__ __attribute__((always_inline)) void chi0_tile(
     for (long long tc = rs; tc < re; tc += CHUNK) {
       const long long nx = tc + (DEPTH - 1) * CHUNK;
       const bool more = nx < t_hi;
-      if (more) {
-        // weights first: a partial wait below leaves the transfers in flight
-        load_weights<C>(pw, delta, df, nx, t_max, tid);
-        dma.issue((size_t)((nx - t_lo) / CHUNK) * chunk_bytes, lds + ahead * C::kBufWords);
-      }
+      // weights first: a partial wait below leaves the transfers in flight
+      if (more) load_weights<C>(pw, delta, df, nx, t_max, tid);
+      // the transfers of chunk nx go out one slot per column block of the
+      // first K-steps rather than all at once: a burst of them at the top of
+      // the chunk stalls the MFMAs of every wave of the CU
+      const size_t nx_off = (size_t)((nx - t_lo) / CHUNK) * chunk_bytes;
+      unsigned int *nx_buf = lds + ahead * C::kBufWords;
+      static_assert(DmaPlan<C, NSUB>::kSlots <= C::kSteps * NSUB, "a slot per column block");
       const unsigned int *buf = lds + cur * C::kBufWords;
       const u32x4 *bfr = (const u32x4 *)buf;
       const float2 *rq = (const float2 *)(buf + C::kBWords);
@@ -249,6 +258,7 @@ __device__ __attribute__((always_inline)) void chi0_tile(
             bh[(b + 1) & 1] = as_bf16x8(bp[0]);
             bl[(b + 1) & 1] = as_bf16x8(bp[64]);
           }
+          if (more) dma.issue_slot(s * NSUB + b, nx_off, nx_buf);
 #pragma unroll
           for (int i = 0; i < WPW; ++i) {
             f32x4 cr = ar[i][b], ci = ai[i][b];
@@ -404,18 +414,19 @@ __device__ inline void step_pipe(f32x4 (&ar)[WPW][NSUB], f32x4 (&ai)[WPW][NSUB],
   for (int e = NSUB; e < 4 * WPW; ++e) element(e);
 }
 
-// LDS DMA of the pipelined tile.  Transfers are dealt to the waves per
-// kind: B transfer x = 4 slot + wave (slots 0 .. kSB-1), rho transfer
-// d = 4 slot' + wave (the kSR slots after them), so every slot's kind is
+// LDS DMA of the pipelined tile.  Transfers are dealt to the NW waves per
+// kind: B transfer x = NW slot + wave (slots 0 .. kSB-1), rho transfer
+// d = NW slot' + wave (the kSR slots after them), so every slot's kind is
 // fixed at compile time; a slot is empty for a wave only when its kind's
-// count is not a multiple of four.
+// count is not a multiple of NW.
 template <class C, int NSUB>
 struct DmaPlanPipe {
+  static constexpr int kW = C::kWaves;
   static constexpr int kB = C::kSteps * NSUB * 2, kR = C::kChunk / 8;
-  static constexpr int kSB = (kB + 3) / 4, kSR = (kR + 3) / 4;
+  static constexpr int kSB = (kB + kW - 1) / kW, kSR = (kR + kW - 1) / kW;
   // B and rho transfers that every wave issues per chunk (a lower bound for
   // the waves that also fill a last, partial slot)
-  static constexpr int kIssuedB = kB / 4, kIssuedR = kR / 4;
+  static constexpr int kIssuedB = kB / kW, kIssuedR = kR / kW;
   const unsigned char *base_b, *base_r;  // the tile's first chunk (uniform)
   unsigned off[kSB + kSR];               // the lane's byte offset per slot
   int dst[kSB + kSR];                    // word offset in a B buffer or a rho slot
@@ -430,7 +441,7 @@ struct DmaPlanPipe {
     const unsigned lane_r = (unsigned)(((lane >> 5) + 4 * ((lane >> 3) & 3)) * ld + 2 * (lane & 7)) * 8u;
 #pragma unroll
     for (int i = 0; i < kSB; ++i) {
-      const int x = std::min(4 * i + wave, kB - 1);
+      const int x = std::min(kW * i + wave, kB - 1);
       const int m = x >> 1, comp = x & 1;
       const int st = m / NSUB, b = m % NSUB;
       off[i] = (unsigned)(((4 * st) * 2 + comp) * ld + 16 * b) * 16u + lane_b;
@@ -438,12 +449,12 @@ struct DmaPlanPipe {
     }
 #pragma unroll
     for (int i = 0; i < kSR; ++i) {
-      const int d = std::min(4 * i + wave, kR - 1);
+      const int d = std::min(kW * i + wave, kR - 1);
       off[kSB + i] = (unsigned)((16 * (d >> 1) + 2 * (d & 1)) * ld) * 8u + lane_r;
       dst[kSB + i] = d * 256;
     }
-    lastb_ok = 4 * (kSB - 1) + wave < kB;
-    lastr_ok = 4 * (kSR - 1) + wave < kR;
+    lastb_ok = kW * (kSB - 1) + wave < kB;
+    lastr_ok = kW * (kSR - 1) + wave < kR;
   }
 
   // B / rho of the chunk `pos` bytes past the tile's first one into buf
@@ -451,31 +462,31 @@ struct DmaPlanPipe {
     const unsigned char *b = base_b + pos;
 #pragma unroll
     for (int i = 0; i < kSB; ++i)
-      if (i < kSB - 1 || kB % 4 == 0 || lastb_ok) dma16(b + off[i], buf + dst[i]);
+      if (i < kSB - 1 || kB % kW == 0 || lastb_ok) dma16(b + off[i], buf + dst[i]);
   }
   __device__ inline void issue_r(size_t pos, unsigned int *buf) const {
     const unsigned char *r = base_r + pos;
 #pragma unroll
     for (int i = 0; i < kSR; ++i)
-      if (i < kSR - 1 || kR % 4 == 0 || lastr_ok) dma16(r + off[kSB + i], buf + dst[kSB + i]);
+      if (i < kSR - 1 || kR % kW == 0 || lastr_ok) dma16(r + off[kSB + i], buf + dst[kSB + i]);
   }
 };
 
-template <int WPW, int SUB, int CHUNK>
+template <int WPW, int SUB, int CHUNK, int NW>
 struct PipeLds {
-  typedef Cfg<WPW, SUB, CHUNK> C;
+  typedef Cfg<WPW, SUB, CHUNK, NW> C;
   static constexpr int kRW = C::kRhoWords + C::kWtWords;  // one rho/weight slot
   static constexpr int kBBufs = 3, kRWSlots = 4;
   static constexpr size_t kBytes = (size_t)(kBBufs * C::kBWords + kRWSlots * kRW) * 4;
 };
 
-template <int WPW, int SUB, int CHUNK, int NSUB>
+template <int WPW, int SUB, int CHUNK, int NSUB, int NW>
 __device__ __attribute__((always_inline)) void chi0_tile_pipe(
     unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
     int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
-  typedef Cfg<WPW, SUB, CHUNK> C;
-  typedef PipeLds<WPW, SUB, CHUNK> L;
+  typedef Cfg<WPW, SUB, CHUNK, NW> C;
+  typedef PipeLds<WPW, SUB, CHUNK, NW> L;
   static_assert(C::kSteps % 2 == 0, "the A register sets alternate per K-step");
   unsigned int *bring = lds, *rwring = lds + L::kBBufs * C::kBWords;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -565,20 +576,20 @@ __device__ __attribute__((always_inline)) void chi0_tile_pipe(
   }
 }
 
-template <int WPW, int SUB, int CHUNK, int NSUB = SUB>
+template <int WPW, int SUB, int CHUNK, int NW, int NSUB = SUB>
 __device__ __attribute__((always_inline)) void chi0_tile_pipe_n(
     int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
     int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
   if constexpr (NSUB > 1) {
     if (nsub < NSUB) {
-      chi0_tile_pipe_n<WPW, SUB, CHUNK, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo,
+      chi0_tile_pipe_n<WPW, SUB, CHUNK, NW, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo,
                                                    t_hi, omega, n_w, eta, paired, n_g, w0, row0, col0,
                                                    part);
       return;
     }
   }
-  chi0_tile_pipe<WPW, SUB, CHUNK, NSUB>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
+  chi0_tile_pipe<WPW, SUB, CHUNK, NSUB, NW>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
                                         n_w, eta, paired, n_g, w0, row0, col0, part);
 }
 
@@ -589,9 +600,8 @@ __device__ __attribute__((always_inline)) void run_tile(
     int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
     int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
-  static_assert(NW == 4 || !PIPE, "8-wave workgroups: plain tile only");
   if constexpr (PIPE)
-    chi0_tile_pipe_n<WPW, SUB, CHUNK>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
+    chi0_tile_pipe_n<WPW, SUB, CHUNK, NW>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
                                       n_w, eta, paired, n_g, w0, row0, col0, part);
   else
     chi0_tile_n<WPW, SUB, CHUNK, DEPTH, NW>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi,
@@ -655,7 +665,7 @@ __global__ void __launch_bounds__(64 * NW, OCC)
 template <int W, int S, int K, bool PIPE, int DEPTH, int NW>
 constexpr size_t variant_lds() {
   if constexpr (PIPE)
-    return PipeLds<W, S, K>::kBytes;
+    return PipeLds<W, S, K, NW>::kBytes;
   else
     return (size_t)DEPTH * Cfg<W, S, K, NW>::kBufWords * 4;
 }
@@ -677,7 +687,8 @@ const Variant kVariants[] = {TDX_V(4, 4, 32, 2, false, 2, 4), TDX_V(2, 8, 16, 2,
                              TDX_V(4, 2, 32, 2, false, 2, 4), TDX_V(2, 4, 32, 2, false, 2, 4),
                              TDX_V(2, 9, 16, 2, false, 2, 4), TDX_V(2, 8, 32, 2, false, 2, 4),
                              TDX_V(2, 9, 32, 1, true, 0, 4),  TDX_V(2, 9, 16, 2, false, 3, 4),
-                             TDX_V(2, 9, 32, 1, false, 2, 8)};
+                             TDX_V(2, 9, 32, 1, false, 2, 8), TDX_V(2, 9, 32, 1, false, 3, 8),
+                             TDX_V(1, 9, 32, 1, true, 0, 12)};
 #undef TDX_V
 
 }  // namespace

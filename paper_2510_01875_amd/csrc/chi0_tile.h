@@ -15,7 +15,12 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kFoldChunks = 256;  // chunks summed in FP32 between folds
+// Chunks summed in FP32 between folds.  Every fold is a read-modify-write of
+// the tile's FP64 partial, and the tiles running side by side fold at about
+// the same time, so a fold costs a burst of HBM traffic; 1024 chunks keep
+// that near 1 % of the kernel's time (it was 5 % at 256) while an FP32 run
+// still adds at most 2^15 transitions.
+constexpr int kFoldChunks = 1024;
 
 // LDS index (float2 units) of the weight of transition tl of a chunk and
 // frequency w of the workgroup: the four groups of four transitions that one
