@@ -2,8 +2,10 @@
 //
 // With G2 = G1 + G + G_s in the basis of k' (k + q = k' + G_s):
 //   rho_t(G) = sum_{G2 in basis(k')} conj(c_nk(G2 - G - G_s)) c_mk'(G2).
-// One wavefront per (k, n) row of the transition list computes the row as a
-// complex matrix product on the FP64 MFMA (details at the kernel).
+// One wavefront per group of transitions sharing one side computes the group
+// as a complex matrix product on the FP64 MFMA: (k, n) rows of the list, and
+// for rows too short to fill the MFMA, (k, m) columns (details at the
+// kernels).
 // Accumulation is FP64; the store converts to the requested layout.
 
 #include <cmath>
@@ -80,47 +82,98 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPdGT = 9;  // 16-wide G tiles held in accumulators at once
 
-// One wavefront per (k, n) row of the transition list.  For the row's
-// transitions m (tiles of 16) and the response vectors G (tiles of 16,
-// kPdGT at a time) the pair densities are the complex matrix product
-//   rho[m][G] = sum_{G2 in basis(k')} c_mk'(G2) U[G2][G],
-//   U[G2][G] = conj(c_nk)(G2 - G - G_s)  (0 if outside the basis of k),
-// on the FP64 16x16x4 MFMA, four real products per K-step of four G2.  Lane
-// l feeds A = c_{m(l%16)}(G2 = 4 s + l/16) and B = U[4 s + l/16][16 gt + l%16];
-// the B operand is gathered per lane through the Miller-index lookup box of
-// k, which sits in LDS next to conj(c_nk).  The output element j of lane l is
-// m row l/16 + 4 j, G column l%16.
-template <int FMT>
+// Rows (k, n) with fewer transitions than this run in column groups (k, m)
+// instead: a (k, n) row of an empty band n pairs it with the few occupied
+// bands m (five to seven on the crystal workload), which would fill under
+// half of the 16 MFMA rows, while the column (k, m) of an occupied band m
+// collects the empty bands of all those rows.
+constexpr int kShortRow = 16;
+
+// Column groups: for every k, the transitions of its short rows grouped by m,
+// listed in perm[colbeg[k][m] .. colend[k][m]); the groups of k occupy the
+// start of k's own range of the list.  The order inside a group does not
+// change any result (every transition is one MFMA row of its own).
+__global__ void k_cols(const long long *koff, const int *tn, const int *tm, int nb_max,
+                       long long n_trans, const long long *rowbeg, const long long *rowend,
+                       long long *colbeg, long long *colend, long long *perm) {
+  extern __shared__ int cnt[];  // [nb_max] counts, then [nb_max] cursors
+  int *cur = cnt + nb_max;
+  const int k = blockIdx.x;
+  const long long t0 = koff[k], t1 = koff[k + 1] < n_trans ? koff[k + 1] : n_trans;
+  for (int i = threadIdx.x; i < 2 * nb_max; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  auto is_short = [&](long long t) {
+    const size_t r = (size_t)k * nb_max + tn[t];
+    return rowend[r] - rowbeg[r] < kShortRow;
+  };
+  for (long long t = t0 + threadIdx.x; t < t1; t += blockDim.x)
+    if (is_short(t)) atomicAdd(&cnt[tm[t]], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int m = 0; m < nb_max; ++m) {
+      colbeg[(size_t)k * nb_max + m] = t0 + acc;
+      colend[(size_t)k * nb_max + m] = t0 + acc + cnt[m];
+      cur[m] = acc;
+      acc += cnt[m];
+    }
+  }
+  __syncthreads();
+  for (long long t = t0 + threadIdx.x; t < t1; t += blockDim.x)
+    if (is_short(t)) perm[t0 + atomicAdd(&cur[tm[t]], 1)] = t;
+}
+
+// One wavefront per group of transitions that share one side: a row group
+// (k, n) (COL false) or a column group (k, m) (COL true).  Row group: with
+// G2 in the basis of k',
+//   rho[m][G] = sum_{G2} c_mk'(G2) U[G2][G],   U[G2][G] = conj(c_nk)(G2 - G - G_s);
+// column group: with G1 = G2 - G - G_s in the basis of k,
+//   rho[n][G] = sum_{G1} conj(c_nk)(G1) V[G1][G],   V[G1][G] = c_mk'(G1 + G + G_s).
+// Both are complex matrix products on the FP64 16x16x4 MFMA, four real
+// products per K-step of four plane waves: the A rows are the coefficients of
+// the group's 16 transitions, the B operand is gathered per lane through the
+// Miller-index lookup box of the fixed side, which sits in LDS next to that
+// side's coefficients (zero outside its basis).  The output element j of
+// lane l is transition row l/16 + 4 j, G column l%16.
+template <int FMT, bool COL>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     k_pair_density(const double2 *coef, const int *miller, const int *npw, int nb_max,
-                   int npw_max, const int *tm, const long long *rowbeg, const long long *rowend,
-                   const int *kpmap, const int *gsmap, const int *gbasis, int n_g, int ld,
-                   const int *lut, long box, int M0, int M1, int M2, void *P,
-                   long long n_trans) {
-  extern __shared__ double2 ckn[];                 // [npw_max] conj(c_nk)
-  int *lutk = (int *)(ckn + npw_max);              // [box] lookup of k
-  const int n = blockIdx.x, k = blockIdx.y;
-  const long long t0 = rowbeg[(size_t)k * nb_max + n], t1 = rowend[(size_t)k * nb_max + n];
-  if (t1 <= t0) return;
+                   int npw_max, const int *tn, const int *tm, const long long *gbeg,
+                   const long long *gend, const long long *perm, const int *kpmap,
+                   const int *gsmap, const int *gbasis, int n_g, int ld, const int *lut, long box,
+                   int M0, int M1, int M2, void *P, long long n_trans) {
+  extern __shared__ double2 cfix[];             // [npw_max] the fixed side
+  int *lutf = (int *)(cfix + npw_max);          // [box] lookup of its k-point
+  const int band = blockIdx.x, k = blockIdx.y;
+  const size_t grp = (size_t)k * nb_max + band;
+  const long long p0 = gbeg[grp], p1 = gend[grp];
+  if (p1 <= p0) return;
+  if (!COL && p1 - p0 < kShortRow) return;  // these run in column groups
   const int lane = threadIdx.x;
   const int kp = kpmap[k];
+  const int kf = COL ? kp : k;  // k-point of the fixed side (and of the lookup)
+  const int ka = COL ? k : kp;  // k-point of the A rows (and of the K index)
   const int gs0 = gsmap[3 * k], gs1 = gsmap[3 * k + 1], gs2 = gsmap[3 * k + 2];
-  const int npk = npw[k], npj = npw[kp];
-  for (int i = lane; i < npk; i += 64) {
-    const double2 c = coef[((size_t)k * nb_max + n) * npw_max + i];
-    ckn[i] = make_double2(c.x, -c.y);
+  const int npf = npw[kf], npa = npw[ka];
+  const double2 *cf = coef + ((size_t)kf * nb_max + band) * npw_max;
+  for (int i = lane; i < npf; i += 64) {
+    const double2 c = cf[i];
+    cfix[i] = COL ? c : make_double2(c.x, -c.y);
   }
-  for (long i = lane; i < box; i += 64) lutk[i] = lut[(size_t)k * box + i];
+  for (long i = lane; i < box; i += 64) lutf[i] = lut[(size_t)kf * box + i];
   __syncthreads();
   const int W1 = 2 * M1 + 1, W2 = 2 * M2 + 1;
-  const int *mj = miller + (size_t)kp * npw_max * 3;
-  const double2 *cj = coef + (size_t)kp * nb_max * npw_max;
+  const int *ma = miller + (size_t)ka * npw_max * 3;
+  const double2 *ca = coef + (size_t)ka * nb_max * npw_max;
+  const int *ta = COL ? tn : tm;  // band of the A row of a transition
   const int r = lane & 15, kq = lane >> 4;
   const int n_gt = ld / 16;
-  for (long long tm0 = t0; tm0 < t1; tm0 += 16) {
-    // this lane's A row: transition tm0 + r (zero past the row)
-    const bool row_ok = tm0 + r < t1;
-    const double2 *crow = cj + (size_t)(row_ok ? tm[tm0 + r] : 0) * npw_max;
+  // transition of group slot p
+  auto trans = [&](long long p) { return COL ? perm[p] : p; };
+  for (long long q0 = p0; q0 < p1; q0 += 16) {
+    // this lane's A row: the transition of slot q0 + r (zero past the group)
+    const bool row_ok = q0 + r < p1;
+    const double2 *crow = ca + (size_t)(row_ok ? ta[trans(q0 + r)] : 0) * npw_max;
     // NQ tiles of 16 G starting at tile gt0 (NQ a compile-time count, so the
     // K-step below is straight-line code)
     auto tiles = [&](int gt0, auto nq_c) {
@@ -138,40 +191,44 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
                 ((unsigned)(gbasis[3 * g + 2] + gs2 + 512) << 20);
       }
       // A operand one K-step ahead (a global load whose latency the current
-      // step's MFMAs cover)
+      // step's MFMAs cover); conjugated for a column group
       auto load_a = [&](int j0) {
         const int j = j0 + kq;
-        return j < npj && row_ok ? crow[j] : make_double2(0.0, 0.0);
+        const double2 c = j < npa && row_ok ? crow[j] : make_double2(0.0, 0.0);
+        return COL ? make_double2(c.x, -c.y) : c;
       };
       double2 a_next = load_a(0);
-      for (int j0 = 0; j0 < npj; j0 += 4) {
+      for (int j0 = 0; j0 < npa; j0 += 4) {
         const int j = j0 + kq;
         const double2 a = a_next;
         a_next = load_a(j0 + 4);
-        const int jc = std::min(j, npj - 1);
-        const int m0 = mj[3 * jc] + M0, m1 = mj[3 * jc + 1] + M1, m2 = mj[3 * jc + 2] + M2;
+        const int jc = std::min(j, npa - 1);
+        const int m0 = ma[3 * jc] + M0, m1 = ma[3 * jc + 1] + M1, m2 = ma[3 * jc + 2] + M2;
         // B operands of every tile: all lookups first, then all values, with
-        // no branches (out-of-range entries read slot 0 and are zeroed)
+        // no branches (out-of-range entries read slot 0 and are zeroed); the
+        // lookup index is G2 - G - G_s (row group) or G1 + G + G_s (column)
         int li[NQ];
         bool ok[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const int g = (gt0 + q) * 16 + r;
-          const int x0 = m0 + 512 - (int)(gp[q] & 1023u);
-          const int x1 = m1 + 512 - (int)((gp[q] >> 10) & 1023u);
-          const int x2 = m2 + 512 - (int)(gp[q] >> 20);
-          ok[q] = j < npj && g < n_g && x0 >= 0 && x0 <= 2 * M0 && x1 >= 0 && x1 < W1 &&
+          const int f0 = (int)(gp[q] & 1023u) - 512, f1 = (int)((gp[q] >> 10) & 1023u) - 512,
+                    f2 = (int)(gp[q] >> 20) - 512;
+          const int x0 = COL ? m0 + f0 : m0 - f0;
+          const int x1 = COL ? m1 + f1 : m1 - f1;
+          const int x2 = COL ? m2 + f2 : m2 - f2;
+          ok[q] = j < npa && g < n_g && x0 >= 0 && x0 <= 2 * M0 && x1 >= 0 && x1 < W1 &&
                   x2 >= 0 && x2 < W2;
           li[q] = ok[q] ? ((x0 * W1 + x1) * W2 + x2) : 0;
         }
         int idx[NQ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) idx[q] = lutk[li[q]];
+        for (int q = 0; q < NQ; ++q) idx[q] = lutf[li[q]];
         double2 u[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
           const bool hit = ok[q] && idx[q] >= 0;
-          const double2 v = ckn[hit ? idx[q] : 0];
+          const double2 v = cfix[hit ? idx[q] : 0];
           u[q] = hit ? v : make_double2(0.0, 0.0);
         }
         // per accumulator the same order of products as one tile at a time
@@ -190,8 +247,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
       for (int q = 0; q < NQ; ++q) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const long long t = tm0 + kq + 4 * e;
-          if (t < t1) store<FMT>(P, t, (gt0 + q) * 16 + r, ld, n_trans, acr[q][e], aci[q][e]);
+          const long long p = q0 + kq + 4 * e;
+          if (p < p1)
+            store<FMT>(P, trans(p), (gt0 + q) * 16 + r, ld, n_trans, acr[q][e], aci[q][e]);
         }
       }
     };
@@ -252,11 +310,14 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
   void *w1, *w2;
   const size_t lut_bytes = (sizeof(int) * (size_t)nk * box + 255) / 256 * 256;
   const size_t row_bytes = sizeof(long long) * 2 * (size_t)nk * nb_max;
-  TDX_TRY(ws_get(ctx, WS_DENS, lut_bytes + row_bytes, &w1));
+  TDX_TRY(ws_get(ctx, WS_DENS,
+                 lut_bytes + 2 * row_bytes + sizeof(long long) * (size_t)n_trans, &w1));
   TDX_TRY(ws_get(ctx, WS_MISC, sizeof(int) * 4 * (size_t)nk, &w2));
   int *d_lut = (int *)w1;
   long long *d_rb = (long long *)((char *)w1 + lut_bytes);
   long long *d_re = d_rb + (size_t)nk * nb_max;
+  long long *d_cb = d_re + (size_t)nk * nb_max, *d_ce = d_cb + (size_t)nk * nb_max;
+  long long *d_perm = d_ce + (size_t)nk * nb_max;
   int *d_kp = (int *)w2, *d_gs = d_kp + nk;
   TDX_HIP(hipMemcpyAsync(d_kp, kp.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
   TDX_HIP(hipMemcpyAsync(d_gs, gs.data(), sizeof(int) * 3 * nk, hipMemcpyHostToDevice, s));
@@ -268,15 +329,25 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
   hipLaunchKernelGGL(k_rows, dim3(nk), dim3(256), 0, s, (const long long *)tl->k_offsets, tl->n,
                      nb_max, (long long)n_trans, d_rb, d_re);
   TDX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_cols, dim3(nk), dim3(256), sizeof(int) * 2 * nb_max, s,
+                     (const long long *)tl->k_offsets, tl->n, tl->m, nb_max, (long long)n_trans,
+                     d_rb, d_re, d_cb, d_ce, d_perm);
+  TDX_HIP(hipGetLastError());
   const int ld = ld_of(n_g);
   const size_t lds = sizeof(double2) * st->npw_max + sizeof(int) * (size_t)box;
   dim3 grid(nb_max, nk);
-#define TDX_PD(F)                                                                              \
-  TDX_HIP(hipFuncSetAttribute((const void *)k_pair_density<F>,                                 \
+  // long rows, then the column groups of the short ones (disjoint outputs)
+#define TDX_PD1(F, COL, B, E)                                                                  \
+  TDX_HIP(hipFuncSetAttribute((const void *)k_pair_density<F, COL>,                            \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));          \
-  hipLaunchKernelGGL(k_pair_density<F>, grid, dim3(64), lds, s, (const double2 *)st->coef,     \
-                     st->miller, st->npw, nb_max, st->npw_max, tl->m, d_rb, d_re, d_kp, d_gs,  \
-                     gbasis, n_g, ld, d_lut, box, M0, M1, M2, P, (long long)n_trans)
+  hipLaunchKernelGGL((k_pair_density<F, COL>), grid, dim3(64), lds, s,                         \
+                     (const double2 *)st->coef, st->miller, st->npw, nb_max, st->npw_max,      \
+                     tl->n, tl->m, B, E, d_perm, d_kp, d_gs, gbasis, n_g, ld, d_lut, box, M0,  \
+                     M1, M2, P, (long long)n_trans);                                           \
+  TDX_HIP(hipGetLastError())
+#define TDX_PD(F)                     \
+  TDX_PD1(F, false, d_rb, d_re);      \
+  TDX_PD1(F, true, d_cb, d_ce)
   if (prec == TDX_PREC_FP64) {
     TDX_PD(TDX_PREC_FP64);
   } else if (prec == TDX_PREC_FP32) {
@@ -288,7 +359,7 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
     TDX_PD(TDX_PREC_BF16X3);
   }
 #undef TDX_PD
-  TDX_HIP(hipGetLastError());
+#undef TDX_PD1
   return TDX_OK;
 }
 
