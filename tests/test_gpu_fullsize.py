@@ -1,7 +1,8 @@
-"""The benchmark workload (fcc_c2, q0) at full size, in the launch
-configuration bench.py times (time-reversal paired lists, the tuned split-BF16
-tile): sampled outputs the oracle can compute one at a time, and properties
-that hold at any size.
+"""Full-size workloads on the GPU, in the launch configuration bench.py times
+(time-reversal paired lists, the tuned split-BF16 tile): sampled outputs the
+oracle can compute one at a time, and properties that hold at any size.
+
+fcc_c2 (the benchmark workload, q0):
 
 - eigenvalues at sampled k-points against the oracle's dense eigensolve;
 - pair densities of sampled transitions (non-degenerate bands, so each row is
@@ -10,6 +11,13 @@ that hold at any size.
   (the pairing identity, 1e-12), split-BF16 against FP64 (1e-4), and the
   anti-Hermitian part of chi0(w > 0) negative semidefinite;
 - S(q, w) through Dyson: split-BF16 against FP64 (1e-4).
+
+h16_c3 (16 protons, 64 k, about 6270 plane waves and 864 bands per k, 304 G,
+1.6e7 paired transitions): the eigenpairs of sampled bands by their residual
+against the oracle's Hamiltonian, pair densities of sampled transitions (from
+long rows, and from short rows, which run as column groups, where k = 0 has
+any) against the oracle's direct sum on the same coefficients, and split-BF16 against FP64 chi0 and S on 20
+frequencies.
 """
 import os
 import sys
@@ -154,4 +162,127 @@ def test_fcc_c2_q0_full_size(tdx):
     e_s = np.max(np.abs(S16 - S64)) / np.max(np.abs(S64))
     _say(f"  S split-BF16 vs FP64 {e_s:.1e}")
     assert e_s < 1e-4
+    ctx.close()
+
+
+def _dense_h(w, kred, millers, omega):
+    """The oracle's H(k) on a basis of about 6000 plane waves: V(G - G') is
+    evaluated once per distinct difference and indexed (the same matrix as
+    oracle.states.hamiltonian, without its 6000^2 x 3 difference array)."""
+    from oracle.lattice import reciprocal
+    from oracle.states import potential_fourier
+    B = reciprocal(np.asarray(w.cell, dtype=np.float64))
+    span = int(np.abs(millers).max())
+    side = 4 * span + 1
+    r = np.arange(-2 * span, 2 * span + 1)
+    d = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+    vtab = potential_fourier(w.potential, B, omega, d)
+    key = (millers + 2 * span).astype(np.int64)
+    key = (key[:, 0] * side + key[:, 1]) * side + key[:, 2]
+    H = vtab[key[:, None] - key[None, :] + ((2 * span * side + 2 * span) * side + 2 * span)]
+    p = (np.asarray(kred) + millers) @ B
+    H[np.diag_indices_from(H)] += 0.5 * np.einsum("ij,ij->i", p, p)
+    return H
+
+
+def test_h16_c3_full_size(tdx):
+    import torch
+    from oracle.lattice import kq_map, mp_kpoints
+    from oracle.response import Transitions, pair_densities
+    from oracle.states import States
+
+    w = workloads.h16_c3()
+    ctx = tdx.Context(0)
+    cache = os.path.join(ROOT, "paper_2510_01875_amd", "tune_gfx950.json")
+    if os.path.exists(cache):
+        tdx.tune_load(ctx, cache)
+    _say("h16_c3 full size: states")
+    st = tdx.build_states(ctx, w, w.temperatures[0])
+    qj = tuple(w.qs[0])
+    kred, _ = mp_kpoints(w.kgrid)
+    kp, _ = kq_map(w.kgrid, qj)
+    npw = st.npw.cpu().numpy()
+    nb = st.nb.cpu().numpy()
+    eps = st.eps.cpu().numpy()
+
+    # --- eigenpairs of sampled bands: residual against the oracle's H(k)
+    host = {}
+    for k in sorted({0, int(kp[0])}):
+        m = st.miller[k, : npw[k]].cpu().numpy().astype(np.int64)
+        C = st.coef[k, : nb[k], : npw[k]].cpu().numpy()
+        host[k] = (m, C)
+        H = _dense_h(w, kred[k], m, st.omega_cell)
+        bands = [0, 1, nb[k] // 2, nb[k] - 1]
+        V = C[bands].T
+        res = np.abs(H @ V - V * eps[k, bands][None, :]).max()
+        gram = np.abs(V.conj().T @ V - np.eye(len(bands))).max()
+        _say(f"  k {k}: {npw[k]} plane waves, {nb[k]} bands, residual {res:.1e}, "
+             f"orthonormality {gram:.1e}")
+        assert res < 1e-9 * np.abs(eps[k, : nb[k]]).max()
+        assert gram < 1e-11
+        del H
+
+    # --- sampled pair densities: long rows and short (column-group) rows of k = 0
+    tr = tdx.transitions(ctx, st, qj, w.f_trans_thr, paired=True)
+    basis, i_g0 = tdx.response_basis(w.cell, w.kgrid, qj, w.ecut_chi[0])
+    n_g = len(basis)
+    gb = torch.from_numpy(basis).cuda()
+    off = tr.k_offsets.cpu().numpy()
+    tk = tr.k[: off[1]].cpu().numpy()
+    tn = tr.n[: off[1]].cpu().numpy()
+    tm = tr.m[: off[1]].cpu().numpy()
+    rowlen = {n: int((tn == n).sum()) for n in np.unique(tn)}
+    rng = np.random.default_rng(11)
+    long_t = [t for t in range(off[1]) if rowlen[tn[t]] >= 16]
+    short_t = [t for t in range(off[1]) if rowlen[tn[t]] < 16]
+    assert long_t
+    n_short = min(8, len(short_t))  # at 4 eV most rows are long
+    rows = np.sort(np.concatenate([rng.choice(long_t, 16 - n_short, replace=False),
+                                   rng.choice(short_t, n_short, replace=False)]).astype(np.int64))
+    P64 = tdx.pair_density(ctx, st, qj, tr, gb, "fp64")
+    got = tdx.pair_density_view(P64, len(tr), n_g, "fp64")[torch.as_tensor(rows, device="cuda")]
+    got = got.cpu().numpy()
+    k0, k1 = 0, int(kp[0])
+    need0 = sorted(set(tn[rows].tolist()) | (set(tm[rows].tolist()) if k1 == k0 else set()))
+    need1 = need0 if k1 == k0 else sorted(set(tm[rows].tolist()))
+    n_k = st.n_k
+    millers, coef = [None] * n_k, [None] * n_k
+    millers[k0], coef[k0] = host[k0][0], host[k0][1][need0]
+    millers[k1], coef[k1] = host[k1][0], host[k1][1][need1]
+    pos0 = {b: i for i, b in enumerate(need0)}
+    pos1 = {b: i for i, b in enumerate(need1)}
+    ost = States(np.asarray(w.cell), None, st.omega_cell, tuple(w.kgrid), kred, millers,
+                 [None] * n_k, coef, [None] * n_k, 0.0, w.temperatures[0], w.n_electrons)
+    z = np.zeros(len(rows))
+    sub = Transitions(tk[rows].astype(np.int64), kp[tk[rows]].astype(np.int64),
+                      np.array([pos0[b] for b in tn[rows]]), np.array([pos1[b] for b in tm[rows]]),
+                      z, z)
+    ref = pair_densities(ost, sub, qj, basis)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    _say(f"  T = {len(tr)} paired, N_G = {n_g}; {len(rows)} pair-density rows "
+         f"({16 - n_short} from long rows, {n_short} from short ones) vs the oracle: {err:.1e}")
+    assert err < 1e-10
+
+    # --- chi0 and S on 20 frequencies: split-BF16 against FP64
+    om = torch.as_tensor(w.omega_grid(0)[::50], device="cuda")
+    pref = 2.0 / (st.n_k * st.omega_cell)
+    c64 = tdx.chi0(ctx, tr, P64, n_g, "fp64", om, w.eta, pref)
+    del P64, got
+    P16 = tdx.pair_density(ctx, st, qj, tr, gb, "bf16x3")
+    c16 = tdx.chi0(ctx, tr, P16, n_g, "bf16x3", om, w.eta, pref)
+    del P16
+    scale = float(c64.abs().max())
+    e_16 = float((c16 - c64).abs().max()) / scale
+    c = c64.cpu().numpy()
+    worst = max(float(np.linalg.eigvalsh((c[i] - c[i].conj().T) / 2j).max())
+                for i in range(1, c.shape[0]))
+    K = tdx.kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid)
+    beta, n = 1.0 / w.temperatures[0], w.n_electrons / st.omega_cell
+    S64 = tdx.dsf(ctx, tdx.dyson(ctx, c64, K, i_g0), om, beta, n).cpu().numpy()
+    S16 = tdx.dsf(ctx, tdx.dyson(ctx, c16, K, i_g0), om, beta, n).cpu().numpy()
+    e_s = np.max(np.abs(S16 - S64)) / np.max(np.abs(S64))
+    _say(f"  chi0 split-BF16 vs FP64 {e_16:.1e}, S {e_s:.1e}, largest eigenvalue of the "
+         f"anti-Hermitian part {worst:.1e} (scale {scale:.1e})")
+    assert e_16 < 1e-4 and e_s < 1e-4
+    assert worst < 1e-12 * scale
     ctx.close()
