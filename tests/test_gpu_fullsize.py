@@ -6,7 +6,8 @@ fcc_c2 (the benchmark workload, q0):
 
 - eigenvalues at sampled k-points against the oracle's dense eigensolve;
 - pair densities of sampled transitions (non-degenerate bands, so each row is
-  unique up to one phase) against the oracle's direct sum, phase-aligned;
+  unique up to one phase; from long rows and from short rows, which run as
+  column groups) against the oracle's direct sum, phase-aligned;
 - chi0 on every 20th frequency: paired FP64 against the full-list FP64 sum
   (the pairing identity, 1e-12), split-BF16 against FP64 (1e-4), and the
   anti-Hermitian part of chi0(w > 0) negative semidefinite;
@@ -108,10 +109,20 @@ def test_fcc_c2_q0_full_size(tdx):
     tk, tn, tm = (x.cpu().numpy() for x in (tr.k, tr.n, tr.m))
     rows = []
     rng = np.random.default_rng(7)
+    n_long = n_short = 0
     for k in ks:
+        # rows of fewer than 16 transitions run as column groups (k, m): take
+        # samples of both kinds
         cand = [t for t in range(off[k], off[k + 1])
                 if _isolated(ost.eps[k], tn[t]) and _isolated(ost.eps[kp[k]], tm[t])]
-        rows += list(rng.choice(cand, size=min(8, len(cand)), replace=False))
+        rowlen = {n: int((tn[off[k]:off[k + 1]] == n).sum()) for n in set(tn[cand].tolist())}
+        for short in (False, True):
+            c = [t for t in cand if (rowlen[tn[t]] < 16) == short]
+            pick = list(rng.choice(c, size=min(4, len(c)), replace=False)) if c else []
+            rows += pick
+            n_short += len(pick) if short else 0
+            n_long += 0 if short else len(pick)
+    assert n_long and n_short
     rows = np.sort(np.array(rows))
     qred = np.asarray(qj, dtype=np.float64) / np.asarray(w.kgrid)
     obasis, _ = o_basis(ost.B, qred, w.ecut_chi[0])
@@ -127,7 +138,8 @@ def test_fcc_c2_q0_full_size(tdx):
         phase = b[g] / a[g]
         assert abs(abs(phase) - 1.0) < 1e-9
         assert np.max(np.abs(a * phase - b)) < 1e-10 * np.max(np.abs(b))
-    _say(f"  states at {len(ks)} k and {len(rows)} pair-density rows match the oracle")
+    _say(f"  states at {len(ks)} k and {len(rows)} pair-density rows ({n_long} from long rows, "
+         f"{n_short} from column groups) match the oracle")
 
     # --- chi0 in the bench configuration, and properties
     c64 = tdx.chi0(ctx, tr, P64, n_g, "fp64", om, w.eta, pref)
