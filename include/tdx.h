@@ -289,8 +289,9 @@ int tdx_chi0_batched(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, int 
 /* Number of tile variants of a precision (split-BF16: frequencies per wave
  * x G' per workgroup x chunk). */
 int tdx_chi0_variants(int prec, int *count);
-/* Tile variant (-1 = default) and slice length 2^slice_log2 used for bases
- * of n_g vectors (size classes of 16). */
+/* Tile variant (-1 = default: the 8-wave 2 x 9 tile with three LDS buffers)
+ * and slice length 2^slice_log2 (default 2^20) used for bases of n_g vectors
+ * (size classes of 16). */
 int tdx_chi0_set_config(tdx_ctx *ctx, int prec, int n_g, int variant, int slice_log2);
 int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slice_log2);
 /* Time every variant and slice length 2^{18,20} on the probe item (its

@@ -27,6 +27,10 @@ struct BatchTile {
 };
 
 int bf16x3_variant_count();
+// Variant used for a basis size with no tuned entry: the 8-wave 2 x 9 tile
+// with three LDS buffers, the fastest variant measured on every basis size
+// tried (N_G 133 to 303).
+int bf16x3_default_variant();
 void bf16x3_variant_shape(int v, int *wblock, int *cols);
 int bf16x3_variant_occupancy(int v);  // workgroups per CU
 // The FP32 rho block that follows the fragment words of a split-BF16

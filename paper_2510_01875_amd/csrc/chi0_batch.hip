@@ -58,7 +58,7 @@ int bucket_of(int ld) { return std::min(ld / 16, 63); }
 
 void pick(const tdx_ctx *ctx, int ld, int *variant, int *slice_log2) {
   const tdx_chi0_tune &t = ctx->tune[bucket_of(ld)];
-  *variant = t.variant >= 0 ? t.variant : 0;
+  *variant = t.variant >= 0 ? t.variant : bf16x3_default_variant();
   *slice_log2 = t.slice_log2;
 }
 

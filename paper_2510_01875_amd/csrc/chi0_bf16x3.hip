@@ -695,6 +695,8 @@ const Variant kVariants[] = {TDX_V(4, 4, 32, 2, false, 2, 4), TDX_V(2, 8, 16, 2,
 
 int bf16x3_variant_count() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
 
+int bf16x3_default_variant() { return 9; }  // TDX_V(2, 9, 32, 1, false, 3, 8)
+
 void bf16x3_variant_shape(int v, int *wblock, int *cols) {
   *wblock = kVariants[v].waves * kVariants[v].wpw;
   *cols = 16 * kVariants[v].sub;

@@ -48,8 +48,8 @@ struct Workspace {
 // Tile variant and slice length of the split-BF16 chi0 kernel for one
 // response-basis size class (ld / 16 blocks); variant -1 = default.
 struct tdx_chi0_tune {
-  int variant = -1;
-  int slice_log2 = 18;
+  int variant = -1;  // -1: the default variant
+  int slice_log2 = 20;
   double ms = 0.0;
 };
 

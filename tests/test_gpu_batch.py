@@ -161,4 +161,4 @@ def test_autotuner_picks_a_variant_and_round_trips_the_cache(tdx, ctx):
         err = float((c - ref).abs().max() / ref.abs().max())
         _say(f"  variant {var} vs 0: {err:.2e}")
         assert err < 1e-5
-    tdx.chi0_set_config(ctx, n_g, -1, 18)
+    tdx.chi0_set_config(ctx, n_g, -1, 20)
