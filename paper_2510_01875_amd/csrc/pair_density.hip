@@ -134,9 +134,12 @@ __global__ void k_cols(const long long *koff, const int *tn, const int *tm, int 
 // the group's 16 transitions, the B operand is gathered per lane through the
 // Miller-index lookup box of the fixed side, which sits in LDS next to that
 // side's coefficients (zero outside its basis).  The output element j of
-// lane l is transition row l/16 + 4 j, G column l%16.
-template <int FMT, bool COL>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// lane l is transition row l/16 + 4 j, G column l%16.  W wavefronts share one
+// group (and its LDS) and take its 16-transition tiles in turn: W = 1 where
+// the LDS of a group is small enough for several groups per CU, W = 4 where
+// it is not (about 6300 plane waves: 149 KB, one group per CU).
+template <int FMT, bool COL, int W>
+__global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2, 2)))
     k_pair_density(const double2 *coef, const int *miller, const int *npw, int nb_max,
                    int npw_max, const int *tn, const int *tm, const long long *gbeg,
                    const long long *gend, const long long *perm, const int *kpmap,
@@ -149,18 +152,18 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
   const long long p0 = gbeg[grp], p1 = gend[grp];
   if (p1 <= p0) return;
   if (!COL && p1 - p0 < kShortRow) return;  // these run in column groups
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kp = kpmap[k];
   const int kf = COL ? kp : k;  // k-point of the fixed side (and of the lookup)
   const int ka = COL ? k : kp;  // k-point of the A rows (and of the K index)
   const int gs0 = gsmap[3 * k], gs1 = gsmap[3 * k + 1], gs2 = gsmap[3 * k + 2];
   const int npf = npw[kf], npa = npw[ka];
   const double2 *cf = coef + ((size_t)kf * nb_max + band) * npw_max;
-  for (int i = lane; i < npf; i += 64) {
+  for (int i = threadIdx.x; i < npf; i += 64 * W) {
     const double2 c = cf[i];
     cfix[i] = COL ? c : make_double2(c.x, -c.y);
   }
-  for (long i = lane; i < box; i += 64) lutf[i] = lut[(size_t)kf * box + i];
+  for (long i = threadIdx.x; i < box; i += 64 * W) lutf[i] = lut[(size_t)kf * box + i];
   __syncthreads();
   const int W1 = 2 * M1 + 1, W2 = 2 * M2 + 1;
   const int *ma = miller + (size_t)ka * npw_max * 3;
@@ -170,7 +173,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
   const int n_gt = ld / 16;
   // transition of group slot p
   auto trans = [&](long long p) { return COL ? perm[p] : p; };
-  for (long long q0 = p0; q0 < p1; q0 += 16) {
+  for (long long q0 = p0 + 16 * wave; q0 < p1; q0 += 16 * W) {
     // this lane's A row: the transition of slot q0 + r (zero past the group)
     const bool row_ok = q0 + r < p1;
     const double2 *crow = ca + (size_t)(row_ok ? ta[trans(q0 + r)] : 0) * npw_max;
@@ -336,17 +339,25 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
   const int ld = ld_of(n_g);
   const size_t lds = sizeof(double2) * st->npw_max + sizeof(int) * (size_t)box;
   dim3 grid(nb_max, nk);
+  // four wavefronts per group when fewer than four groups fit in a CU's LDS
+  const bool wide = lds > 40 * 1024;
   // long rows, then the column groups of the short ones (disjoint outputs)
-#define TDX_PD1(F, COL, B, E)                                                                  \
-  TDX_HIP(hipFuncSetAttribute((const void *)k_pair_density<F, COL>,                            \
+#define TDX_PD2(F, COL, W, B, E)                                                               \
+  TDX_HIP(hipFuncSetAttribute((const void *)k_pair_density<F, COL, W>,                         \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));          \
-  hipLaunchKernelGGL((k_pair_density<F, COL>), grid, dim3(64), lds, s,                         \
+  hipLaunchKernelGGL((k_pair_density<F, COL, W>), grid, dim3(64 * W), lds, s,                  \
                      (const double2 *)st->coef, st->miller, st->npw, nb_max, st->npw_max,      \
                      tl->n, tl->m, B, E, d_perm, d_kp, d_gs, gbasis, n_g, ld, d_lut, box, M0,  \
                      M1, M2, P, (long long)n_trans);                                           \
   TDX_HIP(hipGetLastError())
+#define TDX_PD1(F, COL, B, E)       \
+  if (wide) {                       \
+    TDX_PD2(F, COL, 4, B, E);       \
+  } else {                          \
+    TDX_PD2(F, COL, 1, B, E);       \
+  }
 #define TDX_PD(F)                     \
-  TDX_PD1(F, false, d_rb, d_re);      \
+  TDX_PD1(F, false, d_rb, d_re)       \
   TDX_PD1(F, true, d_cb, d_ce)
   if (prec == TDX_PREC_FP64) {
     TDX_PD(TDX_PREC_FP64);
@@ -360,6 +371,7 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
   }
 #undef TDX_PD
 #undef TDX_PD1
+#undef TDX_PD2
   return TDX_OK;
 }
 
