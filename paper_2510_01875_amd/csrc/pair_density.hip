@@ -136,8 +136,9 @@ __global__ void k_cols(const long long *koff, const int *tn, const int *tm, int 
 // side's coefficients (zero outside its basis).  The output element j of
 // lane l is transition row l/16 + 4 j, G column l%16.  W wavefronts share one
 // group (and its LDS) and take its 16-transition tiles in turn: W = 1 where
-// the LDS of a group is small enough for several groups per CU, W = 4 where
-// it is not (about 6300 plane waves: 149 KB, one group per CU).
+// the LDS of a group is small enough for several groups per CU, W = 8 (two
+// per SIMD) where it is not (about 6300 plane waves: 149 KB, one group per
+// CU).
 template <int FMT, bool COL, int W>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2, 2)))
     k_pair_density(const double2 *coef, const int *miller, const int *npw, int nb_max,
@@ -339,7 +340,7 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
   const int ld = ld_of(n_g);
   const size_t lds = sizeof(double2) * st->npw_max + sizeof(int) * (size_t)box;
   dim3 grid(nb_max, nk);
-  // four wavefronts per group when fewer than four groups fit in a CU's LDS
+  // eight wavefronts per group when fewer than four groups fit in a CU's LDS
   const bool wide = lds > 40 * 1024;
   // long rows, then the column groups of the short ones (disjoint outputs)
 #define TDX_PD2(F, COL, W, B, E)                                                               \
@@ -352,7 +353,7 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
   TDX_HIP(hipGetLastError())
 #define TDX_PD1(F, COL, B, E)       \
   if (wide) {                       \
-    TDX_PD2(F, COL, 4, B, E);       \
+    TDX_PD2(F, COL, 8, B, E);       \
   } else {                          \
     TDX_PD2(F, COL, 1, B, E);       \
   }
