@@ -298,3 +298,92 @@ def test_h16_c3_full_size(tdx):
     assert e_16 < 1e-4 and e_s < 1e-4
     assert worst < 1e-12 * scale
     ctx.close()
+
+
+def test_fcc_c4_full_size_subset(tdx):
+    """fcc_c4 at full size (16^3 k, 800 frequencies) for up to three of its 32
+    q, the smallest at distinct temperatures whose split-BF16 pair densities
+    fit in 110 GB together (the whole set does not fit in one GPU's memory at
+    once): one persistent plan for them is bitwise equal to one launch per q, and on 16 sampled
+    frequencies split-BF16 chi0 and S are within 1e-4 of FP64, with the
+    anti-Hermitian part of chi0 negative semidefinite."""
+    import torch
+
+    w = workloads.fcc_c4()
+    ctx = tdx.Context(0)
+    cache = os.path.join(ROOT, "paper_2510_01875_amd", "tune_gfx950.json")
+    if os.path.exists(cache):
+        tdx.tune_load(ctx, cache)
+    _say("fcc_c4 full size: states")
+    st = tdx.build_states(ctx, w, w.temperatures[0])
+
+    def at_temperature(iq):
+        T = w.temperatures[iq]
+        if st.temperature != T:
+            tdx.occupations(ctx, st, T, w.n_electrons, w.f_trunc)
+
+    # split-BF16 pair-density bytes of every q (paired lists at its temperature)
+    sizes = []
+    for iq, qj in enumerate(w.qs):
+        at_temperature(iq)
+        n_t = len(tdx.transitions(ctx, st, qj, w.f_trans_thr, paired=True))
+        n_g = len(tdx.response_basis(w.cell, w.kgrid, qj, w.ecut_chi[iq])[0])
+        sizes.append((tdx.pair_density_bytes(n_t, n_g, "bf16x3"), iq, n_t))
+    torch.cuda.empty_cache()
+    chosen, temps, total = [], set(), 0
+    for nbytes, iq, _ in sorted(sizes):
+        if w.temperatures[iq] in temps or len(chosen) == 3 or total + nbytes > 110e9:
+            continue
+        chosen.append(iq)
+        temps.add(w.temperatures[iq])
+        total += nbytes
+    assert len(chosen) >= 2
+    _say(f"  paired transition counts {min(x[2] for x in sizes)} .. {max(x[2] for x in sizes)}; "
+         f"chosen q {chosen}, {total / 1e9:.0f} GB of split-BF16 pair densities")
+
+    pref = 2.0 / (st.n_k * st.omega_cell)
+    items, per_q = [], []
+    for iq in chosen:
+        at_temperature(iq)
+        qj = tuple(w.qs[iq])
+        basis, i_g0 = tdx.response_basis(w.cell, w.kgrid, qj, w.ecut_chi[iq])
+        gb = torch.from_numpy(basis).cuda()
+        tr = tdx.transitions(ctx, st, qj, w.f_trans_thr, paired=True)
+        P = tdx.pair_density(ctx, st, qj, tr, gb, "bf16x3")
+        om = torch.as_tensor(w.omega_grid(iq), device="cuda")
+        K = tdx.kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid)
+        items.append(tdx.Chi0Item(tr, P, len(basis), om, w.eta, pref))
+        per_q.append(dict(iq=iq, qj=qj, gb=gb, i_g0=i_g0, tr=tr, om=om, K=K,
+                          beta=1.0 / w.temperatures[iq]))
+    plan = tdx.Chi0Plan(ctx, items, "bf16x3")
+    plan.launch()
+    torch.cuda.synchronize()
+    n = w.n_electrons / st.omega_cell
+    for it, d in zip(items, per_q):
+        single = tdx.chi0(ctx, it.tr, it.P, it.out.shape[1], "bf16x3", it.omega, w.eta, pref)
+        assert torch.equal(single, it.out)
+        del single
+    for it, d in zip(items, per_q):
+        # FP64 on 16 sampled frequencies (its pair densities at the q's temperature)
+        at_temperature(d["iq"])
+        sel = torch.arange(0, d["om"].shape[0], d["om"].shape[0] // 16, device="cuda")[:16]
+        om_s = d["om"][sel].contiguous()
+        P64 = tdx.pair_density(ctx, st, d["qj"], d["tr"], d["gb"], "fp64")
+        c64 = tdx.chi0(ctx, d["tr"], P64, it.out.shape[1], "fp64", om_s, w.eta, pref)
+        del P64
+        c16 = it.out[sel].contiguous()
+        scale = float(c64.abs().max())
+        e_16 = float((c16 - c64).abs().max()) / scale
+        c = c64.cpu().numpy()
+        worst = max(float(np.linalg.eigvalsh((c[i] - c[i].conj().T) / 2j).max())
+                    for i in range(c.shape[0]) if float(om_s[i]) > 0)
+        S64 = tdx.dsf(ctx, tdx.dyson(ctx, c64, d["K"], d["i_g0"]), om_s, d["beta"], n).cpu().numpy()
+        S16 = tdx.dsf(ctx, tdx.dyson(ctx, c16, d["K"], d["i_g0"]), om_s, d["beta"], n).cpu().numpy()
+        e_s = np.max(np.abs(S16 - S64)) / np.max(np.abs(S64))
+        _say(f"  q {d['iq']} (T {w.temperatures[d['iq']] * 27.211386:.0f} eV, N_G "
+             f"{it.out.shape[1]}, {len(d['tr'])} transitions): plan == single launch; "
+             f"split-BF16 vs FP64 chi0 {e_16:.1e}, S {e_s:.1e}, anti-Hermitian max {worst:.1e}")
+        assert e_16 < 1e-4 and e_s < 1e-4
+        assert worst < 1e-12 * scale
+    plan.close()
+    ctx.close()
