@@ -245,9 +245,9 @@ def main():
                                          "launches": 5}}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path's sharding "
-              "over q, frequency or transition blocks is described in DESIGN.md",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); across GPUs the path "
+              "would split the q-vectors, or the frequencies of one q, with no exchange "
+              "inside the chi0 step", file=sys.stderr)
         sys.exit(2)
 
     import torch
