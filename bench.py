@@ -228,7 +228,10 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="tune the split-BF16 tile shape on q0 first and save the cache")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2510_01875_amd",
-                                                         "tune_gfx950.json"))
+                                                         "tune_gfx950.json"),
+                    help="tile cache read when not tuning")
+    ap.add_argument("--tune-save", default=None,
+                    help="where --autotune writes its cache (default: --tune-cache)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (out = in * 1.0, "
                          "five launches): the reference kernel for scaling HBM byte counters")
@@ -280,8 +283,9 @@ def main():
                                  2.0 / (st.n_k * st.omega_cell))
             v, sl, ms = tdx.autotune_chi0(ctx, probe, max_trans=1 << 22)
             tuned = {"variant": v, "slice_log2": sl, "probe_ms": ms, "source": "autotuned now"}
-            os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-            tdx.tune_save(ctx, os.path.join(ROOT, "gpurun_out", "tune_gfx950.json"))
+            out = args.tune_save or args.tune_cache
+            os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
+            tdx.tune_save(ctx, out)
             del P0, tr0, probe
             log(f"autotune: variant {v}, slice 2^{sl}, {ms:.1f} ms on the probe")
         elif os.path.exists(args.tune_cache):
