@@ -377,6 +377,31 @@ int tdx_itcf(tdx_ctx *ctx, const double *S, const double *omega, int n_w,
              tdx_stream stream);
 
 /* ------------------------------------------------------------------ */
+/* The eta-convergence test in imaginary time (Sec. 2, Eq. 2, Fig. 2)  */
+/* ------------------------------------------------------------------ */
+
+/* Metrics of n_set ITCFs F [n_set][n_tau] (device FP64) on one tau grid
+ * (device [n_tau]) that starts at 0 and ends at beta or at beta/2 (then the
+ * symmetry F(tau) = F(beta - tau) supplies the rest) and holds beta/2:
+ * metrics (device FP64 [n_set][5]) = F(beta/2), A = int_0^beta F dtau,
+ * F~(beta/2), int_0^beta F~ dtau = A - beta F(0), chi(q) = -n A, with the
+ * shifted ITCF F~(tau) = F(tau) - F(0) of Eq. 2 and the integrals by the
+ * composite trapezoid on the grid.  Asynchronous; a grid of another form
+ * gives NaN metrics. */
+int tdx_itcf_metrics(tdx_ctx *ctx, const double *F, int n_set, const double *tau, int n_tau,
+                     double beta, double density, double *metrics, tdx_stream stream);
+
+/* The reference eta of the test: eta (host [n_eta], increasing) and its
+ * metrics (host [n_eta][5] from tdx_itcf_metrics); the convergence range is
+ * the run of eta from the smallest one over which both shifted metrics,
+ * F~(beta/2) and int_0^beta F~ dtau, stay within tol (relative) of their
+ * values at the smallest eta, and *ref_index is the largest eta of that run
+ * (the paper selects the largest converged eta by inspection; tol is this
+ * library's reading of "converged").  NUMERIC if a metric is not finite. */
+int tdx_eta_reference(const double *metrics, const double *eta, int n_eta, double tol,
+                      int *ref_index);
+
+/* ------------------------------------------------------------------ */
 /* Reverse mode: vector-Jacobian products of F(q,tau) (FP64)           */
 /* ------------------------------------------------------------------ */
 

@@ -142,6 +142,10 @@ _dyson_async = _sig("tdx_dyson_async", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_
 _itcf = _sig("tdx_itcf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double, C.c_void_p,
                           C.c_int, C.c_void_p, C.c_void_p])
 
+_metrics = _sig("tdx_itcf_metrics", [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
+                                     C.c_double, C.c_double, C.c_void_p, C.c_void_p])
+_eta_ref = _sig("tdx_eta_reference", [c_dbl_p, c_dbl_p, C.c_int, C.c_double,
+                                      C.POINTER(C.c_int)])
 _itcf_vjp = _sig("tdx_itcf_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
                                   C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p])
@@ -169,7 +173,7 @@ EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_occupations", "tdx_response_basis", "tdx_transitions",
             "tdx_pair_density_bytes", "tdx_pair_density", "tdx_chi0", "tdx_kernel_matrix",
             "tdx_xc_kernel_grid", "tdx_kernel_matrix_from_grid",
-            "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
+            "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
             "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
             "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_autotune_chi0", "tdx_tune_save",
             "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async", "tdx_itcf_vjp",
@@ -475,6 +479,31 @@ def itcf(ctx: Context, S: torch.Tensor, omega: torch.Tensor, beta: float, tau: t
     return F
 
 
+# ------------------------------------------------ eta test in imaginary time
+METRICS = ("F(beta/2)", "int_0^beta F", "F~(beta/2)", "int_0^beta F~", "chi(q)")
+
+
+def itcf_metrics(ctx: Context, F: torch.Tensor, tau: torch.Tensor, beta: float, density: float,
+                 stream=None) -> torch.Tensor:
+    """[n_set][5] metrics (METRICS) of the rows of F [n_set][n_tau] (Sec. 2, Eq. 2)."""
+    F = F.reshape(-1, tau.shape[0]).contiguous()
+    m = torch.empty((F.shape[0], 5), dtype=torch.float64, device=F.device)
+    check(_metrics(ctx.handle, _ptr(F), F.shape[0], _ptr(tau), tau.shape[0], beta, density,
+                   _ptr(m), _stream(stream)))
+    return m
+
+
+def eta_reference(metrics, eta, tol: float = 1e-2) -> int:
+    """Index of the reference eta: the largest one of the converged run from the
+    smallest eta (tdx.h)."""
+    m = np.ascontiguousarray(np.asarray(metrics, dtype=np.float64).reshape(-1, 5))
+    e = np.ascontiguousarray(np.asarray(eta, dtype=np.float64))
+    r = C.c_int()
+    check(_eta_ref(m.ctypes.data_as(c_dbl_p), e.ctypes.data_as(c_dbl_p), len(e), tol,
+                   C.byref(r)))
+    return r.value
+
+
 # ------------------------------------------------------------ reverse mode
 # Cotangent convention: real x -> dL = sum xbar dx; complex z ->
 # dL = Re sum conj(zbar) dz (PyTorch's convention for complex gradients).
@@ -722,3 +751,58 @@ def dyson_async(ctx: Context, chi0_t: torch.Tensor, K: torch.Tensor, i_g0: int,
     n_w, n_g, _ = chi0_t.shape
     check(_dyson_async(ctx.handle, _ptr(chi0_t), _ptr(K), n_g, n_w, i_g0, _ptr(chi00),
                        _ptr(work), _ptr(info), _stream(stream)))
+
+
+@dataclass
+class EtaScan:
+    eta: np.ndarray        # [n_eta], increasing
+    omega: torch.Tensor    # [n_w]
+    tau: torch.Tensor      # [n_tau]
+    S: torch.Tensor        # [n_eta][n_w]
+    F: torch.Tensor        # [n_eta][n_tau]
+    metrics: np.ndarray    # [n_eta][5], METRICS
+    ref_index: int         # the reference eta: eta[ref_index]
+    beta: float
+    density: float
+    n_trans: int
+
+
+def eta_scan(ctx: Context, w, st: States, iq: int, etas, prec: str = "bf16x3",
+             tol: float = 1e-2, paired: bool = True, stream=None) -> EtaScan:
+    """The eta-convergence test in imaginary time (Sec. 2, Eq. 2, Fig. 2): chi0
+    for every eta from one set of pair densities (split-BF16: one persistent
+    launch for all of them), then Dyson, S and F per eta, the metrics of the
+    F and the reference eta."""
+    etas = np.asarray(etas, dtype=np.float64)
+    if etas.ndim != 1 or len(etas) == 0 or np.any(np.diff(etas) <= 0):
+        raise ValueError("etas must be a non-empty increasing sequence")
+    dev = st.eps.device
+    qj = tuple(w.qs[iq])
+    T = w.temperatures[iq]
+    if abs(st.temperature - T) > 0:
+        occupations(ctx, st, T, w.n_electrons, w.f_trunc, stream)
+    basis, i_g0 = response_basis(w.cell, w.kgrid, qj, w.ecut_chi[iq])
+    n_g = len(basis)
+    gb = torch.from_numpy(basis).to(dev)
+    tr = transitions(ctx, st, qj, w.f_trans_thr, stream, paired=paired)
+    P = pair_density(ctx, st, qj, tr, gb, prec, stream)
+    om = torch.as_tensor(w.omega_grid(iq), device=dev)
+    pref = 2.0 / (st.n_k * st.omega_cell)
+    if prec == "bf16x3":
+        items = [Chi0Item(tr, P, n_g, om, float(e), pref) for e in etas]
+        plan = Chi0Plan(ctx, items, prec)
+        plan.launch(stream)
+        chis = [it.out for it in items]
+    else:
+        plan = None
+        chis = [chi0(ctx, tr, P, n_g, prec, om, float(e), pref, stream=stream) for e in etas]
+    K = kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid, stream)
+    beta, n = 1.0 / T, w.n_electrons / st.omega_cell
+    tau = torch.as_tensor(w.tau_grid(iq), device=dev)
+    S = torch.stack([dsf(ctx, dyson(ctx, c, K, i_g0, stream), om, beta, n, stream) for c in chis])
+    F = torch.stack([itcf(ctx, S[i], om, beta, tau, stream) for i in range(len(etas))])
+    if plan is not None:
+        plan.close()
+    del chis, P
+    m = itcf_metrics(ctx, F, tau, beta, n, stream).cpu().numpy()
+    return EtaScan(etas, om, tau, S, F, m, eta_reference(m, etas, tol), beta, n, len(tr))

@@ -48,6 +48,47 @@ __global__ void __launch_bounds__(256)
   if (threadIdx.x == 0) F[it] = sh[0];
 }
 
+// Imaginary-time metrics of one ITCF per block (Sec. 2, Eq. 2):
+//   m[0] = F(beta/2), m[1] = A = int_0^beta F dtau, m[2] = F~(beta/2),
+//   m[3] = int_0^beta F~ dtau = A - beta F(0), m[4] = chi(q) = -n A,
+// with F~(tau) = F(tau) - F(0) and the integral by the composite trapezoid
+// on the tau grid.  A grid ending at beta/2 stands for [0, beta] by the
+// symmetry F(tau) = F(beta - tau) (the integral doubles).  A grid that does
+// not start at 0, end at beta/2 or beta, or hold beta/2 gives NaN.
+__global__ void __launch_bounds__(64)
+    k_itcf_metrics(const double *F, int n_tau, const double *tau, double beta, double dens,
+                   double *m) {
+  __shared__ double sh[64];
+  const int set = blockIdx.x;
+  const double *f = F + (size_t)set * n_tau;
+  const double tol = 1e-12 * beta;
+  const double t_end = tau[n_tau - 1];
+  const bool half = fabs(t_end - 0.5 * beta) <= tol, full = fabs(t_end - beta) <= tol;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j + 1 < n_tau; j += 64)
+    acc += 0.5 * (tau[j + 1] - tau[j]) * (f[j] + f[j + 1]);
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 32; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int mid = -1;
+    for (int j = 0; j < n_tau; ++j)
+      if (fabs(tau[j] - 0.5 * beta) <= tol) mid = j;
+    const bool ok = n_tau > 1 && tau[0] == 0.0 && (half || full) && mid >= 0;
+    const double A = (half ? 2.0 : 1.0) * sh[0];
+    const double f0 = f[0], fm = ok ? f[mid] : NAN;
+    double *o = m + (size_t)set * 5;
+    o[0] = ok ? fm : NAN;
+    o[1] = ok ? A : NAN;
+    o[2] = ok ? fm - f0 : NAN;
+    o[3] = ok ? A - beta * f0 : NAN;
+    o[4] = ok ? -dens * A : NAN;
+  }
+}
+
 }  // namespace
 }  // namespace tdx
 
@@ -79,6 +120,44 @@ int tdx_itcf(tdx_ctx *ctx, const double *S, const double *omega, int n_w, double
   hipLaunchKernelGGL(k_itcf, dim3(n_tau), dim3(256), 0, as_stream(stream), S, omega, n_w, beta,
                      tau, F);
   TDX_HIP(hipGetLastError());
+  return TDX_OK;
+}
+
+int tdx_itcf_metrics(tdx_ctx *ctx, const double *F, int n_set, const double *tau, int n_tau,
+                     double beta, double density, double *metrics, tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && F && tau && metrics, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(n_set > 0 && n_tau > 1, TDX_ERR_SHAPE, "bad sizes");
+  TDX_REQUIRE(std::isfinite(beta) && beta > 0 && std::isfinite(density) && density > 0,
+              TDX_ERR_INVALID_ARG, "bad beta or density");
+  TDX_TRY(check_device(ctx));
+  hipLaunchKernelGGL(k_itcf_metrics, dim3(n_set), dim3(64), 0, as_stream(stream), F, n_tau, tau,
+                     beta, density, metrics);
+  TDX_HIP(hipGetLastError());
+  return TDX_OK;
+}
+
+int tdx_eta_reference(const double *metrics, const double *eta, int n_eta, double tol,
+                      int *ref_index) {
+  clear_error();
+  TDX_REQUIRE(metrics && eta && ref_index, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(n_eta > 0, TDX_ERR_SHAPE, "n_eta must be positive");
+  TDX_REQUIRE(std::isfinite(tol) && tol >= 0, TDX_ERR_INVALID_ARG, "bad tolerance");
+  for (int i = 0; i < n_eta; ++i) {
+    TDX_REQUIRE(std::isfinite(eta[i]) && eta[i] > 0 && (i == 0 || eta[i] > eta[i - 1]),
+                TDX_ERR_INVALID_ARG, "eta must be positive and increasing");
+    for (int c = 0; c < 5; ++c)
+      TDX_REQUIRE(std::isfinite(metrics[5 * i + c]), TDX_ERR_NUMERIC,
+                  "metric %d of eta %d is not finite", c, i);
+  }
+  const double a0 = metrics[2], b0 = metrics[3];
+  int ref = 0;
+  for (int i = 1; i < n_eta; ++i) {
+    const double a = metrics[5 * i + 2], b = metrics[5 * i + 3];
+    if (fabs(a - a0) > tol * fabs(a0) || fabs(b - b0) > tol * fabs(b0)) break;
+    ref = i;
+  }
+  *ref_index = ref;
   return TDX_OK;
 }
 
