@@ -232,6 +232,9 @@ def main():
                     help="tile cache read when not tuning")
     ap.add_argument("--tune-save", default=None,
                     help="where --autotune writes its cache (default: --tune-cache)")
+    ap.add_argument("--eta-scan", type=int, default=8,
+                    help="also time the eta-convergence test (Sec. 2) on q0 over this many "
+                         "eta (powers of two around the workload's eta; 0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (out = in * 1.0, "
                          "five launches): the reference kernel for scaling HBM byte counters")
@@ -344,6 +347,28 @@ def main():
             err["fp32"] = errors(legs["fp32"]["S"], legs["fp64"]["S"], legs["fp32"]["F"],
                                  legs["fp64"]["F"])
 
+    eta_info = None
+    if args.prec == "bf16x3" and args.eta_scan > 0:
+        k = args.eta_scan
+        etas = w.eta * 2.0 ** np.arange(-(k // 2), k - k // 2)
+        tdx.eta_scan(ctx, w, st, 0, etas, prec=args.prec, paired=paired)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        es = tdx.eta_scan(ctx, w, st, 0, etas, prec=args.prec, paired=paired)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        n_w0, n_g0 = int(es.omega.shape[0]), int(setup[0][0].shape[0])
+        eta_info = {
+            "n_eta": k, "eta_ha": etas.tolist(), "ms": dt * 1e3,
+            "s_eval_per_s": k * n_w0 / dt,
+            "chi0_tflops_whole_scan": k * f_alg(n_w0, n_g0, es.n_trans) / dt / 1e12,
+            "reference_eta_ha": float(etas[es.ref_index]), "tol": 1e-2,
+            "metrics": {"columns": list(tdx.METRICS), "rows": es.metrics.tolist()},
+            "form": "q0: transitions, pair densities, one persistent chi0 launch for all eta, "
+                    "then Dyson, S, F and the metrics per eta (whole scan timed)"}
+        log(f"eta scan: {k} eta in {dt * 1e3:.0f} ms, reference eta {etas[es.ref_index]:.4f}")
+        del es
+
     per_launch = flops_step
     avg_ms = sum(launch_ms) / len(launch_ms)
     line = {
@@ -375,6 +400,7 @@ def main():
         "plain": {p: {"chi0_tflops": v["chi0_tflops"], "chi0_ms_q0": v["chi0_ms_q0"]}
                   for p, v in legs.items()},
         "error_vs_fp64": err,
+        "eta_scan": eta_info,
         "roofline": {"bound": "mfma", "achieved": per_launch / (avg_ms * 1e-3) / 1e12,
                      "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
                      "frac": per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],
