@@ -402,6 +402,22 @@ int tdx_eta_reference(const double *metrics, const double *eta, int n_eta, doubl
                       int *ref_index);
 
 /* ------------------------------------------------------------------ */
+/* Dielectric properties from S (Sec. 3 and A.2, Eqs. 8, A-1, A-2)     */
+/* ------------------------------------------------------------------ */
+
+/* From S on an increasing grid 0 <= w_0 < ... (device [n_w]): Im chi by the
+ * FDT in the normalisation of tdx_dsf, Im chi = -pi n (1 - e^{-beta w}) S;
+ * Re chi by the Kramers-Kronig relation
+ *   Re chi(w) = (2/pi) P int_0^{w_max} w' Im chi(w') / (w'^2 - w^2) dw'
+ * with Im chi linear between grid points (closed form per interval; no tail
+ * past the grid); eps^{-1} = 1 + (4 pi / q2) chi (Eq. A-1, q2 = |q + G|^2 of
+ * the element); sigma = -i w (eps - 1) / (4 pi) (Eq. A-2).  Outputs are
+ * device complex128 [n_w], each may be null.  Asynchronous. */
+int tdx_dielectric(tdx_ctx *ctx, const double *S, const double *omega, int n_w, double beta,
+                   double density, double q2, double *chi, double *eps_inv, double *sigma,
+                   tdx_stream stream);
+
+/* ------------------------------------------------------------------ */
 /* Reverse mode: vector-Jacobian products of F(q,tau) (FP64)           */
 /* ------------------------------------------------------------------ */
 

@@ -144,6 +144,9 @@ _itcf = _sig("tdx_itcf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_doubl
 
 _metrics = _sig("tdx_itcf_metrics", [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
                                      C.c_double, C.c_double, C.c_void_p, C.c_void_p])
+_dielectric = _sig("tdx_dielectric", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
+                                      C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p])
 _eta_ref = _sig("tdx_eta_reference", [c_dbl_p, c_dbl_p, C.c_int, C.c_double,
                                       C.POINTER(C.c_int)])
 _itcf_vjp = _sig("tdx_itcf_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
@@ -173,7 +176,7 @@ EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_occupations", "tdx_response_basis", "tdx_transitions",
             "tdx_pair_density_bytes", "tdx_pair_density", "tdx_chi0", "tdx_kernel_matrix",
             "tdx_xc_kernel_grid", "tdx_kernel_matrix_from_grid",
-            "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
+            "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_dielectric", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
             "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
             "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_autotune_chi0", "tdx_tune_save",
             "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async", "tdx_itcf_vjp",
@@ -502,6 +505,26 @@ def eta_reference(metrics, eta, tol: float = 1e-2) -> int:
     check(_eta_ref(m.ctypes.data_as(c_dbl_p), e.ctypes.data_as(c_dbl_p), len(e), tol,
                    C.byref(r)))
     return r.value
+
+
+# ------------------------------------------------- dielectric properties
+def q_squared(cell, kgrid, qj) -> float:
+    """|q|^2 (bohr^-2) of q = sum_i (qj_i / kgrid_i) b_i."""
+    A = np.asarray(cell, dtype=np.float64).reshape(3, 3)
+    B = 2.0 * math.pi * np.linalg.inv(A).T
+    q = (np.asarray(qj, dtype=np.float64) / np.asarray(kgrid, dtype=np.float64)) @ B
+    return float(q @ q)
+
+
+def dielectric(ctx: Context, S: torch.Tensor, omega: torch.Tensor, beta: float, density: float,
+               q2: float, stream=None):
+    """(chi, eps^{-1}, sigma) [n_w] complex128 from S: Im chi by the FDT, Re chi
+    by Kramers-Kronig on the grid, Eqs. A-1 and A-2 (tdx.h)."""
+    n = omega.shape[0]
+    out = [torch.empty(n, dtype=torch.complex128, device=omega.device) for _ in range(3)]
+    check(_dielectric(ctx.handle, _ptr(S), _ptr(omega), n, beta, density, q2, _ptr(out[0]),
+                      _ptr(out[1]), _ptr(out[2]), _stream(stream)))
+    return tuple(out)
 
 
 # ------------------------------------------------------------ reverse mode

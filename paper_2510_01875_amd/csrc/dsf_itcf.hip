@@ -89,6 +89,59 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// Im chi at grid point j from S by the FDT (Eq. 8): -pi n (1 - e^{-beta w}) S.
+__device__ inline double im_chi_of(const double *S, const double *w, int j, double beta,
+                                   double dens) {
+  return -M_PI * dens * (-expm1(-beta * w[j])) * S[j];
+}
+
+// Per frequency w_i (one block): chi(w_i) with Im chi from S and Re chi by
+// the Kramers-Kronig relation
+//   Re chi(w) = (1/pi) P int_0^wmax f(w') [1/(w' - w) + 1/(w' + w)] dw',
+// f = Im chi linear between grid points, so that on [a, b] with slope s
+//   int f(w') / (w' - c) dw' = f(c) (ln|b - c| - ln|a - c|) + s (b - a);
+// the logarithms of zero at c = w_i cancel between the two intervals that
+// meet there (f is continuous), which is the principal value, so they are
+// left out.  Then eps^{-1} = 1 + (4 pi / q^2) chi (Eq. A-1) and
+// sigma = -i w (eps - 1) / (4 pi) (Eq. A-2).  Fixed-order reduction.
+__global__ void __launch_bounds__(256)
+    k_dielectric(const double *S, const double *w, int n, double beta, double dens, double q2,
+                 double2 *chi, double2 *eps_inv, double2 *sigma) {
+  __shared__ double sh[256];
+  const int i = blockIdx.x;
+  const double wi = w[i];
+  double acc = 0.0;
+  for (int j = threadIdx.x; j + 1 < n; j += 256) {
+    const double a = w[j], b = w[j + 1], fa = im_chi_of(S, w, j, beta, dens),
+                 fb = im_chi_of(S, w, j + 1, beta, dens);
+    const double sl = (fb - fa) / (b - a);
+    double t = 2.0 * sl * (b - a);
+    const double cs[2] = {wi, -wi};
+    for (int k = 0; k < 2; ++k) {
+      const double c = cs[k], fc = fa + sl * (c - a);
+      const double lb = b != c ? log(fabs(b - c)) : 0.0, la = a != c ? log(fabs(a - c)) : 0.0;
+      t += fc * (lb - la);
+    }
+    acc += t;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double re = sh[0] / M_PI, im = im_chi_of(S, w, i, beta, dens);
+    const double v = 4.0 * M_PI / q2;
+    const double er = 1.0 + v * re, ei = v * im;  // eps^{-1}
+    const double d = er * er + ei * ei;
+    const double pr = er / d - 1.0, pi = -ei / d;  // eps - 1
+    if (chi) chi[i] = make_double2(re, im);
+    if (eps_inv) eps_inv[i] = make_double2(er, ei);
+    if (sigma) sigma[i] = make_double2(wi * pi / (4.0 * M_PI), -wi * pr / (4.0 * M_PI));
+  }
+}
+
 }  // namespace
 }  // namespace tdx
 
@@ -133,6 +186,22 @@ int tdx_itcf_metrics(tdx_ctx *ctx, const double *F, int n_set, const double *tau
   TDX_TRY(check_device(ctx));
   hipLaunchKernelGGL(k_itcf_metrics, dim3(n_set), dim3(64), 0, as_stream(stream), F, n_tau, tau,
                      beta, density, metrics);
+  TDX_HIP(hipGetLastError());
+  return TDX_OK;
+}
+
+int tdx_dielectric(tdx_ctx *ctx, const double *S, const double *omega, int n_w, double beta,
+                   double density, double q2, double *chi, double *eps_inv, double *sigma,
+                   tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && S && omega, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(n_w > 1, TDX_ERR_SHAPE, "need at least two frequencies");
+  TDX_REQUIRE(std::isfinite(beta) && beta > 0 && std::isfinite(density) && density > 0 &&
+                  std::isfinite(q2) && q2 > 0,
+              TDX_ERR_INVALID_ARG, "bad beta, density or q^2");
+  TDX_TRY(check_device(ctx));
+  hipLaunchKernelGGL(k_dielectric, dim3(n_w), dim3(256), 0, as_stream(stream), S, omega, n_w,
+                     beta, density, q2, (double2 *)chi, (double2 *)eps_inv, (double2 *)sigma);
   TDX_HIP(hipGetLastError());
   return TDX_OK;
 }
