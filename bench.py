@@ -369,6 +369,20 @@ def main():
         log(f"eta scan: {k} eta in {dt * 1e3:.0f} ms, reference eta {etas[es.ref_index]:.4f}")
         del es
 
+    # dielectric properties of q0 from its S (Kramers-Kronig on the grid)
+    stream = torch.cuda.current_stream()
+    d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    om0 = setup[0][2]
+    q2 = tdx.q_squared(w.cell, w.kgrid, w.qs[0])
+    beta0, dens0 = 1.0 / w.temperatures[0], w.n_electrons / st.omega_cell
+    tdx.dielectric(ctx, main_q0["S"], om0, beta0, dens0, q2)
+    d0.record(stream)
+    tdx.dielectric(ctx, main_q0["S"], om0, beta0, dens0, q2)
+    d1.record(stream)
+    torch.cuda.synchronize()
+    diel = {"ms": d0.elapsed_time(d1), "n_w": int(om0.shape[0]),
+            "form": "q0: Im chi by the FDT, Re chi by Kramers-Kronig over the grid, eps^-1, sigma"}
+
     per_launch = flops_step
     avg_ms = sum(launch_ms) / len(launch_ms)
     line = {
@@ -401,6 +415,7 @@ def main():
                   for p, v in legs.items()},
         "error_vs_fp64": err,
         "eta_scan": eta_info,
+        "dielectric": diel,
         "roofline": {"bound": "mfma", "achieved": per_launch / (avg_ms * 1e-3) / 1e12,
                      "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
                      "frac": per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],
