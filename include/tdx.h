@@ -412,7 +412,8 @@ int tdx_eta_reference(const double *metrics, const double *eta, int n_eta, doubl
  * with Im chi linear between grid points (closed form per interval; no tail
  * past the grid); eps^{-1} = 1 + (4 pi / q2) chi (Eq. A-1, q2 = |q + G|^2 of
  * the element); sigma = -i w (eps - 1) / (4 pi) (Eq. A-2).  Outputs are
- * device complex128 [n_w], each may be null.  Asynchronous. */
+ * device complex128 [n_w], each may be null.  Asynchronous; the grid is not
+ * checked (one that does not increase gives non-finite values). */
 int tdx_dielectric(tdx_ctx *ctx, const double *S, const double *omega, int n_w, double beta,
                    double density, double q2, double *chi, double *eps_inv, double *sigma,
                    tdx_stream stream);
