@@ -1,0 +1,160 @@
+"""Pins of the attenuation oracle (Sec. 3, Eqs. 3-7): the Savitzky-Golay
+filter and its smoother diagonal against scipy.signal, polynomial
+reproduction and projection traces (closed forms), the derivative spectrum
+against numpy's FFT, the residual conditions on F_n of known closed form, and
+the selection rule on a seeded rippled spectrum."""
+import numpy as np
+import pytest
+from scipy.signal import savgol_coeffs, savgol_filter
+
+import workloads
+from oracle import attenuation as att
+
+
+@pytest.mark.parametrize("w,p", [(5, 2), (11, 3), (21, 1), (31, 6), (7, 0)])
+def test_sg_filter_matches_scipy_interp(w, p):
+    rng = np.random.default_rng(w * 10 + p)
+    y = rng.standard_normal(97).cumsum()
+    ours = att.sg_filter(y, w, p)
+    ref = savgol_filter(y, w, p, mode="interp")
+    assert np.max(np.abs(ours - ref)) <= 1e-10 * np.max(np.abs(y))
+
+
+def test_sg_filter_reproduces_polynomials():
+    x = np.linspace(-1.0, 2.0, 60)
+    for p in (0, 1, 3, 5):
+        y = np.polyval(np.arange(1.0, p + 2.0), x)
+        for w in (p + 1 + (p % 2 == 0), 13, 25):
+            if w % 2 == 0:
+                w += 1
+            out = att.sg_filter(y, w, p)
+            assert np.max(np.abs(out - y)) <= 1e-9 * np.max(np.abs(y)), (p, w)
+
+
+@pytest.mark.parametrize("w,p", [(9, 2), (15, 4), (21, 1)])
+def test_hat_diagonal_matches_scipy(w, p):
+    n = 40
+    h = att.sg_hat_diag(n, w, p)
+    # interior: the centre tap of the convolution coefficients
+    c = savgol_coeffs(w, p)[w // 2]
+    assert np.allclose(h[w // 2:n - w // 2], c, rtol=0, atol=1e-12)
+    # every sample: the filter applied to a unit impulse, read at the impulse
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        assert abs(savgol_filter(e, w, p, mode="interp")[i] - h[i]) <= 1e-12
+
+
+def test_projection_traces_and_identity():
+    n = 31
+    # one window over the whole grid: a projection of rank p + 1
+    for p in (0, 1, 4):
+        assert abs(att.sg_hat_diag(n, n, p).sum() - (p + 1)) <= 1e-10
+    # degree w - 1 interpolates: the identity filter
+    y = np.random.default_rng(1).standard_normal(n)
+    assert np.allclose(att.sg_filter(y, 5, 4), y, atol=1e-12)
+    assert np.allclose(att.sg_hat_diag(n, 5, 4), 1.0, atol=1e-12)
+
+
+def test_derivative_psd_matches_fft():
+    n, dw, w0 = 130, 0.01, 0.3
+    w = w0 + dw * np.arange(n)
+    S = np.random.default_rng(2).standard_normal(n)
+    D = (S[2:] - S[:-2]) / (2 * dw)
+    m = len(D)
+    k = np.arange(0, 12)
+    nus = k / (m * dw)
+    ref = np.abs(np.fft.fft(D)[k] / m) ** 2  # |e^{-2 pi i nu w_1}| = 1
+    assert np.allclose(att.derivative_psd(S, w, nus), ref, rtol=1e-12, atol=0)
+
+
+def test_derivative_psd_peaks_at_ripple():
+    w = np.linspace(0.0, 4.0, 801)
+    S = np.sin(2 * np.pi * 2.5 * w)
+    nus = np.linspace(0.5, 5.0, 91)
+    assert abs(nus[np.argmax(att.derivative_psd(S, w, nus))] - 2.5) <= 0.051
+
+
+def test_scores_special_filters():
+    w, S, nu = workloads.rippled_spectrum(n_w=101)
+    n = len(S)
+    # identity (degree w - 1): nothing removed, both penalties 1, AICc infinite
+    Sp, h = att.sg_filter(S, 3, 2), att.sg_hat_diag(n, 3, 2)
+    o = att.sg_scores(S, Sp, h, w, nu)
+    assert o[0] <= 1e-24 and abs(o[1] - n) <= 1e-9 and o[2] == np.inf
+    assert abs(o[3] - 1) <= 1e-9 and abs(o[4] - 1) <= 1e-9
+    # straight-line fit over the whole grid: k = 2, no curvature left, and
+    # the AICc of a 2-parameter model
+    Sp, h = att.sg_filter(S, n, 1), att.sg_hat_diag(n, n, 1)
+    o = att.sg_scores(S, Sp, h, w, nu)
+    line = np.polyval(np.polyfit(w, S, 1), w)
+    rss = np.sum((line - S) ** 2)
+    assert abs(o[1] - 2) <= 1e-10 and abs(o[0] - rss) <= 1e-10 * rss
+    assert abs(o[2] - (n * np.log(rss / n) + 4 + 12 / (n - 3))) <= 1e-9
+    assert o[4] <= 1e-20
+
+
+def _quad_grid(beta, n, half):
+    end = 0.5 * beta if half else beta
+    return np.linspace(0.0, end, n)
+
+
+@pytest.mark.parametrize("half", [False, True])
+def test_residual_closed_form(half):
+    # F_n = a (tau - beta/2)^2 + b: mean a beta^2/12 + b and
+    # sigma_n = |a| beta^{3/2} / sqrt(180)
+    beta, a, b = 2.0, 3e-4, -1e-4
+    t = _quad_grid(beta, 4001 if not half else 2001, half)
+    F_ref = 1.0 + 0.5 * np.cosh(t - 0.5 * beta)
+    Fn = a * (t - 0.5 * beta) ** 2 + b
+    r = att.residual_itcf(F_ref, F_ref - Fn, t, beta)
+    f_half = 1.5
+    assert abs(r[0] - np.max(np.abs(Fn / F_ref))) <= 1e-15
+    assert abs(r[1] - (a * beta ** 2 / 12 + b) / f_half) <= 1e-9
+    assert abs(r[2] - abs(a) * beta ** 1.5 / np.sqrt(180) / f_half) <= 1e-6 * r[2]
+
+
+def test_residual_zero_for_unchanged_itcf():
+    t = np.linspace(0.0, 1.0, 11)
+    F = np.cosh(t - 0.5)
+    assert np.all(att.residual_itcf(F, F, t, 1.0) == 0.0)
+
+
+def test_select_rule():
+    sc = np.array([[0, 0, -100.0, 0.1, 0.1],    # best J, fails sigma
+                   [0, 0, -90.0, 0.1, 0.1],     # passes
+                   [0, 0, -95.0, 0.1, np.nan],  # non-finite J
+                   [0, 0, -80.0, 0.0, 0.0]])    # passes, larger J
+    rs = np.array([[0, 1e-4, 1e-3], [0, 1e-4, 1e-6], [0, 0, 0], [0, 0, 0]])
+    assert att.sg_select(sc, rs, 10, 1.0, 1.0) == 1
+    assert att.sg_select(sc, None, 10, 1.0, 1.0) == 0
+    assert att.sg_select(sc[:1], rs[:1], 10, 1.0, 1.0) == -1
+    # the default weights make the penalties dominate: J = -8 beats -9 + 11
+    assert att.sg_select(sc, rs, 10) == 3
+
+
+def test_grid_search_attenuates_ripple():
+    """End to end on a seeded rippled spectrum: the selected filter removes
+    most of the ripple power and leaves the ITCF within the tolerances."""
+    from oracle.response import itcf
+    w, S, nu = workloads.rippled_spectrum(n_w=301)
+    beta = 20.0
+    taus = np.linspace(0.0, 0.5 * beta, 21)
+    F_ref = itcf(S, w, beta, taus)
+    rows, sc, rs = [], [], []
+    for p in (2, 4):
+        for win in range(p + 3 - (p % 2), 62, 6):
+            if win % 2 == 0:
+                win += 1
+            Sp = att.sg_filter(S, win, p)
+            h = att.sg_hat_diag(len(S), win, p)
+            rows.append((win, p))
+            sc.append(att.sg_scores(S, Sp, h, w, nu))
+            rs.append(att.residual_itcf(F_ref, itcf(Sp, w, beta, taus), taus, beta))
+    sc, rs = np.array(sc), np.array(rs)
+    b = att.sg_select(sc, rs, len(S))
+    assert b >= 0
+    assert sc[b][3] < 0.05, (rows[b], sc[b])
+    assert abs(rs[b][1]) <= 4e-3 and rs[b][2] <= 4.2e-5
+    # unit weights let the AICc keep the ripple: the penalties are what remove it
+    assert sc[att.sg_select(sc, rs, len(S), 1.0, 1.0)][3] > 0.5

@@ -299,3 +299,24 @@ REGISTRY = {
 
 def get(name: str) -> Workload:
     return REGISTRY[name]()
+
+
+def rippled_spectrum(seed: int = 11, n_w: int = 500, omega_max: float = 2.0,
+                     ripple_periods=(0.06, 0.11), ripple_amp: float = 0.03):
+    """A seeded stand-in for a TDDFT S(q, w) with finite-k-grid ringing (the
+    shape of Sec. 3, Fig. 3): a smooth positive spectrum (two Gaussian peaks
+    on the w >= 0 grid, atomic units) plus quasi-periodic ripples of the given
+    periods in w, slowly modulated, plus 1e-4 white noise.  Returns
+    (omega [n_w], S [n_w], ripple frequencies 1/period)."""
+    rng = np.random.default_rng(seed)
+    w = np.linspace(0.0, omega_max, n_w)
+    c1, c2 = omega_max * (0.25 + 0.05 * rng.random()), omega_max * (0.55 + 0.05 * rng.random())
+    s1, s2 = omega_max * 0.08, omega_max * 0.15
+    smooth = np.exp(-0.5 * ((w - c1) / s1) ** 2) + 0.5 * np.exp(-0.5 * ((w - c2) / s2) ** 2)
+    ripple = np.zeros_like(w)
+    for p in ripple_periods:
+        phase = 2.0 * np.pi * rng.random()
+        env = 1.0 + 0.3 * np.sin(2.0 * np.pi * w / omega_max + phase)
+        ripple += ripple_amp * env * np.sin(2.0 * np.pi * w / p + phase)
+    S = smooth * (1.0 + ripple) + 1e-4 * rng.standard_normal(n_w)
+    return w, S, np.array([1.0 / p for p in ripple_periods])
