@@ -62,14 +62,17 @@ def sg_filter(y, w, p):
 
 
 def sg_hat_diag(n, w, p):
-    """Weight of sample i in its own filtered value: the constant-term row of
-    the pseudo-inverse of the window's Vandermonde matrix, at sample i."""
+    """Weight of sample i in its own filtered value: the leverage of sample i
+    in the least-squares fit over its window, i.e. the squared norm of row
+    i - s of an orthonormal basis Q of the polynomials on the window (QR of
+    the Vandermonde matrix, abscissae scaled to [-1, 1] so that Q is
+    accurate at degree 8; the projection Q Q^T does not depend on scaling)."""
     h = np.empty(n)
     for i in range(n):
         s = _window_start(i, n, w)
-        x = np.arange(s, s + w, dtype=np.float64) - i
-        V = np.vander(x, p + 1, increasing=True)
-        h[i] = np.linalg.pinv(V)[0, i - s]
+        x = (np.arange(s, s + w, dtype=np.float64) - (s + 0.5 * (w - 1))) / max(0.5 * (w - 1), 1.0)
+        Q, _ = np.linalg.qr(np.vander(x, p + 1, increasing=True))
+        h[i] = float(Q[i - s] @ Q[i - s])
     return h
 
 

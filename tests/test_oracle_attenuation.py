@@ -45,11 +45,47 @@ def test_hat_diagonal_matches_scipy(w, p):
         assert abs(savgol_filter(e, w, p, mode="interp")[i] - h[i]) <= 1e-12
 
 
+def _exact_leverage(n, w, p, i):
+    """Leverage of sample i in exact rationals: with integer offsets x_j = j - i
+    over its window, the fitted value at i is e_0^T G^{-1} sum_j phi(x_j) y_j
+    with G = sum_j phi(x_j) phi(x_j)^T, so the weight of y_i (phi(0) = e_0) is
+    (G^{-1})_00; G is solved by Gaussian elimination in fractions."""
+    from fractions import Fraction
+    s = min(max(i - w // 2, 0), n - w)
+    xs = [j - i for j in range(s, s + w)]
+    m = p + 1
+    G = [[Fraction(sum(x ** (a + b) for x in xs)) for b in range(m)] + [Fraction(int(a == 0))]
+         for a in range(m)]
+    for c in range(m):
+        r = next(r for r in range(c, m) if G[r][c] != 0)
+        G[c], G[r] = G[r], G[c]
+        for r in range(m):
+            if r != c and G[r][c] != 0:
+                f = G[r][c] / G[c][c]
+                G[r] = [a - f * b for a, b in zip(G[r], G[c])]
+    return float(G[0][m] / G[0][0])
+
+
+@pytest.mark.parametrize("w,p", [(31, 8), (61, 8), (41, 6)])
+def test_hat_diagonal_exact_rational(w, p):
+    """Degree 6-8 over wide windows, where an unscaled fit loses digits."""
+    n = 70
+    h = att.sg_hat_diag(n, w, p)
+    for i in (0, 1, w // 2 - 1, w // 2, n // 2, n - 2, n - 1):
+        assert abs(h[i] - _exact_leverage(n, w, p, i)) <= 1e-12, i
+
+
 def test_projection_traces_and_identity():
     n = 31
     # one window over the whole grid: a projection of rank p + 1
     for p in (0, 1, 4):
         assert abs(att.sg_hat_diag(n, n, p).sum() - (p + 1)) <= 1e-10
+    # the same at degree 8 over a wide grid, and every window's leverages sum
+    # to p + 1 (each is a rank-(p + 1) projection restricted to its window)
+    assert abs(att.sg_hat_diag(499, 499, 8).sum() - 9) <= 1e-10
+    for w in (9, 61):
+        h = att.sg_hat_diag(w, w, 8)
+        assert abs(h.sum() - 9) <= 1e-10 and np.all(h <= 1 + 1e-12)
     # degree w - 1 interpolates: the identity filter
     y = np.random.default_rng(1).standard_normal(n)
     assert np.allclose(att.sg_filter(y, 5, 4), y, atol=1e-12)
