@@ -383,6 +383,33 @@ def main():
     diel = {"ms": d0.elapsed_time(d1), "n_w": int(om0.shape[0]),
             "form": "q0: Im chi by the FDT, Re chi by Kramers-Kronig over the grid, eps^-1, sigma"}
 
+    # attenuation of narrow-band fluctuations on q0's S: the two strongest
+    # peaks of the spectrum of dS/dw as targets, then the whole grid search
+    # (filter bank, scores, F of every filtered S, residual conditions,
+    # per-degree selection)
+    tau0 = setup[0][3]
+    span = float(om0[-1] - om0[0])
+    nus = torch.linspace(4.0 / span, 0.25 * (om0.shape[0] - 1) / span, 400,
+                         dtype=torch.float64, device="cuda")
+    psd = tdx.derivative_psd(ctx, main_q0["S"], om0, nus).cpu().numpy()[0]
+    peaks = [i for i in range(1, len(psd) - 1) if psd[i] >= psd[i - 1] and psd[i] > psd[i + 1]]
+    peaks = sorted(peaks, key=lambda i: -psd[i])[:2]
+    targets = nus[torch.as_tensor(sorted(peaks), dtype=torch.long, device="cuda")]
+    pairs = [(x, p) for p in range(1, 7) for x in range(5, 62, 4) if x > p]
+    windows, degrees = [x for x, _ in pairs], [p for _, p in pairs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    at = tdx.attenuate(ctx, main_q0["S"], om0, beta0, tau0, windows, degrees, targets)
+    torch.cuda.synchronize()
+    dt_att = time.perf_counter() - t0
+    atten = {"ms": dt_att * 1e3, "n_filters": len(windows), "n_w": int(om0.shape[0]),
+             "targets_per_ha": targets.cpu().tolist(),
+             "selected": {str(p): ([windows[b], p] if b >= 0 else None)
+                          for p, b in at.best.items()},
+             "form": "q0: filter bank, scores, F of each filtered S, residual ITCF "
+                     "conditions and per-degree selection (whole search timed)"}
+    log(f"attenuation: {len(windows)} filters in {dt_att * 1e3:.1f} ms")
+
     per_launch = flops_step
     avg_ms = sum(launch_ms) / len(launch_ms)
     line = {
@@ -416,6 +443,7 @@ def main():
         "error_vs_fp64": err,
         "eta_scan": eta_info,
         "dielectric": diel,
+        "attenuation": atten,
         "roofline": {"bound": "mfma", "achieved": per_launch / (avg_ms * 1e-3) / 1e12,
                      "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",
                      "frac": per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec],

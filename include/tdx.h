@@ -419,6 +419,78 @@ int tdx_dielectric(tdx_ctx *ctx, const double *S, const double *omega, int n_w, 
                    tdx_stream stream);
 
 /* ------------------------------------------------------------------ */
+/* Attenuation of narrow-band fluctuations (Sec. 3, Eqs. 3-7, Figs. 3  */
+/* and 4): S = S_p + S_n, S_p from a Savitzky-Golay filter whose       */
+/* window and degree a scored grid search picks, subject to conditions */
+/* on the residual F_n in imaginary time.  All FP64.                   */
+/* ------------------------------------------------------------------ */
+
+/* A bank of n_filt Savitzky-Golay filters applied to S (device [n_w],
+ * samples taken as equally spaced): Sp[f][i] (device [n_filt][n_w]) is the
+ * least-squares polynomial of degree degrees[f] over the windows[f] samples
+ * centred on i, evaluated at i; near the ends the window is moved inside
+ * the grid ([0, w) or [n_w - w, n_w)) and the same fit is evaluated at i.
+ * hdiag (device [n_filt][n_w], may be null) receives the weight of S_i in
+ * its own filtered value (the smoother's diagonal; its sum is the filter's
+ * effective number of parameters).  windows, degrees: host [n_filt]; each
+ * window odd, above its degree and at most n_w; degrees 0..8, else
+ * INVALID_ARG.  Synchronises (the host lists are copied on the stream). */
+int tdx_sg_filter(tdx_ctx *ctx, const double *S, int n_w, const int *windows,
+                  const int *degrees, int n_filt, double *Sp, double *hdiag, tdx_stream stream);
+
+/* Power spectrum of dS/dw, used to find the frequencies of the
+ * fluctuations: with the central difference
+ *   D_i = (S_{i+1} - S_{i-1}) / (w_{i+1} - w_{i-1}),  i = 1 .. n_w - 2,
+ * psd[s][k] = |(1/(n_w - 2)) sum_i D_i exp(-2 pi i nu_k w_i)|^2, nu in
+ * cycles per unit of w.  S: device [n_set][n_w], omega: device [n_w], nu:
+ * device [n_nu], psd: device [n_set][n_nu].  Asynchronous. */
+int tdx_derivative_psd(tdx_ctx *ctx, const double *S, const double *omega, int n_w, int n_set,
+                       const double *nu, int n_nu, double *psd, tdx_stream stream);
+
+/* Scores of each filter of a bank against the unfiltered S (all device):
+ * scores[f] (device [n_filt][5]) = (RSS, k, AICc, P_freq, P_curv) with
+ *   RSS = sum_i (Sp_i - S_i)^2,  k = sum_i hdiag_i,
+ *   AICc = n ln(RSS / n) + 2k + 2k(k+1)/(n - k - 1)  (+inf if n - k - 1 <= 0),
+ *   P_freq = mean over the n_nu target frequencies of the ratio of the
+ *            power of dSp/dw to that of dS/dw (tdx_derivative_psd), 0 if
+ *            n_nu = 0,
+ *   P_curv = sum of squared second differences of Sp over those of S (NaN
+ *            if S has none).
+ * The two penalties are this library's reading of the paper's
+ * frequency-domain and second-derivative penalties, whose forms it does not
+ * give.  n_nu <= 16.  Asynchronous. */
+int tdx_sg_scores(tdx_ctx *ctx, const double *S, const double *Sp, const double *hdiag,
+                  const double *omega, int n_w, int n_filt, const double *nu, int n_nu,
+                  double *scores, tdx_stream stream);
+
+/* Imaginary-time conditions on the residual (Eqs. 5 and 7): for each set s,
+ * F_n = F_ref - F_p[s] on the tau grid (device [n_tau], from 0 to beta or
+ * to beta/2, holding beta/2, as for tdx_itcf_metrics) and
+ *   out[s] = (max_tau |F_n / F_ref|,  Fbar_n / F_ref(beta/2),
+ *             sigma_n / F_ref(beta/2)),
+ *   Fbar_n = (1/beta) int_0^beta F_n dtau,
+ *   sigma_n = (1/beta) (int_0^beta (F_n - Fbar_n)^2 dtau)^{1/2}
+ * (Eq. 7 with its upper limit read as beta), by the trapezoid rule; a grid
+ * ending at beta/2 uses F_n(tau) = F_n(beta - tau).  F_ref: device [n_tau],
+ * F_p: device [n_set][n_tau], out: device [n_set][3]; NaN for a grid of
+ * another form.  Asynchronous. */
+int tdx_residual_itcf(tdx_ctx *ctx, const double *F_ref, const double *F_p, int n_set,
+                      const double *tau, int n_tau, double beta, double *out,
+                      tdx_stream stream);
+
+/* Selection of the grid search (host): the filter with the smallest
+ *   J = AICc / n_w + lam_f P_freq + lam_c P_curv
+ * over scores (host [n_filt][5] from tdx_sg_scores) among those whose
+ * residual (host [n_filt][3] from tdx_residual_itcf, or null for none)
+ * satisfies |Fbar_n / F_ref(beta/2)| <= mean_tol and
+ * sigma_n / F_ref(beta/2) <= sigma_tol; filters with a non-finite J are
+ * skipped.  *best = its index, or -1 if none qualifies.  The weights and
+ * tolerances are the caller's (the paper gives neither); to pick the best
+ * window per degree, call it on each degree's rows. */
+int tdx_sg_select(const double *scores, const double *resid, int n_filt, int n_w, double lam_f,
+                  double lam_c, double mean_tol, double sigma_tol, int *best);
+
+/* ------------------------------------------------------------------ */
 /* Reverse mode: vector-Jacobian products of F(q,tau) (FP64)           */
 /* ------------------------------------------------------------------ */
 

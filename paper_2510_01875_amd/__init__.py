@@ -147,6 +147,16 @@ _metrics = _sig("tdx_itcf_metrics", [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p
 _dielectric = _sig("tdx_dielectric", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
                                       C.c_double, C.c_double, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p])
+_sgf = _sig("tdx_sg_filter", [C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_int),
+                              C.POINTER(C.c_int), C.c_int, C.c_void_p, C.c_void_p, C.c_void_p])
+_dpsd = _sig("tdx_derivative_psd", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                    C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
+_sgs = _sig("tdx_sg_scores", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                              C.c_int, C.c_int, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
+_resid = _sig("tdx_residual_itcf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                                    C.c_int, C.c_double, C.c_void_p, C.c_void_p])
+_sgsel = _sig("tdx_sg_select", [c_dbl_p, c_dbl_p, C.c_int, C.c_int, C.c_double, C.c_double,
+                                C.c_double, C.c_double, C.POINTER(C.c_int)])
 _eta_ref = _sig("tdx_eta_reference", [c_dbl_p, c_dbl_p, C.c_int, C.c_double,
                                       C.POINTER(C.c_int)])
 _itcf_vjp = _sig("tdx_itcf_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
@@ -176,7 +186,7 @@ EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_occupations", "tdx_response_basis", "tdx_transitions",
             "tdx_pair_density_bytes", "tdx_pair_density", "tdx_chi0", "tdx_kernel_matrix",
             "tdx_xc_kernel_grid", "tdx_kernel_matrix_from_grid",
-            "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_dielectric", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
+            "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_dielectric", "tdx_sg_filter", "tdx_derivative_psd", "tdx_sg_scores", "tdx_residual_itcf", "tdx_sg_select", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
             "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
             "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_autotune_chi0", "tdx_tune_save",
             "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async", "tdx_itcf_vjp",
@@ -525,6 +535,97 @@ def dielectric(ctx: Context, S: torch.Tensor, omega: torch.Tensor, beta: float, 
     check(_dielectric(ctx.handle, _ptr(S), _ptr(omega), n, beta, density, q2, _ptr(out[0]),
                       _ptr(out[1]), _ptr(out[2]), _stream(stream)))
     return tuple(out)
+
+
+# ------------------------------------- attenuation of narrow-band fluctuations
+SG_SCORES = ("RSS", "k", "AICc", "P_freq", "P_curv")
+RESIDUAL = ("max|F_n/F|", "Fbar_n/F(beta/2)", "sigma_n/F(beta/2)")
+
+
+def sg_filter(ctx: Context, S: torch.Tensor, windows, degrees, stream=None):
+    """(Sp, hdiag) [n_filt][n_w]: a bank of Savitzky-Golay filters applied to S
+    and the smoother diagonals (Sec. 3; tdx.h)."""
+    n = S.shape[0]
+    win = (C.c_int * len(windows))(*[int(x) for x in windows])
+    deg = (C.c_int * len(degrees))(*[int(x) for x in degrees])
+    if len(windows) != len(degrees):
+        raise ValueError("windows and degrees differ in length")
+    Sp = torch.empty((len(windows), n), dtype=torch.float64, device=S.device)
+    hd = torch.empty_like(Sp)
+    check(_sgf(ctx.handle, _ptr(S.contiguous()), n, win, deg, len(windows), _ptr(Sp), _ptr(hd),
+               _stream(stream)))
+    return Sp, hd
+
+
+def derivative_psd(ctx: Context, S: torch.Tensor, omega: torch.Tensor, nu: torch.Tensor,
+                   stream=None) -> torch.Tensor:
+    """[n_set][n_nu] power of dS/dw at the frequencies nu (Sec. 3, Fig. 3)."""
+    S = S.reshape(-1, omega.shape[0]).contiguous()
+    out = torch.empty((S.shape[0], nu.shape[0]), dtype=torch.float64, device=S.device)
+    check(_dpsd(ctx.handle, _ptr(S), _ptr(omega), omega.shape[0], S.shape[0], _ptr(nu),
+                nu.shape[0], _ptr(out), _stream(stream)))
+    return out
+
+
+def sg_scores(ctx: Context, S: torch.Tensor, Sp: torch.Tensor, hdiag: torch.Tensor,
+              omega: torch.Tensor, nu: torch.Tensor, stream=None) -> torch.Tensor:
+    """[n_filt][5] scores (SG_SCORES) of a filter bank (Sec. 3; tdx.h)."""
+    out = torch.empty((Sp.shape[0], 5), dtype=torch.float64, device=S.device)
+    check(_sgs(ctx.handle, _ptr(S), _ptr(Sp), _ptr(hdiag), _ptr(omega), omega.shape[0],
+               Sp.shape[0], _ptr(nu) if nu.numel() else None, nu.shape[0], _ptr(out),
+               _stream(stream)))
+    return out
+
+
+def residual_itcf(ctx: Context, F_ref: torch.Tensor, F_p: torch.Tensor, tau: torch.Tensor,
+                  beta: float, stream=None) -> torch.Tensor:
+    """[n_set][3] conditions (RESIDUAL) on F_n = F_ref - F_p (Eqs. 5 and 7)."""
+    F_p = F_p.reshape(-1, tau.shape[0]).contiguous()
+    out = torch.empty((F_p.shape[0], 3), dtype=torch.float64, device=F_p.device)
+    check(_resid(ctx.handle, _ptr(F_ref), _ptr(F_p), F_p.shape[0], _ptr(tau), tau.shape[0],
+                 beta, _ptr(out), _stream(stream)))
+    return out
+
+
+def sg_select(scores, resid, n_w: int, lam_f: float = 100.0, lam_c: float = 10.0,
+              mean_tol: float = 4e-3, sigma_tol: float = 4.2e-5) -> int:
+    """Index of the selected filter, or -1 (tdx.h)."""
+    sc = np.ascontiguousarray(np.asarray(scores, dtype=np.float64))
+    rs = None if resid is None else np.ascontiguousarray(np.asarray(resid, dtype=np.float64))
+    best = C.c_int(-1)
+    check(_sgsel(sc.ctypes.data_as(c_dbl_p), None if rs is None else rs.ctypes.data_as(c_dbl_p),
+                 sc.shape[0], n_w, lam_f, lam_c, mean_tol, sigma_tol, C.byref(best)))
+    return best.value
+
+
+@dataclass
+class Attenuation:
+    Sp: torch.Tensor          # [n_filt][n_w] filtered spectra
+    scores: torch.Tensor      # [n_filt][5] (SG_SCORES)
+    resid: torch.Tensor       # [n_filt][3] (RESIDUAL)
+    best: dict                # degree -> index of its selected filter (or -1)
+
+
+def attenuate(ctx: Context, S: torch.Tensor, omega: torch.Tensor, beta: float,
+              tau: torch.Tensor, windows, degrees, nu: torch.Tensor, lam_f: float = 100.0,
+              lam_c: float = 10.0, mean_tol: float = 4e-3, sigma_tol: float = 4.2e-5,
+              stream=None) -> Attenuation:
+    """The grid search of Sec. 3 over the (window, degree) pairs: filter bank,
+    scores, F of every filtered spectrum (Eq. 1), the residual conditions
+    (Eqs. 5 and 7) and the selected window of each degree."""
+    Sp, hd = sg_filter(ctx, S, windows, degrees, stream)
+    sc = sg_scores(ctx, S, Sp, hd, omega, nu, stream)
+    F_ref = itcf(ctx, S, omega, beta, tau, stream)
+    F_p = torch.stack([itcf(ctx, Sp[f], omega, beta, tau, stream) for f in range(Sp.shape[0])])
+    rs = residual_itcf(ctx, F_ref, F_p, tau, beta, stream)
+    sc_h, rs_h = sc.cpu().numpy(), rs.cpu().numpy()
+    deg = np.asarray(degrees)
+    best = {}
+    for d in sorted(set(int(x) for x in degrees)):
+        rows = np.nonzero(deg == d)[0]
+        b = sg_select(sc_h[rows], rs_h[rows], S.shape[0], lam_f, lam_c, mean_tol, sigma_tol)
+        best[d] = int(rows[b]) if b >= 0 else -1
+    return Attenuation(Sp, sc, rs, best)
 
 
 # ------------------------------------------------------------ reverse mode

@@ -58,7 +58,7 @@ struct tdx_ctx {
   int n_cu = 0;
   rocblas_handle blas = nullptr;
   size_t limit = 0;  // 0 = unlimited
-  tdx::Workspace ws[12];
+  tdx::Workspace ws[13];
   tdx_chi0_tune tune[64];
 };
 
@@ -77,6 +77,7 @@ enum WsSlot {
   WS_ADJ2 = 9,      // adjoint: eigen-adjoint products
   WS_ADJ3 = 10,     // adjoint: reductions
   WS_FXC = 11,      // f_xc(G) grid of the composed kernel-matrix call
+  WS_SG = 12,       // window and degree lists of a Savitzky-Golay filter bank
 };
 
 size_t ws_total(const tdx_ctx *ctx);

@@ -1,0 +1,146 @@
+"""Attenuation of narrow-band fluctuations on the GPU (Sec. 3, Eqs. 3-7): the
+Savitzky-Golay bank, its smoother diagonals, the derivative spectrum, the
+scores, the residual ITCF conditions and the selection against the oracle on
+a seeded rippled spectrum of 500 frequencies (the frequency count of the fcc
+workload), FP64 to 1e-10."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+# (window, degree): every degree 0..8, windows from the identity (degree
+# w - 1) and a single sample to the whole grid
+BANK = [(1, 0), (3, 2), (9, 8), (5, 1), (31, 0), (11, 2), (41, 2), (61, 3), (25, 4),
+        (57, 4), (33, 5), (45, 6), (61, 7), (61, 8), (21, 8), (499, 3), (499, 8)]
+
+
+@pytest.fixture(scope="module")
+def tdx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_01875_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def case():
+    return workloads.rippled_spectrum(seed=11, n_w=500)
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def test_filter_bank_matches_oracle(tdx, case):
+    from oracle import attenuation as att
+    w, S, nu = case
+    ctx = tdx.Context(0)
+    Sp, hd = tdx.sg_filter(ctx, _dev(S), [b[0] for b in BANK], [b[1] for b in BANK])
+    Sp, hd = Sp.cpu().numpy(), hd.cpu().numpy()
+    scale = np.max(np.abs(S))
+    for f, (win, p) in enumerate(BANK):
+        ref = att.sg_filter(S, win, p)
+        assert np.max(np.abs(Sp[f] - ref)) <= 1e-10 * scale, (win, p)
+        h = att.sg_hat_diag(len(S), win, p)
+        assert np.max(np.abs(hd[f] - h)) <= 1e-10, (win, p)
+    ctx.close()
+
+
+def test_scores_and_spectrum_match_oracle(tdx, case):
+    from oracle import attenuation as att
+    w, S, nu = case
+    ctx = tdx.Context(0)
+    Sd, wd = _dev(S), _dev(w)
+    grid = np.linspace(0.5, 30.0, 60)
+    psd = tdx.derivative_psd(ctx, Sd, wd, _dev(grid)).cpu().numpy()[0]
+    ref = att.derivative_psd(S, w, grid)
+    assert np.max(np.abs(psd - ref)) <= 1e-10 * np.max(ref)
+    Sp, hd = tdx.sg_filter(ctx, Sd, [b[0] for b in BANK], [b[1] for b in BANK])
+    sc = tdx.sg_scores(ctx, Sd, Sp, hd, wd, _dev(nu)).cpu().numpy()
+    for f, (win, p) in enumerate(BANK):
+        o = att.sg_scores(S, att.sg_filter(S, win, p), att.sg_hat_diag(len(S), win, p), w, nu)
+        # RSS of the identity filters is rounding only
+        assert abs(sc[f, 0] - o[0]) <= 1e-9 * o[0] + 1e-24, (win, p)
+        assert abs(sc[f, 1] - o[1]) <= 1e-9 * len(S), (win, p)
+        if np.isinf(o[2]):
+            assert np.isinf(sc[f, 2]) and sc[f, 2] > 0, (win, p)
+        else:
+            assert abs(sc[f, 2] - o[2]) <= 1e-8 * abs(o[2]), (win, p)
+        assert abs(sc[f, 3] - o[3]) <= 1e-9 * max(o[3], 1e-6), (win, p)
+        assert abs(sc[f, 4] - o[4]) <= 1e-9 * max(o[4], 1e-12), (win, p)
+    # no targets: the frequency penalty is 0
+    import torch
+    sc0 = tdx.sg_scores(ctx, Sd, Sp, hd, wd, torch.empty(0, dtype=torch.float64,
+                                                         device="cuda")).cpu().numpy()
+    assert np.all(sc0[:, 3] == 0.0)
+    ctx.close()
+
+
+@pytest.mark.parametrize("half", [False, True])
+def test_residual_matches_oracle(tdx, case, half):
+    from oracle import attenuation as att
+    from oracle.response import itcf
+    w, S, nu = case
+    beta = 20.0
+    taus = np.linspace(0.0, 0.5 * beta if half else beta, 21 if half else 41)
+    F_ref = itcf(S, w, beta, taus)
+    F_p = np.stack([itcf(att.sg_filter(S, win, p), w, beta, taus)
+                    for win, p in [(11, 2), (41, 2), (25, 4), (61, 8)]])
+    ctx = tdx.Context(0)
+    out = tdx.residual_itcf(ctx, _dev(F_ref), _dev(F_p), _dev(taus), beta).cpu().numpy()
+    f_half = F_ref[np.argmin(np.abs(taus - 0.5 * beta))]
+    for s in range(F_p.shape[0]):
+        ref = att.residual_itcf(F_ref, F_p[s], taus, beta)
+        # the mean of F_n can cancel: its rounding scales with |F_n|, not the mean
+        scale = np.max(np.abs(F_ref - F_p[s])) / f_half
+        assert np.all(np.abs(out[s] - ref) <= 1e-10 * np.abs(ref) + 1e-13 * scale), (s, out[s], ref)
+    # a grid that does not hold beta/2 gives NaN
+    bad = np.linspace(0.0, beta, 40)
+    o = tdx.residual_itcf(ctx, _dev(itcf(S, w, beta, bad)), _dev(itcf(S, w, beta, bad)),
+                          _dev(bad), beta).cpu().numpy()
+    assert np.all(np.isnan(o))
+    ctx.close()
+
+
+def test_attenuate_selects_as_oracle(tdx, case):
+    """The whole grid search through the library (filter bank, scores, F of
+    every filtered spectrum, residual conditions, per-degree selection)
+    against the oracle's: the same filter for every degree."""
+    from oracle import attenuation as att
+    from oracle.response import itcf
+    w, S, nu = case
+    beta = 20.0
+    taus = np.linspace(0.0, 0.5 * beta, 21)
+    wins = [5, 11, 17, 23, 29, 35, 41, 47, 53, 59]
+    windows = [x for p in (2, 4) for x in wins if x > p]
+    degrees = [p for p in (2, 4) for x in wins if x > p]
+    ctx = tdx.Context(0)
+    r = tdx.attenuate(ctx, _dev(S), _dev(w), beta, _dev(taus), windows, degrees, _dev(nu))
+    F_ref = itcf(S, w, beta, taus)
+    for p in (2, 4):
+        rows = [f for f in range(len(windows)) if degrees[f] == p]
+        sc, rs = [], []
+        for f in rows:
+            Sp = att.sg_filter(S, windows[f], p)
+            sc.append(att.sg_scores(S, Sp, att.sg_hat_diag(len(S), windows[f], p), w, nu))
+            rs.append(att.residual_itcf(F_ref, itcf(Sp, w, beta, taus), taus, beta))
+        b = att.sg_select(np.array(sc), np.array(rs), len(S))
+        assert r.best[p] == (rows[b] if b >= 0 else -1), (p, r.best, windows[rows[b]])
+    assert any(v >= 0 for v in r.best.values())
+    # the host selection entry point on the oracle's own scores
+    assert tdx.sg_select(np.array(sc), np.array(rs), len(S)) == b
+    ctx.close()
+
+
+def test_filter_rejects_bad_windows(tdx, case):
+    w, S, nu = case
+    ctx = tdx.Context(0)
+    Sd = _dev(S)
+    for win, p in [(4, 1), (3, 3), (501, 2), (11, 9), (11, -1)]:
+        with pytest.raises(RuntimeError):
+            tdx.sg_filter(ctx, Sd, [win], [p])
+    ctx.close()
