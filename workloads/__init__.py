@@ -320,3 +320,24 @@ def rippled_spectrum(seed: int = 11, n_w: int = 500, omega_max: float = 2.0,
         ripple += ripple_amp * env * np.sin(2.0 * np.pi * w / p + phase)
     S = smooth * (1.0 + ripple) + 1e-4 * rng.standard_normal(n_w)
     return w, S, np.array([1.0 / p for p in ripple_periods])
+
+
+def kg_conductivity(seed: int = 13, n_w: int = 500, omega_max: float = 2.0,
+                    ripple_period: float = 0.05, ripple_amp: float = 0.03):
+    """A seeded stand-in for a Kubo-Greenwood conductivity sigma(w) of a warm
+    metal with finite-k-grid ringing (Sec. A.3): a Drude term
+    sigma_D / (1 - i w tau) plus two bound-bound oscillators
+    (f / 4 pi) (-i w) / (w0^2 - w^2 - i w gamma), its real part rippled with
+    the given period (atomic units, w >= 0 grid).  Returns (omega [n_w],
+    sigma [n_w] complex128)."""
+    rng = np.random.default_rng(seed)
+    w = np.linspace(0.0, omega_max, n_w)
+    tau = 8.0 + 4.0 * rng.random()
+    sig = (0.05 + 0.02 * rng.random()) / (1.0 - 1j * w * tau)
+    for w0, g in ((0.6 * omega_max, 0.05), (0.8 * omega_max, 0.08)):
+        f = 0.02 + 0.02 * rng.random()
+        sig = sig + (f / (4.0 * np.pi)) * (-1j * w) / (w0 ** 2 - w ** 2 - 1j * w * g)
+    phase = 2.0 * np.pi * rng.random()
+    sig = sig.real * (1.0 + ripple_amp * np.sin(2.0 * np.pi * w / ripple_period + phase)) \
+        + 1j * sig.imag
+    return w, sig.astype(np.complex128)
