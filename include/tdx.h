@@ -491,6 +491,24 @@ int tdx_sg_select(const double *scores, const double *resid, int n_filt, int n_w
                   double lam_c, double mean_tol, double sigma_tol, int *best);
 
 /* ------------------------------------------------------------------ */
+/* Kubo-Greenwood route (Sec. A.3, with Eqs. 8, A-1, A-2)               */
+/* ------------------------------------------------------------------ */
+
+/* The scaled structure factor S* = v(q) S of the optical limit from a
+ * conductivity sigma (device complex128 [n_w], e.g. a Kubo-Greenwood
+ * calculation's) on the grid omega (device [n_w], w >= 0):
+ *   eps = 1 + 4 pi i sigma / w,  chi* = 1/eps - 1,
+ *   S* = -Im chi* / (pi n (1 - e^{-beta w}))
+ * (the normalisation of tdx_dsf; w = 0 takes the limit from the next grid
+ * point, NaN without one).  S*: device [n_w].  F* (tdx_itcf), the eta
+ * metrics, the attenuation and the way back run on S* unchanged; the way
+ * back (Re chi* by Kramers-Kronig, eps^{-1} = 1 + chi*,
+ * sigma = i w (1 - eps) / (4 pi)) is tdx_dielectric with q2 = 4 pi.
+ * Asynchronous. */
+int tdx_kg_dsf(tdx_ctx *ctx, const double *sigma, const double *omega, int n_w, double beta,
+               double density, double *S_star, tdx_stream stream);
+
+/* ------------------------------------------------------------------ */
 /* Reverse mode: vector-Jacobian products of F(q,tau) (FP64)           */
 /* ------------------------------------------------------------------ */
 

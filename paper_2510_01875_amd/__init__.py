@@ -157,6 +157,8 @@ _resid = _sig("tdx_residual_itcf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
                                     C.c_int, C.c_double, C.c_void_p, C.c_void_p])
 _sgsel = _sig("tdx_sg_select", [c_dbl_p, c_dbl_p, C.c_int, C.c_int, C.c_double, C.c_double,
                                 C.c_double, C.c_double, C.POINTER(C.c_int)])
+_kgdsf = _sig("tdx_kg_dsf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
+                            C.c_double, C.c_void_p, C.c_void_p])
 _eta_ref = _sig("tdx_eta_reference", [c_dbl_p, c_dbl_p, C.c_int, C.c_double,
                                       C.POINTER(C.c_int)])
 _itcf_vjp = _sig("tdx_itcf_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
@@ -186,7 +188,7 @@ EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_occupations", "tdx_response_basis", "tdx_transitions",
             "tdx_pair_density_bytes", "tdx_pair_density", "tdx_chi0", "tdx_kernel_matrix",
             "tdx_xc_kernel_grid", "tdx_kernel_matrix_from_grid",
-            "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_dielectric", "tdx_sg_filter", "tdx_derivative_psd", "tdx_sg_scores", "tdx_residual_itcf", "tdx_sg_select", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
+            "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_dielectric", "tdx_sg_filter", "tdx_derivative_psd", "tdx_sg_scores", "tdx_residual_itcf", "tdx_sg_select", "tdx_kg_dsf", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
             "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
             "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_autotune_chi0", "tdx_tune_save",
             "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async", "tdx_itcf_vjp",
@@ -626,6 +628,27 @@ def attenuate(ctx: Context, S: torch.Tensor, omega: torch.Tensor, beta: float,
         b = sg_select(sc_h[rows], rs_h[rows], S.shape[0], lam_f, lam_c, mean_tol, sigma_tol)
         best[d] = int(rows[b]) if b >= 0 else -1
     return Attenuation(Sp, sc, rs, best)
+
+
+# ---------------------------------------------------- Kubo-Greenwood route
+KG_Q2 = 4.0 * math.pi  # the dielectric step at this q^2 gives eps^{-1} = 1 + chi*
+
+
+def kg_dsf(ctx: Context, sigma: torch.Tensor, omega: torch.Tensor, beta: float, density: float,
+           stream=None) -> torch.Tensor:
+    """S* = v(q) S [n_w] of the optical limit from a conductivity sigma
+    (complex128 [n_w]) (Sec. A.3; tdx.h)."""
+    S = torch.empty(omega.shape[0], dtype=torch.float64, device=omega.device)
+    check(_kgdsf(ctx.handle, _ptr(sigma.contiguous()), _ptr(omega), omega.shape[0], beta,
+                 density, _ptr(S), _stream(stream)))
+    return S
+
+
+def kg_dielectric(ctx: Context, S_star: torch.Tensor, omega: torch.Tensor, beta: float,
+                  density: float, stream=None):
+    """(chi*, eps^{-1}, sigma) from S*: Re chi* by Kramers-Kronig,
+    eps^{-1} = 1 + chi*, sigma = i w (1 - eps) / (4 pi) (Sec. A.3)."""
+    return dielectric(ctx, S_star, omega, beta, density, KG_Q2, stream)
 
 
 # ------------------------------------------------------------ reverse mode
