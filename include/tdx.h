@@ -422,7 +422,9 @@ int tdx_dielectric(tdx_ctx *ctx, const double *S, const double *omega, int n_w, 
 /* Attenuation of narrow-band fluctuations (Sec. 3, Eqs. 3-7, Figs. 3  */
 /* and 4): S = S_p + S_n, S_p from a Savitzky-Golay filter whose       */
 /* window and degree a scored grid search picks, subject to conditions */
-/* on the residual F_n in imaginary time.  All FP64.                   */
+/* on the residual F_n in imaginary time.  All FP64.  With a zero     */
+/* filter, set or frequency count the outputs may be null and nothing  */
+/* is written.                                                        */
 /* ------------------------------------------------------------------ */
 
 /* A bank of n_filt Savitzky-Golay filters applied to S (device [n_w],

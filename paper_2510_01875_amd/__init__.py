@@ -618,7 +618,9 @@ def attenuate(ctx: Context, S: torch.Tensor, omega: torch.Tensor, beta: float,
     Sp, hd = sg_filter(ctx, S, windows, degrees, stream)
     sc = sg_scores(ctx, S, Sp, hd, omega, nu, stream)
     F_ref = itcf(ctx, S, omega, beta, tau, stream)
-    F_p = torch.stack([itcf(ctx, Sp[f], omega, beta, tau, stream) for f in range(Sp.shape[0])])
+    F_p = (torch.stack([itcf(ctx, Sp[f], omega, beta, tau, stream) for f in range(Sp.shape[0])])
+           if Sp.shape[0] else torch.empty((0, tau.shape[0]), dtype=torch.float64,
+                                           device=S.device))
     rs = residual_itcf(ctx, F_ref, F_p, tau, beta, stream)
     sc_h, rs_h = sc.cpu().numpy(), rs.cpu().numpy()
     deg = np.asarray(degrees)

@@ -253,7 +253,8 @@ extern "C" {
 int tdx_sg_filter(tdx_ctx *ctx, const double *S, int n_w, const int *windows,
                   const int *degrees, int n_filt, double *Sp, double *hdiag, tdx_stream stream) {
   clear_error();
-  TDX_REQUIRE(ctx && S && windows && degrees && Sp, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(ctx && S && (n_filt == 0 || (windows && degrees && Sp)), TDX_ERR_INVALID_ARG,
+              "null argument");
   TDX_REQUIRE(n_w > 0 && n_filt >= 0, TDX_ERR_SHAPE, "bad sizes");
   for (int f = 0; f < n_filt; ++f) {
     const int w = windows[f], p = degrees[f];
@@ -282,7 +283,8 @@ int tdx_sg_filter(tdx_ctx *ctx, const double *S, int n_w, const int *windows,
 int tdx_derivative_psd(tdx_ctx *ctx, const double *S, const double *omega, int n_w, int n_set,
                        const double *nu, int n_nu, double *psd, tdx_stream stream) {
   clear_error();
-  TDX_REQUIRE(ctx && S && omega && nu && psd, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(ctx && S && omega && ((n_set == 0 || n_nu == 0) || (nu && psd)),
+              TDX_ERR_INVALID_ARG, "null argument");
   TDX_REQUIRE(n_w >= 3 && n_set >= 0 && n_nu >= 0, TDX_ERR_SHAPE, "bad sizes");
   TDX_TRY(check_device(ctx));
   if (n_set == 0 || n_nu == 0) return TDX_OK;
@@ -296,7 +298,7 @@ int tdx_sg_scores(tdx_ctx *ctx, const double *S, const double *Sp, const double 
                   const double *omega, int n_w, int n_filt, const double *nu, int n_nu,
                   double *scores, tdx_stream stream) {
   clear_error();
-  TDX_REQUIRE(ctx && S && Sp && hdiag && omega && scores && (nu || n_nu == 0),
+  TDX_REQUIRE(ctx && S && omega && (nu || n_nu == 0) && (n_filt == 0 || (Sp && hdiag && scores)),
               TDX_ERR_INVALID_ARG, "null argument");
   TDX_REQUIRE(n_w >= 3 && n_filt >= 0, TDX_ERR_SHAPE, "bad sizes");
   TDX_REQUIRE(n_nu >= 0 && n_nu <= kMaxTargets, TDX_ERR_SHAPE, "at most %d target frequencies",
@@ -313,7 +315,8 @@ int tdx_residual_itcf(tdx_ctx *ctx, const double *F_ref, const double *F_p, int 
                       const double *tau, int n_tau, double beta, double *out,
                       tdx_stream stream) {
   clear_error();
-  TDX_REQUIRE(ctx && F_ref && F_p && tau && out, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(ctx && F_ref && tau && (n_set == 0 || (F_p && out)), TDX_ERR_INVALID_ARG,
+              "null argument");
   TDX_REQUIRE(n_tau > 1 && n_set >= 0, TDX_ERR_SHAPE, "bad sizes");
   TDX_REQUIRE(std::isfinite(beta) && beta > 0, TDX_ERR_INVALID_ARG, "bad beta");
   TDX_TRY(check_device(ctx));
@@ -327,7 +330,7 @@ int tdx_residual_itcf(tdx_ctx *ctx, const double *F_ref, const double *F_p, int 
 int tdx_sg_select(const double *scores, const double *resid, int n_filt, int n_w, double lam_f,
                   double lam_c, double mean_tol, double sigma_tol, int *best) {
   clear_error();
-  TDX_REQUIRE(scores && best, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(best && (scores || n_filt == 0), TDX_ERR_INVALID_ARG, "null argument");
   TDX_REQUIRE(n_filt >= 0 && n_w > 0, TDX_ERR_SHAPE, "bad sizes");
   TDX_REQUIRE(std::isfinite(lam_f) && lam_f >= 0 && std::isfinite(lam_c) && lam_c >= 0,
               TDX_ERR_INVALID_ARG, "penalty weights must be finite and non-negative");

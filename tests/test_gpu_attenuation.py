@@ -144,3 +144,24 @@ def test_filter_rejects_bad_windows(tdx, case):
         with pytest.raises(RuntimeError):
             tdx.sg_filter(ctx, Sd, [win], [p])
     ctx.close()
+
+
+def test_empty_inputs(tdx, case):
+    """No filters, no target or spectrum frequencies, no residual sets: empty
+    outputs, nothing launched, and no filter selected."""
+    import torch
+    w, S, nu = case
+    ctx = tdx.Context(0)
+    Sd, wd = _dev(S), _dev(w)
+    none = torch.empty(0, dtype=torch.float64, device="cuda")
+    Sp, hd = tdx.sg_filter(ctx, Sd, [], [])
+    assert Sp.shape == (0, len(S))
+    assert tdx.sg_scores(ctx, Sd, Sp, hd, wd, _dev(nu)).shape == (0, 5)
+    assert tdx.derivative_psd(ctx, Sd, wd, none).shape == (1, 0)
+    taus = _dev(np.linspace(0.0, 10.0, 11))
+    F = tdx.itcf(ctx, Sd, wd, 20.0, taus)
+    empty_sets = torch.empty((0, 11), dtype=torch.float64, device="cuda")
+    assert tdx.residual_itcf(ctx, F, empty_sets, taus, 20.0).shape == (0, 3)
+    assert tdx.sg_select(np.zeros((0, 5)), None, len(S)) == -1
+    assert tdx.attenuate(ctx, Sd, wd, 20.0, taus, [], [], _dev(nu)).best == {}
+    ctx.close()
