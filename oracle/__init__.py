@@ -15,9 +15,16 @@ quantities the GPU path computes, written from their definitions:
   * fluctuation-dissipation theorem, Eq. (8), with detailed balance,
   * two-sided Laplace transform to the ITCF, Eq. (1).
 
+and, on top of S and F: the eta-convergence metrics and reference eta
+(Sec. 2, Eq. 2; ``eta``), the constraints-based attenuation of narrow-band
+fluctuations (Sec. 3, Eqs. 3-7; ``attenuation``), the dielectric properties
+from S (Eqs. A-1, A-2; ``dielectric``) and the Kubo-Greenwood route
+(Sec. A.3; ``kubo_greenwood``).
+
 It shares no code with the HIP path; only ``workloads`` (seeded problem
 definitions) serves both.  Library primitives used as single steps: dense
-matrix products, ``numpy.linalg.eigh``/``solve`` and ``numpy.fft``.
+matrix products, ``numpy.linalg.eigh``/``solve``/``qr``, ``numpy.polyfit``
+and ``numpy.fft``.
 
 Each function's pins (closed forms, sum rules, symmetries, brute force) live
 in ``tests/test_oracle_*.py``.  Functions with no independent pin say
