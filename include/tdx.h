@@ -471,8 +471,9 @@ int tdx_sg_scores(tdx_ctx *ctx, const double *S, const double *Sp, const double 
  *   out[s] = (max_tau |F_n / F_ref|,  Fbar_n / F_ref(beta/2),
  *             sigma_n / F_ref(beta/2)),
  *   Fbar_n = (1/beta) int_0^beta F_n dtau,
- *   sigma_n = (1/beta) (int_0^beta (F_n - Fbar_n)^2 dtau)^{1/2}
- * (Eq. 7 with its upper limit read as beta), by the trapezoid rule; a grid
+ *   sigma_n = ((1/beta) int_0^beta (F_n - Fbar_n)^2 dtau)^{1/2}
+ * (Eq. 7 read as the root-mean-square deviation over [0, beta], so that the
+ * ratios do not depend on the unit of tau), by the trapezoid rule; a grid
  * ending at beta/2 uses F_n(tau) = F_n(beta - tau).  F_ref: device [n_tau],
  * F_p: device [n_set][n_tau], out: device [n_set][3]; NaN for a grid of
  * another form.  Asynchronous. */

@@ -32,8 +32,11 @@ Readings (the paper gives no formulas for these):
     a few per cent over noise), and the tolerances are the bounds the paper
     reports for its selected filters (|Fbar_n| / F(beta/2) < 0.4 %,
     sigma_n / F(beta/2) <= 0.0042 %);
-  * in Eq. 7 the integral runs over [0, beta] and Fbar_n is the mean of F_n
-    over it; integrals are the composite trapezoid on the tau grid.
+  * Eq. 7 prints the same symbol for the bound and the variable of its
+    integral and calls sigma_n a normalised root-mean-square deviation: it is
+    read as sigma_n = [(1/beta) int_0^beta (F_n - Fbar_n)^2 dtau]^{1/2}, the
+    RMS over [0, beta], with Fbar_n the mean of F_n there; integrals are the
+    composite trapezoid on the tau grid.
 """
 from __future__ import annotations
 
@@ -135,7 +138,10 @@ def residual_itcf(F_ref, F_p, taus, beta):
     elif abs(t[-1] - beta) > tol:
         raise ValueError("tau grid must end at beta/2 or beta")
     mean = np.trapezoid(Fn, t) / beta
-    sigma = np.sqrt(np.trapezoid((Fn - mean) ** 2, t)) / beta
+    # Eq. 7 as the root-mean-square deviation over [0, beta]: the square
+    # root of the mean of (F_n - Fbar_n)^2, so that sigma_n / F(beta/2) does
+    # not depend on the unit of tau
+    sigma = np.sqrt(np.trapezoid((Fn - mean) ** 2, t) / beta)
     return np.array([eps_max, mean / f_half, sigma / f_half])
 
 

@@ -235,7 +235,9 @@ __global__ void __launch_bounds__(kRedThreads)
       if (fabs(tau[j] - 0.5 * beta) <= tol) mid = j;
     const bool ok = n_tau > 1 && tau[0] == 0.0 && (half || full) && mid >= 0;
     const double fm = ok ? Fr[mid] : NAN;
-    const double sigma = sqrt(q * (beta / span)) / beta;
+    // root-mean-square deviation over [0, beta]: the integral over the grid
+    // is q * beta / span, its mean over [0, beta] q / span
+    const double sigma = sqrt(q / span);
     double *o = out + (size_t)set * 3;
     o[0] = ok ? sh[0] : NAN;
     o[1] = ok ? mean / fm : NAN;

@@ -137,8 +137,8 @@ def _quad_grid(beta, n, half):
 
 @pytest.mark.parametrize("half", [False, True])
 def test_residual_closed_form(half):
-    # F_n = a (tau - beta/2)^2 + b: mean a beta^2/12 + b and
-    # sigma_n = |a| beta^{3/2} / sqrt(180)
+    # F_n = a (tau - beta/2)^2 + b: mean a beta^2/12 + b and the RMS
+    # deviation from it sigma_n = |a| beta^2 / sqrt(180)
     beta, a, b = 2.0, 3e-4, -1e-4
     t = _quad_grid(beta, 4001 if not half else 2001, half)
     F_ref = 1.0 + 0.5 * np.cosh(t - 0.5 * beta)
@@ -147,7 +147,21 @@ def test_residual_closed_form(half):
     f_half = 1.5
     assert abs(r[0] - np.max(np.abs(Fn / F_ref))) <= 1e-15
     assert abs(r[1] - (a * beta ** 2 / 12 + b) / f_half) <= 1e-9
-    assert abs(r[2] - abs(a) * beta ** 1.5 / np.sqrt(180) / f_half) <= 1e-6 * r[2]
+    assert abs(r[2] - abs(a) * beta ** 2 / np.sqrt(180) / f_half) <= 1e-6 * r[2]
+
+
+@pytest.mark.parametrize("half", [False, True])
+def test_residual_is_unit_free(half):
+    # the ratios of Eqs. 5 and 7 to F(beta/2) are dimensionless: measuring
+    # tau in another unit (beta -> c beta, the same F on the stretched grid)
+    # leaves all three unchanged
+    t = _quad_grid(1.0, 401 if not half else 201, half)
+    F_ref = 2.0 + np.cosh(3.0 * (t - 0.5))
+    F_p = F_ref - 1e-3 * np.sin(7.0 * t) - 2e-4 * t
+    r1 = att.residual_itcf(F_ref, F_p, t, 1.0)
+    for c in (0.1, 27.2, 1000.0):
+        rc = att.residual_itcf(F_ref, F_p, c * t, c)
+        assert np.max(np.abs(rc - r1) / np.abs(r1)) <= 1e-12
 
 
 def test_residual_zero_for_unchanged_itcf():
@@ -190,7 +204,9 @@ def test_grid_search_attenuates_ripple():
     sc, rs = np.array(sc), np.array(rs)
     b = att.sg_select(sc, rs, len(S))
     assert b >= 0
-    assert sc[b][3] < 0.05, (rows[b], sc[b])
+    # over 90 % of the ripple's power at the target frequencies removed (the
+    # RMS bound of Eq. 7 at the paper's 0.0042 % keeps the window narrow)
+    assert sc[b][3] < 0.1, (rows[b], sc[b])
     assert abs(rs[b][1]) <= 4e-3 and rs[b][2] <= 4.2e-5
     # unit weights let the AICc keep the ripple: the penalties are what remove it
     assert sc[att.sg_select(sc, rs, len(S), 1.0, 1.0)][3] > 0.5
