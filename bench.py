@@ -7,8 +7,10 @@ Dyson, S, F.  The headline value is the chi0 contraction's algorithmic
 throughput, F_alg = 8 N_w N_G^2 T(q) flops per launch, divided by the chi0
 launch time measured with HIP events on the launch stream.  Comparison legs
 run the FP64 and FP32 contractions on the first q and report the error of
-the chosen form's S and F against the FP64 path.  The CPU baseline times
-the FP64 oracle's chi0 step on a bounded sample of the same crystal.
+the chosen form's S and F against the FP64 path.  The FP64 oracle runs on a
+bounded sample of the same crystal (q0 on a 4^3 grid, every tenth
+frequency): its chi0 step is the CPU baseline, and the GPU path on the same
+sample gives the errors of S and F against the oracle in every precision.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -64,13 +66,13 @@ def run_step(tdx, ctx, w, st, setup, prec, qs, torch, keep=False, paired=True):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        c0 = tdx.chi0(ctx, tr, P, gb.shape[0], prec, om, w.eta, 2.0 / (st.n_k * st.omega_cell))
+        c0 = tdx.chi0(ctx, tr, P, gb.shape[0], prec, om, w.eta, st.chi0_pref)
         e1.record(stream)
         del P
         K = kernel(tdx, ctx, w, st, qj, gb, fx)
         c00 = tdx.dyson(ctx, c0, K, i_g0)
         beta = 1.0 / T
-        S = tdx.dsf(ctx, c00, om, beta, w.n_electrons / st.omega_cell)
+        S = tdx.dsf(ctx, c00, om, beta, st.density)
         F = tdx.itcf(ctx, S, om, beta, tau)
         out.append(dict(iq=iq, n_t=len(tr), n_g=gb.shape[0], n_w=om.shape[0], ev=(e0, e1),
                         S=S if keep else None, F=F if keep else None))
@@ -89,7 +91,7 @@ class BatchedStep:
         self.tdx, self.ctx, self.w, self.st, self.setup, self.prec = tdx, ctx, w, st, setup, prec
         self.torch, self.persistent, self.paired = torch, persistent, paired
         self.tr, self.P, self.items = [], [], []
-        pref = 2.0 / (st.n_k * st.omega_cell)
+        pref = st.chi0_pref
         for iq in range(len(w.qs)):
             self._occ(iq)
             gb, i_g0, om, tau = setup[iq]
@@ -133,7 +135,7 @@ class BatchedStep:
             T = w.temperatures[iq]
             K = kernel(tdx, ctx, w, st, w.qs[iq], gb, fx)
             c00 = tdx.dyson(ctx, self.items[iq].out, K, i_g0)
-            S = tdx.dsf(ctx, c00, om, 1.0 / T, w.n_electrons / st.omega_cell)
+            S = tdx.dsf(ctx, c00, om, 1.0 / T, st.density)
             F = tdx.itcf(ctx, S, om, 1.0 / T, tau)
             out.append(dict(iq=iq, n_t=len(self.tr[iq]), n_g=gb.shape[0], n_w=om.shape[0],
                             S=S if keep else None, F=F if keep else None))
@@ -179,37 +181,72 @@ def errors(S, Sref, F, Fref):
     return {"S_max_rel_normwise": norm, "S_max_rel_pointwise": point, "F_max_rel": ferr}
 
 
-def cpu_baseline(w, n_w_sample=50):
-    """FP64 oracle chi0 on a bounded sample: the same crystal and q on a 4^3
-    grid (the q vector is unchanged), every tenth frequency."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_sample(w, n_w_sample=50):
+    """The FP64 oracle on a bounded sample of the workload: the same crystal
+    and q0 on a 4^3 grid (the q vector is unchanged), every tenth frequency;
+    states, transitions, pair densities, chi0 (timed on all BLAS threads and,
+    on a tenth of those frequencies, on one), K, Dyson, S and F.  Returns the
+    cpu_baseline record, the sample workload and the oracle's S and F."""
     import oracle
     from oracle import response
-    from oracle.lattice import response_basis
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()
-                     if i.get("user_api") == "blas"] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()
+                 if i.get("user_api") == "blas"] or [os.cpu_count()])
     N = np.asarray(w.kgrid)
     small = (4, 4, 4)
     qj = tuple(int(x) for x in np.asarray(w.qs[0]) * np.asarray(small) // N)
-    ws = w.with_(kgrid=small, qs=(qj,))
-    st = oracle.build_states(ws)
-    qred = np.asarray(qj) / np.asarray(small)
-    basis, _ = response_basis(st.B, qred, ws.ecut_chi[0])
-    tr = response.transitions(st, qj, ws.f_trans_thr)
-    P = response.pair_densities(st, tr, qj, basis)
     om = w.omega_grid(0)[:: max(1, w.n_omega // n_w_sample)]
+    ws = w.with_(name=w.name + "_k4", kgrid=small, qs=(qj,), temperatures=w.temperatures[:1],
+                 ecut_chi=w.ecut_chi[:1], omega_max=w.omega_max[:1])
+    st = oracle.build_states(ws)
+    r = oracle.run_q(ws, st, 0, omegas=om)
     t0 = time.perf_counter()
-    response.chi0(tr, P, om, ws.eta, st.n_k, st.omega)
+    response.chi0(r.tr, r.P, om, ws.eta, st.n_k, st.omega)
     dt = time.perf_counter() - t0
-    fl = f_alg(len(om), len(basis), len(tr))
-    return {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"{w.name} crystal and q0 on a 4^3 k-grid (T={len(tr)} transitions, "
-                       f"N_G={len(basis)}), {len(om)} of {w.n_omega} frequencies; FP64 NumPy "
-                       f"chi0 step {dt:.2f} s"),
+    om1 = om[:: 5]
+    with threadpool_limits(limits=1, user_api="blas"):
+        t0 = time.perf_counter()
+        response.chi0(r.tr, r.P, om1, ws.eta, st.n_k, st.omega)
+        dt1 = time.perf_counter() - t0
+    nb = len(r.basis)
+    fl, fl1 = f_alg(len(om), nb, len(r.tr)), f_alg(len(om1), nb, len(r.tr))
+    base = {"value": fl / dt / 1e12, "unit": "TFLOP/s", "cores": int(cores), "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": fl1 / dt1 / 1e12, "unit": "TFLOP/s", "cores": 1,
+                           "n_omega": len(om1), "seconds": dt1},
+            "sample": (f"{w.name} crystal and q0 on a 4^3 k-grid (T={len(r.tr)} transitions, "
+                       f"full list; N_G={nb}), {len(om)} of {w.n_omega} frequencies; FP64 "
+                       f"NumPy chi0 step {dt:.2f} s on {cores} BLAS threads, "
+                       f"{len(om1)} frequencies {dt1:.2f} s on one"),
             "seconds": dt}
+    return base, ws, om, r
+
+
+def gpu_vs_oracle(tdx, ctx, ws, om, r, precs, paired):
+    """The GPU path on the oracle's sample (same states model, q, frequencies
+    and tau grid) in each precision: max relative errors of S and F against
+    the oracle's."""
+    import torch
+    st = tdx.build_states(ctx, ws)
+    out = {}
+    for prec in precs:
+        g = tdx.run_q(ctx, ws, st, 0, prec=prec, omega=om, keep_chi0=False, paired=paired)
+        out[prec] = errors(g.S.cpu().numpy(), r.S, g.F.cpu().numpy(), r.F)
+        del g
+    torch.cuda.synchronize()
+    del st
+    return out
 
 
 def main():
@@ -283,7 +320,7 @@ def main():
             tr0 = tdx.transitions(ctx, st, w.qs[0], w.f_trans_thr, paired=paired)
             P0 = tdx.pair_density(ctx, st, w.qs[0], tr0, b0, "bf16x3")
             probe = tdx.Chi0Item(tr0, P0, b0.shape[0], setup[0][2], w.eta,
-                                 2.0 / (st.n_k * st.omega_cell))
+                                 st.chi0_pref)
             v, sl, ms = tdx.autotune_chi0(ctx, probe, max_trans=1 << 22)
             tuned = {"variant": v, "slice_log2": sl, "probe_ms": ms, "source": "autotuned now"}
             out = args.tune_save or args.tune_cache
@@ -374,7 +411,7 @@ def main():
     d0, d1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     om0 = setup[0][2]
     q2 = tdx.q_squared(w.cell, w.kgrid, w.qs[0])
-    beta0, dens0 = 1.0 / w.temperatures[0], w.n_electrons / st.omega_cell
+    beta0, dens0 = 1.0 / w.temperatures[0], st.density
     tdx.dielectric(ctx, main_q0["S"], om0, beta0, dens0, q2)
     d0.record(stream)
     tdx.dielectric(ctx, main_q0["S"], om0, beta0, dens0, q2)
@@ -454,8 +491,15 @@ def main():
                      * per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec]},
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline ...")
-        line["cpu_baseline"] = cpu_baseline(w)
+        log("oracle sample ...")
+        base, ws, om_s, r_s = oracle_sample(w)
+        line["cpu_baseline"] = base
+        precs = [args.prec] + [p for p in args.compare.split(",") if p and p != args.prec]
+        line["error_vs_oracle"] = dict(
+            gpu_vs_oracle(tdx, ctx, ws, om_s, r_s, precs, paired),
+            sample=base["sample"].split(";")[0] + "; S normwise and pointwise "
+            "(S > 1e-3 max S), F pointwise, GPU and oracle on the same sample")
+        log(f"errors vs oracle: {line['error_vs_oracle']}")
     ctx.close()
     print(json.dumps(line), flush=True)
 

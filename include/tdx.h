@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define TDX_ABI_VERSION 1
+#define TDX_ABI_VERSION 2
 
 enum {
   TDX_OK = 0,
@@ -138,19 +138,28 @@ typedef struct {
   double mu;          /* out (host): chemical potential                    */
   double temperature; /* out (host)                                        */
   double omega_cell;  /* out (host): cell volume                           */
+  double n_electrons; /* out (host): electrons per cell of the occupations */
+  double beta;        /* out (host): 1 / temperature                       */
+  double density;     /* out (host): n = n_electrons / omega_cell, the     */
+                      /* electron density of the FDT (tdx_dsf)             */
+  double chi0_pref;   /* out (host): 2 / (n_k omega_cell), the Adler-Wiser */
+                      /* normalisation (spin-unpolarised) of tdx_chi0      */
 } tdx_states;
 
 /* Plane-wave Hamiltonian H_GG'(k) = 1/2|k+G|^2 delta + V(G-G') on every
  * k of the grid, dense FP64 eigensolve, band count snapped to a multiplet
  * end, chemical potential by bisection on (2/N_k) sum f = N_e, Fermi-Dirac
- * occupations at `temperature`.  Synchronises the stream.
+ * occupations at `temperature`.  Writes every "out (host)" field of st,
+ * among them the density and the chi0 normalisation that tdx_dsf and
+ * tdx_chi0 take.  Synchronises the stream.
  * Errors: SHAPE if the snapped band count exceeds nb_max, NUMERIC if the
  * top kept band has f >= f_trunc or the electron count cannot be met. */
 int tdx_build_states(tdx_ctx *ctx, const tdx_model *model, double temperature,
                      tdx_states *st, tdx_stream stream);
 
 /* Occupations and mu of existing states at another temperature (same
- * orbitals: the model is non-self-consistent).  Synchronises. */
+ * orbitals: the model is non-self-consistent); updates mu, temperature,
+ * beta, n_electrons, density and chi0_pref of st.  Synchronises. */
 int tdx_occupations(tdx_ctx *ctx, tdx_states *st, double temperature,
                     double n_electrons, double f_trunc, tdx_stream stream);
 
@@ -166,6 +175,13 @@ int tdx_occupations(tdx_ctx *ctx, tdx_states *st, double temperature,
 int tdx_response_basis(const double cell[9], const int kgrid[3], const int qj[3],
                        double ecut_chi, int *miller_out, int capacity, int *n_out,
                        int *i_g0);
+
+/* Host-only: the momentum transfer q = sum_i (qj_i / kgrid_i) b_i in
+ * Cartesian coordinates (q_out host [3], may be null) and |q|^2 (q2_out,
+ * may be null), the |q + G|^2 of the reported element G = 0 that the
+ * dielectric step (tdx_dielectric) takes. */
+int tdx_momentum(const double cell[9], const int kgrid[3], const int qj[3], double *q_out,
+                 double *q2_out);
 
 /* ------------------------------------------------------------------ */
 /* Transitions                                                          */
@@ -240,7 +256,8 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
 /* ------------------------------------------------------------------ */
 
 /* chi0_GG'(q,w) = pref * sum_t df_t / (w - delta_t + i eta) rho_t(G) rho_t(G')*
- * with pref = 2 / (N_k Omega) supplied by the caller.  The weights are
+ * with pref the normalisation 2 / (N_k Omega) of the states (their
+ * chi0_pref field; another value scales the result).  The weights are
  * formed in FP64 in-kernel; the products run in `prec` (see TDX_PREC_*).
  * omega: device [n_w] FP64.  chi0: device complex128 [n_w][n_g][n_g].
  * The sum over t is split into fixed chunks reduced in a fixed order. */
@@ -262,6 +279,8 @@ typedef struct {
   int n_w;
   double eta, pref;
   double *chi0;            /* device complex128 [n_w][n_g][n_g], output     */
+  int64_t p_rows;          /* transitions P was written for (0: n_trans);   */
+                           /* the first n_trans <= p_rows are contracted    */
 } tdx_chi0_item;
 
 typedef struct tdx_chi0_plan tdx_chi0_plan;
@@ -294,6 +313,17 @@ int tdx_chi0_variants(int prec, int *count);
  * (size classes of 16). */
 int tdx_chi0_set_config(tdx_ctx *ctx, int prec, int n_g, int variant, int slice_log2);
 int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slice_log2);
+/* Slice length of every later chi0 contraction on this context (all
+ * precisions, grid launches and plans): with n > 0 the transition list of a
+ * q is cut into slices of n transitions (rounded up to the kernel's chunk),
+ * the last one shorter, whatever the tile count; n = 0 (the default) lets
+ * each call choose the length (the tuned 2^slice_log2, shortened until the
+ * tiles fill the chip).  Within a slice the sums run in FP32 over runs of
+ * chunks (split-BF16, FP32) and in FP64 across runs; the slices' FP64
+ * partials are reduced in a fixed order, so the length fixes the rounding
+ * order and the partial workspace (slices x n_w x n_g^2 x 16 bytes). */
+int tdx_chi0_set_slice_length(tdx_ctx *ctx, int64_t n);
+
 /* Time every variant and slice length 2^{18,20} on the probe item (its
  * first max_trans transitions; probe->chi0 is overwritten) in both launch
  * forms, one grid launch and a one-item plan (the persistent kernel), keep

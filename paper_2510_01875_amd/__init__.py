@@ -64,7 +64,8 @@ class StatesC(C.Structure):
                 ("eps", C.c_void_p), ("occ", C.c_void_p), ("coef", C.c_void_p),
                 ("kgrid", C.c_int * 3), ("mmax", C.c_int * 3), ("cell", C.c_double * 9),
                 ("bvec", C.c_double * 9), ("mu", C.c_double), ("temperature", C.c_double),
-                ("omega_cell", C.c_double)]
+                ("omega_cell", C.c_double), ("n_electrons", C.c_double), ("beta", C.c_double),
+                ("density", C.c_double), ("chi0_pref", C.c_double)]
 
 
 class TransC(C.Structure):
@@ -95,6 +96,7 @@ _occ = _sig("tdx_occupations", [C.c_void_p, C.POINTER(StatesC), C.c_double, C.c_
                                 C.c_double, C.c_void_p])
 _basis = _sig("tdx_response_basis", [C.c_double * 9, C.c_int * 3, C.c_int * 3, C.c_double,
                                      c_int_p, C.c_int, c_int_p, c_int_p])
+_momentum = _sig("tdx_momentum", [C.c_double * 9, C.c_int * 3, C.c_int * 3, c_dbl_p, c_dbl_p])
 _trans = _sig("tdx_transitions", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3, C.c_double,
                                   C.POINTER(TransC), C.POINTER(C.c_int64), C.c_void_p])
 _pair = _sig("tdx_pair_density", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
@@ -117,7 +119,7 @@ _dsf = _sig("tdx_dsf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
 class Chi0ItemC(C.Structure):
     _fields_ = [("tl", C.POINTER(TransC)), ("n_trans", C.c_int64), ("P", C.c_void_p),
                 ("n_g", C.c_int), ("omega", C.c_void_p), ("n_w", C.c_int), ("eta", C.c_double),
-                ("pref", C.c_double), ("chi0", C.c_void_p)]
+                ("pref", C.c_double), ("chi0", C.c_void_p), ("p_rows", C.c_int64)]
 
 
 _plan_create = _sig("tdx_chi0_plan_create", [C.c_void_p, C.POINTER(Chi0ItemC), C.c_int, C.c_int,
@@ -128,6 +130,7 @@ _batched = _sig("tdx_chi0_batched", [C.c_void_p, C.POINTER(Chi0ItemC), C.c_int, 
                                      C.c_void_p])
 _variants = _sig("tdx_chi0_variants", [C.c_int, C.POINTER(C.c_int)])
 _set_cfg = _sig("tdx_chi0_set_config", [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int])
+_set_slice = _sig("tdx_chi0_set_slice_length", [C.c_void_p, C.c_int64])
 _get_cfg = _sig("tdx_chi0_get_config", [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int),
                                         C.POINTER(C.c_int)])
 _autotune = _sig("tdx_autotune_chi0", [C.c_void_p, C.POINTER(Chi0ItemC), C.c_int, C.c_int64,
@@ -185,12 +188,12 @@ _pot_vjp = _sig("tdx_potential_vjp", [C.c_void_p, C.POINTER(Model), C.POINTER(St
 
 EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_set_workspace_limit", "tdx_states_query", "tdx_build_states",
-            "tdx_occupations", "tdx_response_basis", "tdx_transitions",
+            "tdx_occupations", "tdx_response_basis", "tdx_momentum", "tdx_transitions",
             "tdx_pair_density_bytes", "tdx_pair_density", "tdx_chi0", "tdx_kernel_matrix",
             "tdx_xc_kernel_grid", "tdx_kernel_matrix_from_grid",
             "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_dielectric", "tdx_sg_filter", "tdx_derivative_psd", "tdx_sg_scores", "tdx_residual_itcf", "tdx_sg_select", "tdx_kg_dsf", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
             "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
-            "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_autotune_chi0", "tdx_tune_save",
+            "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_chi0_set_slice_length", "tdx_autotune_chi0", "tdx_tune_save",
             "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async", "tdx_itcf_vjp",
             "tdx_dsf_vjp", "tdx_dyson_vjp", "tdx_chi0_vjp", "tdx_weights_vjp",
             "tdx_occupations_vjp", "tdx_pair_density_vjp", "tdx_potential_vjp"]
@@ -296,6 +299,20 @@ class States:
     @property
     def omega_cell(self):
         return self.c.omega_cell
+
+    @property
+    def beta(self):
+        return self.c.beta
+
+    @property
+    def density(self):
+        """Electron density n of the FDT (library-computed)."""
+        return self.c.density
+
+    @property
+    def chi0_pref(self):
+        """The chi0 normalisation 2 / (N_k Omega) (library-computed)."""
+        return self.c.chi0_pref
 
     @property
     def n_k(self):
@@ -520,12 +537,18 @@ def eta_reference(metrics, eta, tol: float = 1e-2) -> int:
 
 
 # ------------------------------------------------- dielectric properties
+def momentum(cell, kgrid, qj):
+    """(q Cartesian [3], |q|^2) of q = sum_i (qj_i / kgrid_i) b_i (tdx_momentum)."""
+    cellc = (C.c_double * 9)(*np.asarray(cell, dtype=np.float64).reshape(-1))
+    q = (C.c_double * 3)()
+    q2 = C.c_double()
+    check(_momentum(cellc, (C.c_int * 3)(*kgrid), (C.c_int * 3)(*qj), q, C.byref(q2)))
+    return np.array(list(q)), q2.value
+
+
 def q_squared(cell, kgrid, qj) -> float:
     """|q|^2 (bohr^-2) of q = sum_i (qj_i / kgrid_i) b_i."""
-    A = np.asarray(cell, dtype=np.float64).reshape(3, 3)
-    B = 2.0 * math.pi * np.linalg.inv(A).T
-    q = (np.asarray(qj, dtype=np.float64) / np.asarray(kgrid, dtype=np.float64)) @ B
-    return float(q @ q)
+    return momentum(cell, kgrid, qj)[1]
 
 
 def dielectric(ctx: Context, S: torch.Tensor, omega: torch.Tensor, beta: float, density: float,
@@ -783,13 +806,11 @@ def run_q(ctx: Context, w, st: States, iq: int, prec: str = "fp64", omega=None,
     P = pair_density(ctx, st, qj, tr, gb, prec, stream)
     om = torch.as_tensor(w.omega_grid(iq) if omega is None else np.asarray(omega, dtype=np.float64),
                          device=dev)
-    pref = 2.0 / (st.n_k * st.omega_cell)
-    c0 = chi0(ctx, tr, P, len(basis), prec, om, w.eta, pref, stream=stream)
+    c0 = chi0(ctx, tr, P, len(basis), prec, om, w.eta, st.chi0_pref, stream=stream)
     del P
     K = kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid, stream)
     c00 = dyson(ctx, c0, K, i_g0, stream)
-    beta = 1.0 / T
-    n = w.n_electrons / st.omega_cell
+    beta, n = st.beta, st.density
     S = dsf(ctx, c00, om, beta, n, stream)
     tau = torch.as_tensor(w.tau_grid(iq), device=dev)
     F = itcf(ctx, S, om, beta, tau, stream)
@@ -802,14 +823,18 @@ class Chi0Item:
     """One q of a batch; keeps the tensors it points to alive."""
 
     def __init__(self, tr: Transitions, P: torch.Tensor, n_g: int, omega: torch.Tensor,
-                 eta: float, pref: float, out: Optional[torch.Tensor] = None):
+                 eta: float, pref: float, out: Optional[torch.Tensor] = None,
+                 n_trans: Optional[int] = None, p_rows: int = 0):
+        """The first n_trans transitions (all by default) of P, a buffer written
+        for p_rows transitions (0: n_trans)."""
         n_w = omega.shape[0]
         self.tr, self.P, self.omega, self.eta, self.pref = tr, P, omega, eta, pref
         self.out = out if out is not None else torch.empty(
             (n_w, n_g, n_g), dtype=torch.complex128, device=omega.device)
         c = Chi0ItemC()
         c.tl = C.pointer(tr.c)
-        c.n_trans = len(tr)
+        c.n_trans = len(tr) if n_trans is None else int(n_trans)
+        c.p_rows = int(p_rows)
         c.P = P.data_ptr()
         c.n_g = n_g
         c.omega = omega.data_ptr()
@@ -867,6 +892,11 @@ def chi0_variants(prec: str = "bf16x3") -> int:
 
 def chi0_set_config(ctx: Context, n_g: int, variant: int, slice_log2: int, prec: str = "bf16x3"):
     check(_set_cfg(ctx.handle, PREC[prec], n_g, variant, slice_log2))
+
+
+def chi0_set_slice_length(ctx: Context, n: int):
+    """Fixed chi0 slice length for later calls on ctx (0: chosen per call)."""
+    check(_set_slice(ctx.handle, int(n)))
 
 
 def chi0_get_config(ctx: Context, n_g: int, prec: str = "bf16x3"):
@@ -936,7 +966,7 @@ def eta_scan(ctx: Context, w, st: States, iq: int, etas, prec: str = "bf16x3",
     tr = transitions(ctx, st, qj, w.f_trans_thr, stream, paired=paired)
     P = pair_density(ctx, st, qj, tr, gb, prec, stream)
     om = torch.as_tensor(w.omega_grid(iq), device=dev)
-    pref = 2.0 / (st.n_k * st.omega_cell)
+    pref = st.chi0_pref
     if prec == "bf16x3":
         items = [Chi0Item(tr, P, n_g, om, float(e), pref) for e in etas]
         plan = Chi0Plan(ctx, items, prec)
@@ -946,7 +976,7 @@ def eta_scan(ctx: Context, w, st: States, iq: int, etas, prec: str = "bf16x3",
         plan = None
         chis = [chi0(ctx, tr, P, n_g, prec, om, float(e), pref, stream=stream) for e in etas]
     K = kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid, stream)
-    beta, n = 1.0 / T, w.n_electrons / st.omega_cell
+    beta, n = st.beta, st.density
     tau = torch.as_tensor(w.tau_grid(iq), device=dev)
     S = torch.stack([dsf(ctx, dyson(ctx, c, K, i_g0, stream), om, beta, n, stream) for c in chis])
     F = torch.stack([itcf(ctx, S[i], om, beta, tau, stream) for i in range(len(etas))])

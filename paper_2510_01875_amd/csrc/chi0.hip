@@ -80,13 +80,17 @@ extern "C" int tdx_chi0(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, 
   chi0_fp_shape(f64, &wblock, &cols, &chunk);
   const long long base =
       (long long)((n_w + wblock - 1) / wblock) * nblk * ((ld + cols - 1) / cols);
-  // enough slices to fill the chip; each slice a multiple of the chunk
+  // enough slices to fill the chip (or the context's fixed length); each
+  // slice a multiple of the chunk
   long long slices = std::max<long long>(1, (4096 + base - 1) / base);
   slices = std::min<long long>(slices, (n_trans + chunk - 1) / chunk);
   slices = std::min<long long>(slices, 512);
   long long slice_len = (n_trans + slices - 1) / slices;
+  if (ctx->slice_len > 0) slice_len = ctx->slice_len;
   slice_len = (slice_len + chunk - 1) / chunk * chunk;
   slices = (n_trans + slice_len - 1) / slice_len;
+  TDX_REQUIRE(slices <= 65535, TDX_ERR_SHAPE, "%lld slices exceed the grid (slice length %lld)",
+              slices, slice_len);
   void *w;
   TDX_TRY(ws_get(ctx, WS_PARTIAL, sizeof(double2) * out_elems * slices, &w));
   double2 *part = (double2 *)w;

@@ -63,9 +63,16 @@ void pick(const tdx_ctx *ctx, int ld, int *variant, int *slice_log2) {
 }
 
 // Slices of a transition list: about 2^slice_log2 transitions each, enough
-// of them that the tile count fills the chip, a multiple of the chunk.
-void slicing(long long n_trans, int slice_log2, long long tiles_per_slice, long long *slice_len,
-             int *slices) {
+// of them that the tile count fills the chip, a multiple of the chunk; or,
+// with a fixed length set on the context, slices of that length.
+void slicing(const tdx_ctx *ctx, long long n_trans, int slice_log2, long long tiles_per_slice,
+             long long *slice_len, int *slices) {
+  if (ctx->slice_len > 0) {
+    const long long len = (ctx->slice_len + kChunkAlign - 1) / kChunkAlign * kChunkAlign;
+    *slice_len = len;
+    *slices = (int)std::max<long long>(1, (n_trans + len - 1) / len);
+    return;
+  }
   long long ns = std::max<long long>((n_trans + (1LL << slice_log2) - 1) >> slice_log2,
                                      (kMinTiles + tiles_per_slice - 1) / tiles_per_slice);
   ns = std::max<long long>(1, std::min<long long>(ns, (n_trans + kChunkAlign - 1) / kChunkAlign));
@@ -90,7 +97,9 @@ int chi0_bf16x3_with(tdx_ctx *ctx, int v, int slice_log2, const void *P, long lo
                      double pref, double2 *chi0, hipStream_t s) {
   long long slice_len;
   int slices;
-  slicing(n_trans, slice_log2, tiles_per_slice(v, n_w, ld), &slice_len, &slices);
+  slicing(ctx, n_trans, slice_log2, tiles_per_slice(v, n_w, ld), &slice_len, &slices);
+  TDX_REQUIRE(slices <= 65535, TDX_ERR_SHAPE, "%d slices exceed the grid (slice length %lld)",
+              slices, slice_len);
   const size_t out_elems = (size_t)n_w * n_g * n_g;
   void *w;
   TDX_TRY(ws_get(ctx, WS_PARTIAL, sizeof(double2) * out_elems * slices, &w));
@@ -155,6 +164,15 @@ int tdx_chi0_set_config(tdx_ctx *ctx, int prec, int n_g, int variant, int slice_
   return TDX_OK;
 }
 
+int tdx_chi0_set_slice_length(tdx_ctx *ctx, int64_t n) {
+  clear_error();
+  TDX_REQUIRE(ctx, TDX_ERR_INVALID_ARG, "ctx is null");
+  TDX_REQUIRE(n >= 0 && n <= (1LL << 40), TDX_ERR_INVALID_ARG, "bad slice length %lld",
+              (long long)n);
+  ctx->slice_len = (long long)n;
+  return TDX_OK;
+}
+
 int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slice_log2) {
   clear_error();
   TDX_REQUIRE(ctx && variant && slice_log2, TDX_ERR_INVALID_ARG, "null argument");
@@ -172,7 +190,8 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
     const tdx_chi0_item &it = items[i];
     TDX_REQUIRE(it.tl && it.P && it.omega && it.chi0, TDX_ERR_INVALID_ARG,
                 "item %d has a null pointer", i);
-    TDX_REQUIRE(it.n_g > 0 && it.n_w > 0 && it.n_trans > 0 && it.n_trans <= it.tl->capacity,
+    TDX_REQUIRE(it.n_g > 0 && it.n_w > 0 && it.n_trans > 0 && it.n_trans <= it.tl->capacity &&
+                    it.p_rows >= 0 && (it.p_rows == 0 || it.n_trans <= it.p_rows),
                 TDX_ERR_SHAPE, "item %d has bad sizes", i);
     TDX_REQUIRE(std::isfinite(it.eta) && it.eta > 0 && std::isfinite(it.pref),
                 TDX_ERR_INVALID_ARG, "item %d has a bad eta or prefactor", i);
@@ -207,12 +226,15 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
     pick(ctx, ld, &vi, &sl);
     long long slice_len;
     int slices;
-    slicing(it.n_trans, sl, tiles_per_slice(v, it.n_w, ld), &slice_len, &slices);
+    slicing(ctx, it.n_trans, sl, tiles_per_slice(v, it.n_w, ld), &slice_len, &slices);
     const size_t per = (size_t)it.n_w * it.n_g * it.n_g;
     part_off[i] = part_bytes;
     part_bytes += per * slices * sizeof(double2);
     p->max_per_slice = std::max(p->max_per_slice, per);
-    bi[i] = BatchItem{it.P,        bf16x3_rho(it.P, it.n_trans, ld), ld, it.tl->delta,
+    // the FP32 rows follow the fragment words of all p_rows transitions the
+    // buffer was written for, of which the first n_trans are contracted
+    const long long rows = it.p_rows > 0 ? it.p_rows : it.n_trans;
+    bi[i] = BatchItem{it.P,        bf16x3_rho(it.P, rows, ld), ld, it.tl->delta,
                       it.tl->df,   (long long)it.n_trans, slice_len, it.omega,
                       it.n_w,      it.eta,      (int)it.tl->paired,   it.n_g,
                       nullptr};
@@ -333,8 +355,11 @@ int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_
   int rc = TDX_OK;
   // both launch forms of the probe: one grid launch, and a one-item plan
   // (persistent kernel) built for the variant under test
+  const long long p_rows = probe->p_rows > 0 ? probe->p_rows : probe->n_trans;
+  TDX_REQUIRE(probe->n_trans <= p_rows, TDX_ERR_SHAPE, "probe has n_trans above p_rows");
   tdx_chi0_item one = *probe;
   one.n_trans = nt;
+  one.p_rows = p_rows;
   tdx_chi0_tune &slot = ctx->tune[bucket_of(ld)];
   const tdx_chi0_tune saved = slot;
   auto timed = [&](auto &&enqueue) {
@@ -353,7 +378,7 @@ int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_
   for (int v = 0; v < bf16x3_variant_count() && rc == TDX_OK; ++v) {
     for (int sl : slice_opts) {
       double ms_best = timed([&] {
-        return chi0_bf16x3_with(ctx, v, sl, probe->P, probe->n_trans, ld, probe->tl->delta,
+        return chi0_bf16x3_with(ctx, v, sl, probe->P, p_rows, ld, probe->tl->delta,
                                 probe->tl->df, (int)probe->tl->paired, nt, probe->omega,
                                 probe->n_w, probe->eta, probe->n_g, probe->pref,
                                 (double2 *)probe->chi0, s);

@@ -217,4 +217,20 @@ int tdx_response_basis(const double cell[9], const int kgrid[3], const int qj[3]
   return TDX_OK;
 }
 
+int tdx_momentum(const double cell[9], const int kgrid[3], const int qj[3], double *q_out,
+                 double *q2_out) {
+  clear_error();
+  TDX_REQUIRE(cell && kgrid && qj, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(kgrid[0] > 0 && kgrid[1] > 0 && kgrid[2] > 0, TDX_ERR_INVALID_ARG, "bad kgrid");
+  Lattice L;
+  TDX_TRY(make_lattice(cell, &L));
+  double q[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) q[j] += (double)qj[i] / kgrid[i] * L.b[i][j];
+  if (q_out)
+    for (int j = 0; j < 3; ++j) q_out[j] = q[j];
+  if (q2_out) *q2_out = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+  return TDX_OK;
+}
+
 }  // extern "C"

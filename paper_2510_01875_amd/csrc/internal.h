@@ -60,6 +60,7 @@ struct tdx_ctx {
   size_t limit = 0;  // 0 = unlimited
   tdx::Workspace ws[13];
   tdx_chi0_tune tune[64];
+  long long slice_len = 0;  // chi0 slice length; 0 = chosen per call to fill the chip
 };
 
 namespace tdx {

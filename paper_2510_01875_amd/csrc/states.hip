@@ -301,6 +301,10 @@ int occupations_impl(tdx_ctx *ctx, tdx_states *st, double T, double ne, double f
               "band set too small: highest kept band has occupation %.3e >= %.3e", top, f_trunc);
   st->mu = h[0];
   st->temperature = T;
+  st->beta = 1.0 / T;
+  st->n_electrons = ne;
+  st->density = ne / st->omega_cell;
+  st->chi0_pref = 2.0 / ((double)st->n_k * st->omega_cell);
   return TDX_OK;
 }
 
@@ -621,6 +625,8 @@ int tdx_occupations(tdx_ctx *ctx, tdx_states *st, double T, double ne, double f_
                     tdx_stream stream) {
   clear_error();
   TDX_REQUIRE(ctx && st && st->eps && st->nb && st->occ, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(std::isfinite(st->omega_cell) && st->omega_cell > 0, TDX_ERR_INVALID_ARG,
+              "states without a cell volume (build them with tdx_build_states)");
   TDX_TRY(check_device(ctx));
   return occupations_impl(ctx, st, T, ne, f_trunc, as_stream(stream));
 }

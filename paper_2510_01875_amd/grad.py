@@ -51,7 +51,7 @@ class ChainRunner:
         ctx = self.ctx
         st = build_states(ctx, w, T)
         dev = st.eps.device
-        pref = 2.0 / (st.n_k * st.omega_cell)
+        pref = st.chi0_pref
         out, per_q = [], []
         for iq, qj in enumerate(w.qs):
             basis, g0 = response_basis(w.cell, w.kgrid, qj, w.ecut_chi[iq])
@@ -159,7 +159,7 @@ def itcf_differentiable(ctx: Context, w, T: torch.Tensor, eta: torch.Tensor,
     runner = ChainRunner(ctx, w)
     chi00 = Chi00.apply(T, eta, v, runner)
     st = runner.saved["st"]
-    dens = w.n_electrons / st.omega_cell
+    dens = st.density
     beta = 1.0 / T
     dev = chi00.device
     out = []

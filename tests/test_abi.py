@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(tdx):
 
 
 def test_abi_version(tdx):
-    assert tdx.abi_version() == 1
+    assert tdx.abi_version() == 2
 
 
 def test_null_arguments_are_rejected(tdx):
@@ -91,6 +91,25 @@ def test_response_basis_matches_oracle(tdx, name, iq):
     assert {tuple(x) for x in g} == {tuple(x) for x in ref}
     assert len(g) == len(ref)
     assert tuple(g[g0]) == (0, 0, 0) and tuple(ref[r0]) == (0, 0, 0)
+
+
+@pytest.mark.parametrize("name,iq", [("feg_c1", 0), ("fcc_c2", 1), ("h16_c5", 3), ("fcc_c4", 9)])
+def test_momentum_matches_oracle(tdx, name, iq):
+    """q and |q|^2 of the library (host) against the oracle's reciprocal
+    vectors; feg_c1's q = (2 pi / a) x exactly."""
+    from oracle.lattice import reciprocal
+    w = workloads.get(name)
+    q, q2 = tdx.momentum(w.cell, w.kgrid, w.qs[iq])
+    ref = (np.asarray(w.qs[iq]) / np.asarray(w.kgrid)) @ reciprocal(w.cell)
+    assert np.max(np.abs(q - ref)) <= 1e-14 * np.max(np.abs(ref))
+    assert abs(q2 - ref @ ref) <= 1e-14 * (ref @ ref)
+    if name == "feg_c1":
+        assert abs(q2 - (2 * np.pi / 7.0) ** 2) <= 1e-14
+
+
+def test_slice_length_setting_validates(tdx):
+    lib = C.CDLL(LIB)
+    assert lib.tdx_chi0_set_slice_length(None, C.c_int64(0)) == tdx.ERR_INVALID_ARG
 
 
 def test_response_basis_rejects_g0_outside(tdx):

@@ -46,7 +46,7 @@ def _prepare(tdx, ctx, w, st, prec, paired=False):
         P = tdx.pair_density(ctx, st, w.qs[iq], tr, gb, prec)
         om = torch.as_tensor(w.omega_grid(iq), device="cuda")
         K = tdx.kernel_matrix(ctx, st, w.qs[iq], gb, w.xc, w.dens_grid)
-        item = tdx.Chi0Item(tr, P, len(basis), om, w.eta, 2.0 / (st.n_k * st.omega_cell))
+        item = tdx.Chi0Item(tr, P, len(basis), om, w.eta, st.chi0_pref)
         out.append(dict(iq=iq, basis=basis, g0=g0, gb=gb, tr=tr, P=P, om=om, K=K, item=item))
     return out
 
@@ -69,7 +69,7 @@ def test_batched_persistent_matches_single_and_oracle(tdx, ctx, paired):
     ost = oracle.build_states(w)
     for p in prep:
         single = tdx.chi0(ctx, p["tr"], p["P"], len(p["basis"]), "bf16x3", p["om"], w.eta,
-                          2.0 / (st.n_k * st.omega_cell))
+                          st.chi0_pref)
         assert torch.equal(single, p["item"].out)
         r = oracle.run_q(w, ost, p["iq"])
         pos = {tuple(x): i for i, x in enumerate(r.basis)}
@@ -95,7 +95,7 @@ def test_plan_replays_in_a_hip_graph(tdx, ctx):
         p["info"] = torch.empty(n_w, dtype=torch.int32, device="cuda")
         p["chi00"] = torch.empty(n_w, dtype=torch.complex128, device="cuda")
         p["tau"] = torch.as_tensor(w.tau_grid(p["iq"]), device="cuda")
-    dens = w.n_electrons / st.omega_cell
+    dens = st.density
 
     def body():
         plan.launch()
@@ -150,12 +150,28 @@ def test_autotuner_picks_a_variant_and_round_trips_the_cache(tdx, ctx):
     tdx.tune_load(c2, path)
     assert tdx.chi0_get_config(c2, n_g) == (v, sl)
     c2.close()
+    # a probe truncated below its buffer's row count: the plans the tuner
+    # times must read the FP32 rows where the buffer holds them
+    nt = len(p["tr"]) // 3
+    tdx.autotune_chi0(ctx, p["item"], max_trans=nt)
+    P_nt = tdx.pair_density(ctx, st, w.qs[0], p["tr"], p["gb"], "bf16x3", n_trans=nt)
+    tdx.chi0_set_config(ctx, n_g, -1, 20)
+    a = tdx.Chi0Item(p["tr"], p["P"], n_g, p["om"], w.eta, st.chi0_pref, n_trans=nt,
+                     p_rows=len(p["tr"]))
+    b = tdx.Chi0Item(p["tr"], P_nt, n_g, p["om"], w.eta, st.chi0_pref, n_trans=nt)
+    tdx.chi0_batched(ctx, [a, b], "bf16x3")
+    ref_nt = tdx.chi0(ctx, p["tr"], P_nt, n_g, "bf16x3", p["om"], w.eta, st.chi0_pref,
+                      n_trans=nt)
+    _say(f"  truncated probe: {nt} of {len(p['tr'])} transitions")
+    assert torch.equal(a.out, b.out) and torch.equal(a.out, ref_nt)
+    err = float((p["item"].out - ref_nt).abs().max() / ref_nt.abs().max())
+    assert err < 1e-5, err
     # every variant gives the same chi0 to the split-BF16 bar
     ref = None
     for var in range(tdx.chi0_variants("bf16x3")):
         tdx.chi0_set_config(ctx, n_g, var, 18)
         c = tdx.chi0(ctx, p["tr"], p["P"], n_g, "bf16x3", p["om"], w.eta,
-                     2.0 / (st.n_k * st.omega_cell))
+                     st.chi0_pref)
         if ref is None:
             ref = c.clone()
         err = float((c - ref).abs().max() / ref.abs().max())

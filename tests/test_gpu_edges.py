@@ -91,7 +91,7 @@ def test_small_cases_match_the_oracle(tdx, ctx, crystal, case):
     p = np.array([pos[tuple(x)] for x in basis])
     ref = ref[:, p][:, :, p]
     om = torch.as_tensor(omegas, device="cuda")
-    pref = 2.0 / (st.n_k * st.omega_cell)
+    pref = st.chi0_pref
     for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4), ("bf16x3", 1e-4)):
         P = tdx.pair_density(ctx, st, w.qs[0], tr, gb, prec, n_trans=nt)
         c0 = tdx.chi0(ctx, tr, P, len(basis), prec, om, w.eta, pref, n_trans=nt).cpu().numpy()

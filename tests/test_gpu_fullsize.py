@@ -90,7 +90,7 @@ def test_fcc_c2_q0_full_size(tdx):
     gb = torch.from_numpy(basis).cuda()
     om_all = w.omega_grid(0)
     om = torch.as_tensor(om_all[::20], device="cuda")
-    pref = 2.0 / (st.n_k * st.omega_cell)
+    pref = st.chi0_pref
 
     # --- sampled states and pair densities against the oracle
     kp, _ = kq_map(w.kgrid, qj)
@@ -168,7 +168,7 @@ def test_fcc_c2_q0_full_size(tdx):
 
     # --- S through Dyson, split-BF16 against FP64
     K = tdx.kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid)
-    beta, n = 1.0 / w.temperatures[0], w.n_electrons / st.omega_cell
+    beta, n = 1.0 / w.temperatures[0], st.density
     S64 = tdx.dsf(ctx, tdx.dyson(ctx, c64, K, i_g0), om, beta, n).cpu().numpy()
     S16 = tdx.dsf(ctx, tdx.dyson(ctx, c16, K, i_g0), om, beta, n).cpu().numpy()
     e_s = np.max(np.abs(S16 - S64)) / np.max(np.abs(S64))
@@ -277,7 +277,7 @@ def test_h16_c3_full_size(tdx):
 
     # --- chi0 and S on 20 frequencies: split-BF16 against FP64
     om = torch.as_tensor(w.omega_grid(0)[::50], device="cuda")
-    pref = 2.0 / (st.n_k * st.omega_cell)
+    pref = st.chi0_pref
     c64 = tdx.chi0(ctx, tr, P64, n_g, "fp64", om, w.eta, pref)
     del P64, got
     P16 = tdx.pair_density(ctx, st, qj, tr, gb, "bf16x3")
@@ -289,7 +289,7 @@ def test_h16_c3_full_size(tdx):
     worst = max(float(np.linalg.eigvalsh((c[i] - c[i].conj().T) / 2j).max())
                 for i in range(1, c.shape[0]))
     K = tdx.kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid)
-    beta, n = 1.0 / w.temperatures[0], w.n_electrons / st.omega_cell
+    beta, n = 1.0 / w.temperatures[0], st.density
     S64 = tdx.dsf(ctx, tdx.dyson(ctx, c64, K, i_g0), om, beta, n).cpu().numpy()
     S16 = tdx.dsf(ctx, tdx.dyson(ctx, c16, K, i_g0), om, beta, n).cpu().numpy()
     e_s = np.max(np.abs(S16 - S64)) / np.max(np.abs(S64))
@@ -341,7 +341,7 @@ def test_fcc_c4_full_size_subset(tdx):
     _say(f"  paired transition counts {min(x[2] for x in sizes)} .. {max(x[2] for x in sizes)}; "
          f"chosen q {chosen}, {total / 1e9:.0f} GB of split-BF16 pair densities")
 
-    pref = 2.0 / (st.n_k * st.omega_cell)
+    pref = st.chi0_pref
     items, per_q = [], []
     for iq in chosen:
         at_temperature(iq)
@@ -358,7 +358,7 @@ def test_fcc_c4_full_size_subset(tdx):
     plan = tdx.Chi0Plan(ctx, items, "bf16x3")
     plan.launch()
     torch.cuda.synchronize()
-    n = w.n_electrons / st.omega_cell
+    n = st.density
     for it, d in zip(items, per_q):
         single = tdx.chi0(ctx, it.tr, it.P, it.out.shape[1], "bf16x3", it.omega, w.eta, pref)
         assert torch.equal(single, it.out)

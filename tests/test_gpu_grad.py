@@ -130,7 +130,7 @@ def test_chi0_vjp_matches_autograd(tdx, ctx):
     T_all = len(tr_full) - 37          # ragged tail of the last tile
     n_w = 70
     om = torch.linspace(0.0, 3.0, n_w, dtype=torch.float64, device="cuda")
-    eta, pref = 0.02, 2.0 / (st.n_k * st.omega_cell)
+    eta, pref = 0.02, st.chi0_pref
     g = torch.Generator().manual_seed(3)
     u = (torch.randn(n_w, n_g, generator=g, dtype=torch.float64) +
          1j * torch.randn(n_w, n_g, generator=g, dtype=torch.float64))

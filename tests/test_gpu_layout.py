@@ -65,7 +65,7 @@ def test_split_bf16_layout_is_bit_exact(tdx):
         assert torch.equal(got[:T], ref[:T].to(torch.int32)), f"component {comp}"
         assert int(got[T:].abs().max()) == 0 if T4 > T else True, f"tail of component {comp}"
     om = torch.as_tensor(w.omega_grid(0), device="cuda")
-    pref = 2.0 / (st.n_k * st.omega_cell)
+    pref = st.chi0_pref
     c64 = tdx.chi0(ctx, tr, P64buf, n_g, "fp64", om, w.eta, pref)
     c16 = tdx.chi0(ctx, tr, buf, n_g, "bf16x3", om, w.eta, pref)
     err = float((c16 - c64).abs().max() / c64.abs().max())
