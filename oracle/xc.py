@@ -9,6 +9,10 @@ parametrisation of the unpolarised correlation energy,
 with A = 0.031091, a1 = 0.21370, b1..b4 = 7.5957, 3.5876, 1.6382, 0.49294
 (Hartree; Phys. Rev. B 45, 13244 (1992), Table I, zeta = 0 column).
 
+The second derivative is taken by evaluating n eps_xc(n) in hyper-dual
+arithmetic, which yields it exactly (up to rounding) from the energy formula
+itself.
+
 The kernel matrix is f_xc(G - G') with
   f_xc(G) = (1/N_r) sum_j f_xc(n(r_j)) exp(-i G.r_j)
 on the real-space grid r_j = sum_i (j_i/N_i) a_i, and
@@ -25,46 +29,111 @@ PW92_A1 = 0.21370
 PW92_B = (7.5957, 3.5876, 1.6382, 0.49294)
 
 
+class HyperDual:
+    """x = a + b e1 + c e2 + d e1 e2 with e1^2 = e2^2 = 0 (hyper-dual numbers,
+    Fike and Alonso, AIAA 2011-886): evaluating f at a + e1 + e2 gives f(a),
+    f'(a), f'(a) and f''(a) in the four parts, exactly up to rounding (no
+    step size).  Components are numpy arrays."""
+
+    __slots__ = ("a", "b", "c", "d")
+
+    def __init__(self, a, b=0.0, c=0.0, d=0.0):
+        self.a, self.b, self.c, self.d = a, b, c, d
+
+    @staticmethod
+    def _lift(x):
+        return x if isinstance(x, HyperDual) else HyperDual(x)
+
+    def _chain(self, f, f1, f2):
+        """g(self) for a scalar function g with g = f, g' = f1, g'' = f2 at a."""
+        return HyperDual(f, f1 * self.b, f1 * self.c, f1 * self.d + f2 * self.b * self.c)
+
+    def __add__(self, o):
+        o = self._lift(o)
+        return HyperDual(self.a + o.a, self.b + o.b, self.c + o.c, self.d + o.d)
+
+    __radd__ = __add__
+
+    def __neg__(self):
+        return HyperDual(-self.a, -self.b, -self.c, -self.d)
+
+    def __sub__(self, o):
+        return self + (-self._lift(o))
+
+    def __rsub__(self, o):
+        return self._lift(o) - self
+
+    def __mul__(self, o):
+        o = self._lift(o)
+        return HyperDual(self.a * o.a, self.a * o.b + self.b * o.a, self.a * o.c + self.c * o.a,
+                         self.a * o.d + self.b * o.c + self.c * o.b + self.d * o.a)
+
+    __rmul__ = __mul__
+
+    def recip(self):
+        a = self.a
+        return self._chain(1.0 / a, -1.0 / a ** 2, 2.0 / a ** 3)
+
+    def __truediv__(self, o):
+        return self * self._lift(o).recip()
+
+    def __rtruediv__(self, o):
+        return self._lift(o) * self.recip()
+
+    def __pow__(self, p):
+        a = self.a
+        return self._chain(a ** p, p * a ** (p - 1.0), p * (p - 1.0) * a ** (p - 2.0))
+
+    def log1p(self):
+        a = self.a
+        return self._chain(np.log1p(a), 1.0 / (1.0 + a), -1.0 / (1.0 + a) ** 2)
+
+
 def rs_of(n):
     return (3.0 / (4.0 * math.pi * np.asarray(n, dtype=np.float64))) ** (1.0 / 3.0)
 
 
-def _pw92_terms(rs):
-    """eps_c and its first two rs-derivatives."""
+def _ex(n):
+    """Slater exchange energy per electron, -(3/4)(3 n / pi)^(1/3)."""
+    return -0.75 * (3.0 / math.pi) ** (1.0 / 3.0) * n ** (1.0 / 3.0)
+
+
+def _ec(n):
+    """PW92 correlation energy per electron (unpolarised) at density n, with
+    rs = (3 / (4 pi n))^(1/3) (works on floats, arrays and HyperDual)."""
     A, a1 = PW92_A, PW92_A1
     b1, b2, b3, b4 = PW92_B
-    s = np.sqrt(rs)
-    Q = 2 * A * (b1 * s + b2 * rs + b3 * rs * s + b4 * rs * rs)
-    Q1 = 2 * A * (0.5 * b1 / s + b2 + 1.5 * b3 * s + 2 * b4 * rs)
-    Q2 = 2 * A * (-0.25 * b1 / (rs * s) + 0.75 * b3 / s + 2 * b4)
-    L = np.log1p(1.0 / Q)
-    D = Q + Q * Q
-    L1 = -Q1 / D
-    L2 = -Q2 / D + Q1 * Q1 * (1 + 2 * Q) / (D * D)
-    g = -2 * A * (1 + a1 * rs)
-    e = g * L
-    e1 = -2 * A * a1 * L + g * L1
-    e2 = -4 * A * a1 * L1 + g * L2
-    return e, e1, e2
+    rs = (3.0 / (4.0 * math.pi)) ** (1.0 / 3.0) * n ** (-1.0 / 3.0)
+    den = 2.0 * A * (b1 * rs ** 0.5 + b2 * rs + b3 * rs ** 1.5 + b4 * rs ** 2.0)
+    inner = 1.0 / den
+    log_term = inner.log1p() if isinstance(inner, HyperDual) else np.log1p(inner)
+    return -2.0 * A * (1.0 + a1 * rs) * log_term
+
+
+def ec_pw92_rs(rs):
+    """PW92 correlation energy per electron as a function of rs (Ha)."""
+    rs = np.asarray(rs, dtype=np.float64)
+    return _ec(3.0 / (4.0 * math.pi * rs ** 3))
 
 
 def exc_pw92(n):
     """eps_xc(n) per electron (Ha): Slater exchange + PW92 correlation."""
     n = np.asarray(n, dtype=np.float64)
-    ex = -0.75 * (3.0 * n / math.pi) ** (1.0 / 3.0)
-    ec, _, _ = _pw92_terms(rs_of(n))
-    return ex + ec
+    return _ex(n) + _ec(n)
+
+
+def fxc_parts(n):
+    """(f_x, f_c): the second derivatives d^2(n eps_x)/dn^2 and
+    d^2(n eps_c)/dn^2, each read off n eps(n) evaluated at the hyper-dual
+    point n + e1 + e2 (no chain rule through rs written by hand)."""
+    n = np.asarray(n, dtype=np.float64)
+    x = HyperDual(n, np.ones_like(n), np.ones_like(n), np.zeros_like(n))
+    return (x * _ex(x)).d, (x * _ec(x)).d
 
 
 def fxc_alda(n):
     """d^2 (n eps_xc) / dn^2."""
-    n = np.asarray(n, dtype=np.float64)
-    fx = -(1.0 / 3.0) * (3.0 / math.pi) ** (1.0 / 3.0) * n ** (-2.0 / 3.0)
-    rs = rs_of(n)
-    _, e1, e2 = _pw92_terms(rs)
-    # rs(n) = (3/(4 pi n))^(1/3): d/dn = -(rs/3n) d/drs, which gives
-    # d^2(n eps)/dn^2 = (rs^2 eps'' - 2 rs eps') / (9 n).
-    fc = (rs * rs * e2 - 2.0 * rs * e1) / (9.0 * n)
+    fx, fc = fxc_parts(n)
     return fx + fc
 
 
