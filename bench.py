@@ -249,6 +249,203 @@ def gpu_vs_oracle(tdx, ctx, ws, om, r, precs, paired):
     return out
 
 
+def h16_leg(tdx, ctx, sample_every=50):
+    """The 16-proton system at full size (h16_c3: 64 k, about 6290 plane waves
+    and 860 bands per k, 304 G, 1000 frequencies on [0, 5] Ha, RPA): q0 with
+    split-BF16 chi0 and FP64 Dyson, states built once (timed apart).  The
+    step (pair densities, chi0, K, Dyson, S, F) is timed as a whole and the
+    chi0 launch with HIP events on its stream.  The FP64 contraction then
+    runs on every sample_every-th frequency, and S and F (the latter on that
+    coarse grid, for both) of the split-BF16 path are compared with it."""
+    import torch
+    import workloads
+    w = workloads.h16_c3()
+    t0 = time.perf_counter()
+    st = tdx.build_states(ctx, w, w.temperatures[0])
+    torch.cuda.synchronize()
+    t_states = time.perf_counter() - t0
+    qj = w.qs[0]
+    basis, g0 = tdx.response_basis(w.cell, w.kgrid, qj, w.ecut_chi[0])
+    n_g = len(basis)
+    gb = torch.from_numpy(basis).cuda()
+    om = torch.as_tensor(w.omega_grid(0), device="cuda")
+    tau = torch.as_tensor(w.tau_grid(0), device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(prec, omega):
+        tr = tdx.transitions(ctx, st, qj, w.f_trans_thr, paired=True)
+        P = tdx.pair_density(ctx, st, qj, tr, gb, prec)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        c0 = tdx.chi0(ctx, tr, P, n_g, prec, omega, w.eta, st.chi0_pref)
+        e1.record(stream)
+        del P
+        K = tdx.kernel_matrix_from_grid(ctx, st, qj, gb, w.xc)
+        c00 = tdx.dyson(ctx, c0, K, g0)
+        S = tdx.dsf(ctx, c00, omega, st.beta, st.density)
+        return len(tr), (e0, e1), c00, S
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_t, ev, c00, S = step("bf16x3", om)
+    F = tdx.itcf(ctx, S, om, st.beta, tau)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = ev[0].elapsed_time(ev[1])
+    fl = f_alg(om.shape[0], n_g, n_t)
+    sub = om[::sample_every].contiguous()
+    _, ev64, _, S64 = step("fp64", sub)
+    torch.cuda.synchronize()
+    ms64 = ev64[0].elapsed_time(ev64[1])
+    # both paths through S and F on the same coarse grid (S(0) is taken from
+    # the grid's next point, so it depends on the grid)
+    S_sub = tdx.dsf(ctx, c00[::sample_every].contiguous(), sub, st.beta, st.density)
+    F_sub = tdx.itcf(ctx, S_sub, sub, st.beta, tau).cpu().numpy()
+    F64 = tdx.itcf(ctx, S64, sub, st.beta, tau).cpu().numpy()
+    err = errors(S_sub.cpu().numpy(), S64.cpu().numpy(), F_sub, F64)
+    del st
+    torch.cuda.empty_cache()
+    return {"workload": w.name, "kgrid": list(w.kgrid), "n_bands": w.n_bands, "n_g": n_g,
+            "n_omega": int(om.shape[0]), "n_trans": n_t,
+            "transitions": "one per time-reversal pair", "dtype": "bf16x3 chi0, FP64 Dyson",
+            "build_states_s": t_states, "step_s": dt,
+            "s_eval_per_s": int(om.shape[0]) / dt,
+            "chi0_ms": ms, "chi0_tflops": fl / (ms * 1e-3) / 1e12,
+            "roofline": {"bound": "mfma", "achieved": fl / (ms * 1e-3) / 1e12,
+                         "peak": PEAK_TFLOPS["bf16x3"], "unit": "TFLOP/s",
+                         "frac": fl / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["bf16x3"]},
+            "fp64_sampled": {"n_omega": int(sub.shape[0]), "chi0_ms": ms64,
+                             "chi0_tflops": f_alg(sub.shape[0], n_g, n_t) / (ms64 * 1e-3) / 1e12},
+            "error_vs_fp64_sampled": err}
+
+
+def batched_graph_run(tdx, ctx, w, args, budget_bytes=200 << 30, slice_log2=22):
+    """A ragged batch of q (fcc_c4: 32 q, per-q temperature and basis) at full
+    size: the q are packed longest first into groups whose split-BF16 pair
+    densities, chi0 slice partials and outputs fit the budget; each group is
+    ONE HIP graph holding pair densities -> one persistent chi0 launch ->
+    Dyson -> S -> F for all its q, captured once and replayed once (timed
+    with events around the replay).  States, occupations, transition lists,
+    f_xc grids and K are set up before the timed graphs."""
+    import torch
+    t0 = time.perf_counter()
+    st = tdx.build_states(ctx, w, w.temperatures[0])
+    torch.cuda.synchronize()
+    t_states = time.perf_counter() - t0
+    log(f"states: {st.n_k} k, {t_states:.1f} s")
+    tdx.chi0_set_slice_length(ctx, 1 << slice_log2)
+    fx, qs = {}, []
+    for iq in range(len(w.qs)):
+        T = w.temperatures[iq]
+        if st.temperature != T:
+            tdx.occupations(ctx, st, T, w.n_electrons, w.f_trunc)
+        if T not in fx:
+            fx[T] = tdx.xc_kernel_grid(ctx, st, w.dens_grid)
+        basis, g0 = tdx.response_basis(w.cell, w.kgrid, w.qs[iq], w.ecut_chi[iq])
+        n_g = len(basis)
+        gb = torch.from_numpy(basis).cuda()
+        tr = tdx.transitions(ctx, st, w.qs[iq], w.f_trans_thr, paired=True)
+        K = tdx.kernel_matrix_from_grid(ctx, st, w.qs[iq], gb, w.xc, w.dens_grid, fx[T])
+        n_w = w.n_omega
+        per = n_w * n_g * n_g * 16
+        slices = max(1, -(-len(tr) // (1 << slice_log2)))
+        nbytes = (tdx.pair_density_bytes(len(tr), n_g, "bf16x3") + (slices + 2) * per +
+                  tdx.pair_density_work_bytes(st, len(tr)))
+        qs.append(dict(iq=iq, T=T, beta=1.0 / T, g0=g0, gb=gb, tr=tr, K=K, n_g=n_g, n_w=n_w,
+                       bytes=nbytes, n_t=len(tr)))
+    dens = st.density
+    order = sorted(qs, key=lambda q: -q["bytes"])
+    groups, cur, used = [], [], 0
+    for q in order:
+        if cur and used + q["bytes"] > budget_bytes:
+            groups.append(cur)
+            cur, used = [], 0
+        cur.append(q)
+        used += q["bytes"]
+    if cur:
+        groups.append(cur)
+    log(f"{len(qs)} q in {len(groups)} groups; transitions {min(q['n_t'] for q in qs)} .. "
+        f"{max(q['n_t'] for q in qs)}")
+    stream = torch.cuda.current_stream()
+    recs, total_ms, total_flops, n_eval = [], 0.0, 0.0, 0
+    S_out = {}
+    for gi, grp in enumerate(groups):
+        torch.cuda.empty_cache()
+        items = []
+        for q in grp:
+            q["P"] = torch.empty(tdx.pair_density_bytes(q["n_t"], q["n_g"], "bf16x3"),
+                                 dtype=torch.uint8, device="cuda")
+            q["pdw"] = torch.empty(tdx.pair_density_work_bytes(st, q["n_t"]), dtype=torch.uint8,
+                                   device="cuda")
+            q["om"] = torch.as_tensor(w.omega_grid(q["iq"]), device="cuda")
+            q["tau"] = torch.as_tensor(w.tau_grid(q["iq"]), device="cuda")
+            q["dw"] = torch.empty(tdx.dyson_work_bytes(q["n_g"], q["n_w"]), dtype=torch.uint8,
+                                  device="cuda")
+            q["info"] = torch.zeros(q["n_w"], dtype=torch.int32, device="cuda")
+            q["chi00"] = torch.empty(q["n_w"], dtype=torch.complex128, device="cuda")
+            q["item"] = tdx.Chi0Item(q["tr"], q["P"], q["n_g"], q["om"], w.eta, st.chi0_pref)
+            items.append(q["item"])
+        plan = tdx.Chi0Plan(ctx, items, "bf16x3")
+
+        def body():
+            for q in grp:
+                tdx.pair_density_async(ctx, st, w.qs[q["iq"]], q["tr"], q["gb"], q["P"], q["pdw"],
+                                       "bf16x3")
+            plan.launch()
+            outs = []
+            for q in grp:
+                tdx.dyson_async(ctx, q["item"].out, q["K"], q["g0"], q["chi00"], q["dw"], q["info"])
+                S = tdx.dsf(ctx, q["chi00"], q["om"], q["beta"], dens)
+                outs.append((S, tdx.itcf(ctx, S, q["om"], q["beta"], q["tau"])))
+            return outs
+
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            captured = body()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        fl = sum(f_alg(q["n_w"], q["n_g"], q["n_t"]) for q in grp)
+        bad = sum(int(q["info"].abs().max()) != 0 for q in grp)
+        for q, (S, F) in zip(grp, captured):
+            S_out[q["iq"]] = (S.cpu().numpy(), F.cpu().numpy())
+        total_ms += ms
+        total_flops += fl
+        n_eval += sum(q["n_w"] for q in grp)
+        recs.append({"q": [q["iq"] for q in grp], "n_trans": [q["n_t"] for q in grp],
+                     "n_g": [q["n_g"] for q in grp], "graph_ms": ms,
+                     "tflops_graph": fl / (ms * 1e-3) / 1e12, "singular": bad,
+                     "gib": sum(q["bytes"] for q in grp) / 2 ** 30})
+        log(f"group {gi + 1}/{len(groups)}: q {recs[-1]['q']} {ms:.0f} ms "
+            f"{recs[-1]['tflops_graph']:.0f} TFLOP/s")
+        del g, captured, plan, items
+        for q in grp:
+            for key in ("P", "pdw", "dw", "item"):
+                q.pop(key, None)
+    finite = all(np.all(np.isfinite(S)) and np.all(np.isfinite(F)) for S, F in S_out.values())
+    line = {
+        "metric": "chi0 TFLOP/s + S(q,w) eval/s at stated error vs FP64, plain vs split-BF16",
+        "value": total_flops / (total_ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": total_ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
+        "data": "synthetic (seeded model crystal; no paper data)",
+        "config": {"workload": w.name, "kgrid": list(w.kgrid), "n_q": len(w.qs),
+                   "n_omega": w.n_omega, "transitions": "one per time-reversal pair",
+                   "form": "groups of q, each one HIP graph: pair densities, one persistent "
+                           "chi0 launch, Dyson, S, F; value = F_alg / graph time (pair "
+                           "densities and Dyson included)",
+                   "slice_log2": slice_log2, "budget_gib": budget_bytes / 2 ** 30},
+        "s_eval_per_s": n_eval / (total_ms * 1e-3), "build_states_s": t_states,
+        "groups": recs, "all_finite": bool(finite),
+        "total_transitions": int(sum(q["n_t"] for q in qs))}
+    tdx.chi0_set_slice_length(ctx, 0)
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +456,8 @@ def main():
     ap.add_argument("--compare", default="fp64,fp32",
                     help="precisions timed on the first q for comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-h16", dest="h16", action="store_false",
+                    help="skip the 16-proton leg (h16_c3 at full size, q0, 1000 frequencies)")
     ap.add_argument("--no-pairing", action="store_true",
                     help="contract the full transition list instead of one transition per "
                          "time-reversal pair")
@@ -299,6 +498,11 @@ def main():
 
     w = workloads.get(args.workload)
     ctx = tdx.Context(0)
+    if args.workload == "fcc_c4":
+        line = batched_graph_run(tdx, ctx, w, args)
+        ctx.close()
+        print(json.dumps(line), flush=True)
+        return
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = tdx.build_states(ctx, w, w.temperatures[0])
@@ -490,6 +694,13 @@ def main():
                      "issued_mfma_frac": (3.0 if args.prec == "bf16x3" else 1.0)
                      * per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec]},
     }
+    if args.h16:
+        del st
+        torch.cuda.empty_cache()
+        log("h16_c3 leg ...")
+        line["h16_c3"] = h16_leg(tdx, ctx)
+        log(f"h16_c3: {line['h16_c3']['chi0_tflops']:.0f} TFLOP/s, step "
+            f"{line['h16_c3']['step_s']:.1f} s, errors {line['h16_c3']['error_vs_fp64_sampled']}")
     if not args.no_cpu_baseline:
         log("oracle sample ...")
         base, ws, om_s, r_s = oracle_sample(w)

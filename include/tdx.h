@@ -211,7 +211,10 @@ int tdx_momentum(const double cell[9], const int kgrid[3], const int qj[3], doub
  * a k that is its own partner keeps n < m.  tdx_chi0 and the batch plans
  * then apply the combined weight (chi0 equals that of the full list up to
  * rounding); pair densities are computed for the kept transitions only.
- * The reverse-mode entry points need the full list (INVALID_ARG). */
+ * The reverse-mode entry points differentiate the combined weight; they
+ * attribute each pair's cotangents to the states of its kept transition,
+ * which, by the same symmetry, leaves the gradients in T, eta and the
+ * potential those of the full list. */
 typedef struct {
   int64_t capacity;
   int *k, *n, *m;
@@ -250,6 +253,25 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
                      const tdx_translist *tl, int64_t n_trans,
                      const int *gbasis, int n_g, int prec, void *P,
                      tdx_stream stream);
+/* The same for the transitions t_begin .. t_end - 1 of the list, stored as
+ * rows 0 .. t_end - t_begin - 1 of P (the layout above for t_end - t_begin
+ * transitions): a list can be processed in blocks whose buffers are
+ * recomputed rather than held (the reverse sweep does this).  Equal, row for
+ * row, to the rows of a whole-list call. */
+int tdx_pair_density_range(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
+                           const tdx_translist *tl, int64_t t_begin, int64_t t_end,
+                           const int *gbasis, int n_g, int prec, void *P, tdx_stream stream);
+/* tdx_pair_density_range without allocation, host copy, memset or
+ * synchronisation (graph-capturable): its tables (Miller lookups, row and
+ * column groups, k + q maps) are built by kernels in `work`, a caller-owned
+ * device buffer of at least tdx_pair_density_work_bytes(st, t_end - t_begin)
+ * bytes (SHAPE otherwise) that must stay alive until the stream has run the
+ * call.  Same results as tdx_pair_density_range. */
+size_t tdx_pair_density_work_bytes(const tdx_states *st, int64_t n_trans);
+int tdx_pair_density_async(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
+                           const tdx_translist *tl, int64_t t_begin, int64_t t_end,
+                           const int *gbasis, int n_g, int prec, void *P, void *work,
+                           size_t work_bytes, tdx_stream stream);
 
 /* ------------------------------------------------------------------ */
 /* chi0 (Adler-Wiser), the MFMA contraction                             */
@@ -580,23 +602,28 @@ int tdx_dyson_vjp(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, in
                   int i_g0, const double *chi00_bar, double *u, double *v, void *work,
                   int *info, tdx_stream stream);
 
-/* chi0 = pref sum_t w_t rho_t rho_t^H, w_t = df_t / (w - delta_t + i eta),
- * with cotangent u v^H per frequency.  For lambda = pref (u^H rho_t)
- * conj(v^H rho_t) and r = 1/(w - delta_t + i eta), writes
- *   w_bar: device complex128 [n_trans][2] = (sum_w lambda r, sum_w lambda r^2)
- * (so df_bar = Re w_bar[0], delta_bar = df Re w_bar[1],
- *  eta_bar = df Im w_bar[1]), and, if rho_bar is not NULL, the pair-density
- * cotangent rho_bar: device complex128 [n_trans][ld], ld = n_g rounded up
- * to 16.  P: FP64 pair densities (TDX_PREC_FP64 layout).  No allocation or
- * synchronisation. */
-int tdx_chi0_vjp(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, const double *P, int n_g,
-                 const double *omega, int n_w, double eta, double pref, const double *u,
-                 const double *v, double *w_bar, double *rho_bar, tdx_stream stream);
+/* chi0 = pref sum_t w_t rho_t rho_t^H, w_t = df_t / (w - delta_t + i eta)
+ * (a paired list: w_t = df_t [1/(w - delta_t + i eta) - 1/(w + delta_t + i eta)]),
+ * with cotangent u v^H per frequency, for the transitions t_begin ..
+ * t_end - 1.  P: their FP64 pair densities (TDX_PREC_FP64 layout, row 0 =
+ * t_begin, e.g. from tdx_pair_density_range).  Writes, per transition (row
+ * t - t_begin), the real cotangents
+ *   w_bar: device FP64 [t_end - t_begin][3] = (df_bar, delta_bar, eta_bar_t),
+ *   dL = sum_t df_bar d(df_t) + delta_bar d(delta_t) + eta_bar_t d(eta),
+ * and, if rho_bar is not NULL, the pair-density cotangent rho_bar: device
+ * complex128 [t_end - t_begin][ld], ld = n_g rounded up to 16.  With
+ * lambda = pref (u^H rho_t) conj(v^H rho_t) each entry is Re sum_w lambda
+ * dw_t/dx.  No allocation or synchronisation. */
+int tdx_chi0_vjp(tdx_ctx *ctx, const tdx_translist *tl, int64_t t_begin, int64_t t_end,
+                 const double *P, int n_g, const double *omega, int n_w, double eta, double pref,
+                 const double *u, const double *v, double *w_bar, double *rho_bar,
+                 tdx_stream stream);
 
-/* From w_bar of one q: accumulates the occupation and eigenvalue
- * cotangents of the states (occ_bar, eps_bar: device [n_k][nb_max], +=)
- * through df_t = f_n(k) - f_m(k') and delta_t = eps_m(k') - eps_n(k), and
- * eta_bar (device [1], +=).  Synchronises. */
+/* From w_bar of one q (device FP64 [n_trans][3] as written by tdx_chi0_vjp
+ * for the whole list): accumulates the occupation and eigenvalue cotangents
+ * of the states (occ_bar, eps_bar: device [n_k][nb_max], +=) through
+ * df_t = f_n(k) - f_m(k') and delta_t = eps_m(k') - eps_n(k), and
+ * eta_bar (device [1], += sum_t eta_bar_t).  Synchronises. */
 int tdx_weights_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const tdx_translist *tl,
                     int64_t n_trans, const double *w_bar, double *occ_bar, double *eps_bar,
                     double *eta_bar, tdx_stream stream);
@@ -610,10 +637,13 @@ int tdx_occupations_vjp(tdx_ctx *ctx, const tdx_states *st, const double *occ_ba
 
 /* rho_t(G) = sum_G1 c*_nk(G1) c_mk'(G1 + G + G_s): accumulates the
  * orbital cotangents coef_bar (device complex128 [n_k][nb_max][npw_max],
- * +=) from rho_bar of one q (layout of tdx_chi0_vjp).  Synchronises. */
+ * +=) from rho_bar of the transitions t_begin .. t_end - 1 of one q (layout
+ * of tdx_chi0_vjp, row 0 = t_begin), so that a list can be swept in blocks.
+ * Synchronises. */
 int tdx_pair_density_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
-                         const tdx_translist *tl, int64_t n_trans, const int *gbasis, int n_g,
-                         const double *rho_bar, double *coef_bar, tdx_stream stream);
+                         const tdx_translist *tl, int64_t t_begin, int64_t t_end,
+                         const int *gbasis, int n_g, const double *rho_bar, double *coef_bar,
+                         tdx_stream stream);
 
 /* Shell-value gradient from the eigenvalue and orbital cotangents of the
  * kept bands: with H(k) rebuilt and fully diagonalised (all N_pw pairs),

@@ -102,6 +102,16 @@ _trans = _sig("tdx_transitions", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3, C
 _pair = _sig("tdx_pair_density", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
                                   C.POINTER(TransC), C.c_int64, C.c_void_p, C.c_int, C.c_int,
                                   C.c_void_p, C.c_void_p])
+_pair_range = _sig("tdx_pair_density_range", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
+                                              C.POINTER(TransC), C.c_int64, C.c_int64,
+                                              C.c_void_p, C.c_int, C.c_int, C.c_void_p,
+                                              C.c_void_p])
+_pair_async = _sig("tdx_pair_density_async", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
+                                              C.POINTER(TransC), C.c_int64, C.c_int64,
+                                              C.c_void_p, C.c_int, C.c_int, C.c_void_p,
+                                              C.c_void_p, C.c_size_t, C.c_void_p])
+_lib.tdx_pair_density_work_bytes.restype = C.c_size_t
+_lib.tdx_pair_density_work_bytes.argtypes = [C.POINTER(StatesC), C.c_int64]
 _chi0 = _sig("tdx_chi0", [C.c_void_p, C.POINTER(TransC), C.c_int64, C.c_void_p, C.c_int,
                           C.c_int, C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_void_p,
                           C.c_void_p])
@@ -172,24 +182,27 @@ _dsf_vjp = _sig("tdx_dsf_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c
 _dyson_vjp = _sig("tdx_dyson_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p])
-_chi0_vjp = _sig("tdx_chi0_vjp", [C.c_void_p, C.POINTER(TransC), C.c_int64, C.c_void_p, C.c_int,
-                                  C.c_void_p, C.c_int, C.c_double, C.c_double, C.c_void_p,
-                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
+_chi0_vjp = _sig("tdx_chi0_vjp", [C.c_void_p, C.POINTER(TransC), C.c_int64, C.c_int64,
+                                  C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_double,
+                                  C.c_double, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p])
 _weights_vjp = _sig("tdx_weights_vjp", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
                                         C.POINTER(TransC), C.c_int64, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p, C.c_void_p])
 _occ_vjp = _sig("tdx_occupations_vjp", [C.c_void_p, C.POINTER(StatesC), C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p])
 _pair_vjp = _sig("tdx_pair_density_vjp", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
-                                          C.POINTER(TransC), C.c_int64, C.c_void_p, C.c_int,
-                                          C.c_void_p, C.c_void_p, C.c_void_p])
+                                          C.POINTER(TransC), C.c_int64, C.c_int64, C.c_void_p,
+                                          C.c_int, C.c_void_p, C.c_void_p, C.c_void_p])
 _pot_vjp = _sig("tdx_potential_vjp", [C.c_void_p, C.POINTER(Model), C.POINTER(StatesC),
                                       C.c_void_p, C.c_void_p, c_dbl_p, C.c_void_p])
 
 EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_set_workspace_limit", "tdx_states_query", "tdx_build_states",
             "tdx_occupations", "tdx_response_basis", "tdx_momentum", "tdx_transitions",
-            "tdx_pair_density_bytes", "tdx_pair_density", "tdx_chi0", "tdx_kernel_matrix",
+            "tdx_pair_density_bytes", "tdx_pair_density", "tdx_pair_density_range",
+            "tdx_pair_density_work_bytes", "tdx_pair_density_async",
+            "tdx_chi0", "tdx_kernel_matrix",
             "tdx_xc_kernel_grid", "tdx_kernel_matrix_from_grid",
             "tdx_dyson", "tdx_dsf", "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_dielectric", "tdx_sg_filter", "tdx_derivative_psd", "tdx_sg_scores", "tdx_residual_itcf", "tdx_sg_select", "tdx_kg_dsf", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
             "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
@@ -428,6 +441,38 @@ def pair_density(ctx: Context, st: States, qj, tr: Transitions, gbasis: torch.Te
     check(_pair(ctx.handle, C.byref(st.c), q, C.byref(tr.c), nt, _ptr(gbasis), n_g,
                 PREC[prec], _ptr(P), _stream(stream)))
     return P
+
+
+def pair_density_range(ctx: Context, st: States, qj, tr: Transitions, gbasis: torch.Tensor,
+                       t_begin: int, t_end: int, prec: str = "fp64", stream=None,
+                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """P of the transitions t_begin .. t_end - 1 (row 0 = t_begin) as a flat
+    uint8 buffer in the layout of pair_density for t_end - t_begin rows."""
+    n_g = gbasis.shape[0]
+    nbytes = pair_density_bytes(t_end - t_begin, n_g, prec)
+    if out is not None and out.numel() >= nbytes:
+        P = out
+    else:
+        P = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=st.eps.device)
+    check(_pair_range(ctx.handle, C.byref(st.c), (C.c_int * 3)(*qj), C.byref(tr.c), int(t_begin),
+                      int(t_end), _ptr(gbasis), n_g, PREC[prec], _ptr(P), _stream(stream)))
+    return P
+
+
+def pair_density_work_bytes(st: States, n_trans: int) -> int:
+    return _lib.tdx_pair_density_work_bytes(C.byref(st.c), int(n_trans))
+
+
+def pair_density_async(ctx: Context, st: States, qj, tr: Transitions, gbasis: torch.Tensor,
+                       P: torch.Tensor, work: torch.Tensor, prec: str = "bf16x3",
+                       t_begin: int = 0, t_end: Optional[int] = None, stream=None):
+    """pair_density into the given buffer P with the caller's work buffer
+    (pair_density_work_bytes): no allocation, copy or memset, so the call
+    can be captured in a HIP graph."""
+    t_end = len(tr) if t_end is None else int(t_end)
+    check(_pair_async(ctx.handle, C.byref(st.c), (C.c_int * 3)(*qj), C.byref(tr.c), int(t_begin),
+                      t_end, _ptr(gbasis), gbasis.shape[0], PREC[prec], _ptr(P), _ptr(work),
+                      work.numel() * work.element_size(), _stream(stream)))
 
 
 def pair_density_view(P: torch.Tensor, n_trans: int, n_g: int, prec: str) -> torch.Tensor:
@@ -721,25 +766,31 @@ def dyson_vjp(ctx: Context, chi0_t: torch.Tensor, K: torch.Tensor, i_g0: int,
 
 def chi0_vjp(ctx: Context, tr: Transitions, P: torch.Tensor, n_g: int, omega: torch.Tensor,
              eta: float, pref: float, u: torch.Tensor, v: torch.Tensor, want_rho: bool = False,
-             stream=None, n_trans: Optional[int] = None):
-    """(w_bar complex [T, 2], rho_bar complex [T, ld] or None) for FP64 P
-    (the first n_trans transitions if given)."""
+             stream=None, t_begin: int = 0, t_end: Optional[int] = None,
+             w_out: Optional[torch.Tensor] = None):
+    """(w_bar float64 [n, 3] = (df_bar, delta_bar, eta_bar_t), rho_bar complex
+    [n, ld] or None) of the transitions t_begin .. t_end - 1 (all by default),
+    n = t_end - t_begin, from their FP64 pair densities P (row 0 = t_begin);
+    w_bar is written into w_out ([n, 3], contiguous) if given."""
     dev = omega.device
-    T = len(tr) if n_trans is None else int(n_trans)
+    t_end = len(tr) if t_end is None else int(t_end)
+    n = t_end - int(t_begin)
     ld = (n_g + 15) // 16 * 16
-    w_bar = torch.zeros((max(T, 1), 2), dtype=torch.complex128, device=dev)
-    rho_bar = (torch.zeros((max(T, 1), ld), dtype=torch.complex128, device=dev)
+    w_bar = (w_out if w_out is not None else
+             torch.zeros((max(n, 1), 3), dtype=torch.float64, device=dev))
+    rho_bar = (torch.zeros((max(n, 1), ld), dtype=torch.complex128, device=dev)
                if want_rho else None)
-    check(_chi0_vjp(ctx.handle, C.byref(tr.c), T, _ptr(P), n_g, _ptr(omega), omega.shape[0], eta,
-                    pref, _ptr(u), _ptr(v), _ptr(w_bar),
+    check(_chi0_vjp(ctx.handle, C.byref(tr.c), int(t_begin), t_end, _ptr(P), n_g, _ptr(omega),
+                    omega.shape[0], eta, pref, _ptr(u), _ptr(v), _ptr(w_bar),
                     _ptr(rho_bar) if rho_bar is not None else None, _stream(stream)))
-    return w_bar[:T], (rho_bar[:T] if rho_bar is not None else None)
+    return w_bar[:n], (rho_bar[:n] if rho_bar is not None else None)
 
 
 def weights_vjp(ctx: Context, st: States, qj, tr: Transitions, w_bar: torch.Tensor,
                 occ_bar: torch.Tensor, eps_bar: torch.Tensor, eta_bar: torch.Tensor,
                 stream=None):
-    """Accumulate occ_bar, eps_bar [n_k, nb_max] and eta_bar [1] from one q's w_bar."""
+    """Accumulate occ_bar, eps_bar [n_k, nb_max] and eta_bar [1] from one q's
+    w_bar [T, 3] (chi0_vjp over the whole list)."""
     q = (C.c_int * 3)(*qj)
     check(_weights_vjp(ctx.handle, C.byref(st.c), q, C.byref(tr.c), len(tr), _ptr(w_bar),
                        _ptr(occ_bar), _ptr(eps_bar), _ptr(eta_bar), _stream(stream)))
@@ -755,11 +806,15 @@ def occupations_vjp(ctx: Context, st: States, occ_bar: torch.Tensor, eps_bar: to
 
 
 def pair_density_vjp(ctx: Context, st: States, qj, tr: Transitions, gbasis: torch.Tensor,
-                     rho_bar: torch.Tensor, coef_bar: torch.Tensor, stream=None):
-    """Accumulate coef_bar [n_k, nb_max, npw_max] from one q's rho_bar."""
+                     rho_bar: torch.Tensor, coef_bar: torch.Tensor, stream=None,
+                     t_begin: int = 0, t_end: Optional[int] = None):
+    """Accumulate coef_bar [n_k, nb_max, npw_max] from rho_bar of the
+    transitions t_begin .. t_end - 1 of one q (row 0 = t_begin)."""
     q = (C.c_int * 3)(*qj)
-    check(_pair_vjp(ctx.handle, C.byref(st.c), q, C.byref(tr.c), len(tr), _ptr(gbasis),
-                    gbasis.shape[0], _ptr(rho_bar), _ptr(coef_bar), _stream(stream)))
+    t_end = len(tr) if t_end is None else int(t_end)
+    check(_pair_vjp(ctx.handle, C.byref(st.c), q, C.byref(tr.c), int(t_begin), t_end,
+                    _ptr(gbasis), gbasis.shape[0], _ptr(rho_bar), _ptr(coef_bar),
+                    _stream(stream)))
 
 
 def potential_vjp(ctx: Context, w, st: States, eps_bar: torch.Tensor, coef_bar: torch.Tensor,

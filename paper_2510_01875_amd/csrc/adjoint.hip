@@ -26,27 +26,25 @@ constexpr int kVjpG = 32;              // response vectors per LDS chunk
 constexpr int kVjpRow = kVjpG + 1;     // padded LDS row (complex)
 
 // chi0 = pref sum_t w_t rho_t rho_t^H with w_t = df_t / (w - delta_t + i eta)
+// (full list) or, for a time-reversal paired list, the combined weight
+// w_t = df_t (r1 - r2), r1 = 1 / (w - delta_t + i eta), r2 = 1 / (w + delta_t + i eta),
 // and the cotangent of chi0(w) given as u(w) v(w)^H.  Then
 //   dL = Re sum_w sum_t pref [dw_t alpha conj(beta)
 //                             + w_t ((u^H d rho) conj(beta) + alpha conj(v^H d rho))],
-// alpha = u^H rho_t, beta = v^H rho_t.  With lambda = pref alpha conj(beta)
-// and r = 1 / (w - delta_t + i eta), dw = r d(df) + df r^2 (d delta - i d eta):
-//   wbar_t = (sum_w lambda r, sum_w lambda r^2),
-//   rhobar_t(G) = sum_w conj(c1) u_G + c2 v_G,  c1 = pref w_t conj(beta),
-//                                                c2 = pref w_t alpha.
-// alpha and beta are one complex product [conj(u); conj(v)] x rho on FP64
-// MFMA (16x16x4) per block of 64 frequencies, conj(u), conj(v) staged in LDS
-// in chunks of 32 G.  Each lane feeds k-step i of a 16-G step with
-// G = 4 (lane/16) + i on both operands, so its P fragment is 64 contiguous
-// bytes.  The epilogue's registers (rows = frequency, cols = transition) are
-// already the A operand of the rhobar product (rows = transition,
-// k = frequency), so rhobar needs no data movement; it is accumulated in the
-// output rows owned by this workgroup (stored on the first block, added on
-// later ones).
+// alpha = u^H rho_t, beta = v^H rho_t.  With lambda = pref alpha conj(beta),
+//   full:   dw = r1 d(df) + df r1^2 d(delta) - i df r1^2 d(eta),
+//   paired: dw = (r1 - r2) d(df) + df (r1^2 + r2^2) d(delta) - i df (r1^2 - r2^2) d(eta),
+// so each transition's real cotangents are
+//   wbar_t = (dfbar, deltabar, etabar_t)
+//          = (Re sum_w lambda dw/d(df), Re sum_w lambda dw/d(delta), Re sum_w lambda dw/d(eta)),
+// and rhobar_t(G) = sum_w conj(c1) u_G + c2 v_G with c1 = pref w_t conj(beta),
+// c2 = pref w_t alpha.
 __global__ void __launch_bounds__(256)
-    k_chi0_vjp(const double2 *P, int ld, long long n_trans, int n_g, const double *delta,
-               const double *df, const double *omega, int n_w, double eta, double pref,
-               const double2 *u, const double2 *v, double2 *wbar, double2 *rhobar) {
+    k_chi0_vjp(const double2 *P, int ld, long long t_lo, long long n_trans, int n_g,
+               const double *delta, const double *df, int paired, const double *omega, int n_w,
+               double eta, double pref, const double2 *u, const double2 *v, double *wbar,
+               double2 *rhobar) {
+  // rows of P, wbar and rhobar are local (row i is transition t_lo + i)
   __shared__ double2 xs[2][kVjpW][kVjpRow];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, quad = lane >> 4;
@@ -54,8 +52,9 @@ __global__ void __launch_bounds__(256)
   const long long t = tw0 + col;
   const long long tc = t < n_trans ? t : n_trans - 1;
   const double2 *prow = P + (size_t)tc * ld;
-  const double dl = delta[tc], dft = df[tc];
-  double s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
+  const double dl = delta[t_lo + tc], dft = df[t_lo + tc];
+  // sums of lambda times dw/d(df), dw/d(delta) / df, i dw/d(eta) / df
+  double sfr = 0.0, sfi = 0.0, sdr = 0.0, sdi = 0.0, ser = 0.0, sei = 0.0;
   for (int w0 = 0; w0 < n_w; w0 += kVjpW) {
     f64x4 acc[kVjpSub][2][2];
 #pragma unroll
@@ -104,16 +103,33 @@ __global__ void __launch_bounds__(256)
         const double br = acc[sub][1][0][j], bi = acc[sub][1][1][j];
         double c1r = 0.0, c1i = 0.0, c2r = 0.0, c2i = 0.0;
         if (wi < n_w) {
+          const double lr = pref * (ar * br + ai * bi), li = pref * (ai * br - ar * bi);
           const double dr = omega[wi] - dl;
           const double inv = 1.0 / (dr * dr + eta * eta);
-          const double rr = dr * inv, ri = -eta * inv;
-          const double lr = pref * (ar * br + ai * bi), li = pref * (ai * br - ar * bi);
-          const double pr = lr * rr - li * ri, pi = lr * ri + li * rr;
-          s1r += pr;
-          s1i += pi;
-          s2r += pr * rr - pi * ri;
-          s2i += pr * ri + pi * rr;
-          const double wr = dft * rr, wim = dft * ri;
+          // r1 = 1 / (w - delta + i eta) and its square
+          const double r1r = dr * inv, r1i = -eta * inv;
+          const double q1r = r1r * r1r - r1i * r1i, q1i = 2.0 * r1r * r1i;
+          double gr = r1r, gi = r1i, hr = q1r, hi = q1i, er = q1r, ei = q1i;
+          if (paired) {
+            // r2 = 1 / (w + delta + i eta): g = r1 - r2, h = r1^2 + r2^2, e = r1^2 - r2^2
+            const double d2 = omega[wi] + dl;
+            const double inv2 = 1.0 / (d2 * d2 + eta * eta);
+            const double r2r = d2 * inv2, r2i = -eta * inv2;
+            const double q2r = r2r * r2r - r2i * r2i, q2i = 2.0 * r2r * r2i;
+            gr = r1r - r2r;
+            gi = r1i - r2i;
+            hr = q1r + q2r;
+            hi = q1i + q2i;
+            er = q1r - q2r;
+            ei = q1i - q2i;
+          }
+          sfr += lr * gr - li * gi;
+          sfi += lr * gi + li * gr;
+          sdr += lr * hr - li * hi;
+          sdi += lr * hi + li * hr;
+          ser += lr * er - li * ei;
+          sei += lr * ei + li * er;
+          const double wr = dft * gr, wim = dft * gi;
           c1r = pref * (wr * br + wim * bi);
           c1i = pref * (wim * br - wr * bi);
           c2r = pref * (wr * ar - wim * ai);
@@ -168,28 +184,31 @@ __global__ void __launch_bounds__(256)
     }
   }
   // lanes of one column hold disjoint frequencies of the same transition
-  s1r += __shfl_xor(s1r, 16);
-  s1i += __shfl_xor(s1i, 16);
-  s2r += __shfl_xor(s2r, 16);
-  s2i += __shfl_xor(s2i, 16);
-  s1r += __shfl_xor(s1r, 32);
-  s1i += __shfl_xor(s1i, 32);
-  s2r += __shfl_xor(s2r, 32);
-  s2i += __shfl_xor(s2i, 32);
+  sfr += __shfl_xor(sfr, 16);
+  sdr += __shfl_xor(sdr, 16);
+  sei += __shfl_xor(sei, 16);
+  sfr += __shfl_xor(sfr, 32);
+  sdr += __shfl_xor(sdr, 32);
+  sei += __shfl_xor(sei, 32);
+  (void)sfi;
+  (void)sdi;
+  (void)ser;
   if (quad == 0 && t < n_trans) {
-    wbar[2 * t] = make_double2(s1r, s1i);
-    wbar[2 * t + 1] = make_double2(s2r, s2i);
+    // dw/d(eta) = -i df e, so Re(lambda dw/d(eta)) = df Im(sum lambda e)
+    wbar[3 * t] = sfr;
+    wbar[3 * t + 1] = dft * sdr;
+    wbar[3 * t + 2] = dft * sei;
   }
 }
 
-// Per-state cotangents of one q from the transition cotangents:
-//   dfbar_t = Re wbar_t[0], deltabar_t = df_t Re wbar_t[1];
+// Per-state cotangents of one q from the transition cotangents
+// wbar_t = (dfbar_t, deltabar_t, etabar_t):
 //   occ_bar(k,n) += sum_{t out of (k,n)} dfbar_t,
 //   occ_bar(k',m) -= sum_{t into (k',m)} dfbar_t,
 //   eps_bar(k',m) += sum_{t into} deltabar_t, eps_bar(k,n) -= sum_{t out} deltabar_t.
 // One thread per state; incoming transitions are found by binary search of
 // m in each row of the source k-point (rows are sorted by m).
-__global__ void k_weights_states(const double2 *wbar, const double *df, const int *tm,
+__global__ void k_weights_states(const double *wbar, const int *tm,
                                  const long long *rowbeg, const long long *rowend, const int *nb,
                                  const int *kinv, int nk, int nb_max, double *occ_bar,
                                  double *eps_bar) {
@@ -199,8 +218,8 @@ __global__ void k_weights_states(const double2 *wbar, const double *df, const in
   if (j >= nb[k]) return;
   double fb = 0.0, eb = 0.0;
   for (long long t = rowbeg[i]; t < rowend[i]; ++t) {
-    fb += wbar[2 * t].x;
-    eb -= df[t] * wbar[2 * t + 1].x;
+    fb += wbar[3 * t];
+    eb -= wbar[3 * t + 1];
   }
   const int k0 = kinv[k];
   for (int n = 0; n < nb[k0]; ++n) {
@@ -215,8 +234,8 @@ __global__ void k_weights_states(const double2 *wbar, const double *df, const in
         hi = mid;
     }
     if (lo < end && tm[lo] == j) {
-      fb -= wbar[2 * lo].x;
-      eb += df[lo] * wbar[2 * lo + 1].x;
+      fb -= wbar[3 * lo];
+      eb += wbar[3 * lo + 1];
     }
   }
   occ_bar[i] += fb;
@@ -225,14 +244,14 @@ __global__ void k_weights_states(const double2 *wbar, const double *df, const in
 
 constexpr int kRedBlocks = 512;
 
-// etabar = sum_t df_t Im wbar_t[1]  (dw/deta = -i df r^2): per-block partial
-// sums over a fixed grid, then one fixed-order final sum.
+// etabar = sum_t etabar_t: per-block partial sums over a fixed grid, then
+// one fixed-order final sum.
 __global__ void __launch_bounds__(256)
-    k_eta_partial(const double2 *wbar, const double *df, long long n, double *part) {
+    k_eta_partial(const double *wbar, long long n, double *part) {
   __shared__ double sh[256];
   double acc = 0.0;
   for (long long t = blockIdx.x * 256LL + threadIdx.x; t < n; t += 256LL * kRedBlocks)
-    acc += df[t] * wbar[2 * t + 1].y;
+    acc += wbar[3 * t + 2];
   sh[threadIdx.x] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -304,13 +323,14 @@ __global__ void __launch_bounds__(kOccThreads)
 
 // Pair-density adjoint, outgoing side:
 //   coef_bar(k,n)(G1) += sum_{t in row (k,n)} sum_G conj(rhobar_t(G)) c_{m_t,k'}(G1 + G + G_s)
+// over the transitions of the range the row tables cover (rhobar row t - t_lo).
 // One workgroup per (k, n) row; threads over G1.
 __global__ void __launch_bounds__(256)
     k_pd_vjp_out(const double2 *coef, const int *miller, const int *npw, int nb_max, int npw_max,
                  const int *tm, const long long *rowbeg, const long long *rowend,
                  const int *kpmap, const int *gsmap, const int *gbasis, int n_g, int ld,
-                 const int *lut, long box, int M0, int M1, int M2, const double2 *rhobar,
-                 double2 *coef_bar) {
+                 const int *lut, long box, int M0, int M1, int M2, long long t_lo,
+                 const double2 *rhobar, double2 *coef_bar) {
   const int n = blockIdx.x, k = blockIdx.y;
   const long long t0 = rowbeg[(size_t)k * nb_max + n], t1 = rowend[(size_t)k * nb_max + n];
   if (t1 <= t0) return;
@@ -330,7 +350,7 @@ __global__ void __launch_bounds__(256)
       const int idx = lutp[((long)x0 * W1 + x1) * W2 + x2];
       if (idx < 0) continue;
       for (long long t = t0; t < t1; ++t) {
-        const double2 rb = rhobar[(size_t)t * ld + g];
+        const double2 rb = rhobar[(size_t)(t - t_lo) * ld + g];
         const double2 c = cp[(size_t)tm[t] * npw_max + idx];
         ar = fma(rb.x, c.x, fma(rb.y, c.y, ar));
         ai = fma(rb.x, c.y, fma(-rb.y, c.x, ai));
@@ -350,8 +370,8 @@ __global__ void __launch_bounds__(256)
     k_pd_vjp_in(const double2 *coef, const int *miller, const int *npw, const int *nb, int nb_max,
                 int npw_max, const int *tm, const long long *rowbeg, const long long *rowend,
                 const int *kpmap, const int *gsmap, const int *gbasis, int n_g, int ld,
-                const int *lut, long box, int M0, int M1, int M2, const double2 *rhobar,
-                double2 *coef_bar) {
+                const int *lut, long box, int M0, int M1, int M2, long long t_lo,
+                const double2 *rhobar, double2 *coef_bar) {
   extern __shared__ long long tof[];  // [nb_max] transition of (k, n, m) or -1
   const int m = blockIdx.x, k = blockIdx.y;
   const int kp = kpmap[k];
@@ -388,7 +408,7 @@ __global__ void __launch_bounds__(256)
       for (int n = 0; n < nbk; ++n) {
         const long long t = tof[n];
         if (t < 0) continue;
-        const double2 rb = rhobar[(size_t)t * ld + g];
+        const double2 rb = rhobar[(size_t)(t - t_lo) * ld + g];
         const double2 c = ck[(size_t)n * npw_max + idx];
         ar = fma(rb.x, c.x, fma(-rb.y, c.y, ar));
         ai = fma(rb.x, c.y, fma(rb.y, c.x, ai));
@@ -493,7 +513,7 @@ struct QTables {
 };
 
 int q_tables(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const tdx_translist *tl,
-             long long n_trans, bool with_lut, hipStream_t s, QTables *q) {
+             long long t_lo, long long t_hi, bool with_lut, hipStream_t s, QTables *q) {
   const int nk = st->n_k, nb_max = st->nb_max;
   const int M0 = st->mmax[0], M1 = st->mmax[1], M2 = st->mmax[2];
   q->box = (long)(2 * M0 + 1) * (2 * M1 + 1) * (2 * M2 + 1);
@@ -519,7 +539,7 @@ int q_tables(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const tdx_tran
   TDX_HIP(hipMemcpyAsync(q->kinv, kinv.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
   TDX_HIP(hipMemsetAsync(q->rowbeg, 0, row_bytes, s));
   hipLaunchKernelGGL(k_rows, dim3(nk), dim3(256), 0, s, (const long long *)tl->k_offsets, tl->n,
-                     nb_max, n_trans, q->rowbeg, q->rowend);
+                     nb_max, t_lo, t_hi, q->rowbeg, q->rowend);
   TDX_HIP(hipGetLastError());
   if (with_lut) {
     TDX_HIP(hipMemsetAsync(q->lut, 0xff, lut_bytes, s));
@@ -570,24 +590,24 @@ int tdx_dsf_vjp(tdx_ctx *ctx, const double *chi00, const double *omega, int n_w,
   return TDX_OK;
 }
 
-int tdx_chi0_vjp(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, const double *P, int n_g,
-                 const double *omega, int n_w, double eta, double pref, const double *u,
-                 const double *v, double *w_bar, double *rho_bar, tdx_stream stream) {
+int tdx_chi0_vjp(tdx_ctx *ctx, const tdx_translist *tl, int64_t t_begin, int64_t t_end,
+                 const double *P, int n_g, const double *omega, int n_w, double eta, double pref,
+                 const double *u, const double *v, double *w_bar, double *rho_bar,
+                 tdx_stream stream) {
   clear_error();
   TDX_REQUIRE(ctx && tl && P && omega && u && v && w_bar, TDX_ERR_INVALID_ARG, "null argument");
-  TDX_REQUIRE(!tl->paired, TDX_ERR_INVALID_ARG,
-              "reverse mode needs the full (unpaired) transition list");
-  TDX_REQUIRE(n_g > 0 && n_w > 0 && n_trans >= 0 && n_trans <= tl->capacity, TDX_ERR_SHAPE,
-              "bad sizes");
+  TDX_REQUIRE(n_g > 0 && n_w > 0 && t_begin >= 0 && t_begin <= t_end && t_end <= tl->capacity,
+              TDX_ERR_SHAPE, "bad sizes");
   TDX_REQUIRE(std::isfinite(eta) && std::isfinite(pref), TDX_ERR_INVALID_ARG, "bad eta or pref");
   TDX_TRY(check_device(ctx));
-  if (n_trans == 0) return TDX_OK;
-  const long long blocks = (n_trans + kVjpT - 1) / kVjpT;
+  const long long n = t_end - t_begin;
+  if (n == 0) return TDX_OK;
+  const long long blocks = (n + kVjpT - 1) / kVjpT;
   TDX_REQUIRE(blocks <= 0x7fffffffLL, TDX_ERR_SHAPE, "too many transitions");
   hipLaunchKernelGGL(k_chi0_vjp, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream),
-                     (const double2 *)P, ld_of(n_g), (long long)n_trans, n_g, tl->delta, tl->df,
-                     omega, n_w, eta, pref, (const double2 *)u, (const double2 *)v,
-                     (double2 *)w_bar, (double2 *)rho_bar);
+                     (const double2 *)P, ld_of(n_g), (long long)t_begin, n, n_g, tl->delta,
+                     tl->df, (int)tl->paired, omega, n_w, eta, pref, (const double2 *)u,
+                     (const double2 *)v, w_bar, (double2 *)rho_bar);
   TDX_HIP(hipGetLastError());
   return TDX_OK;
 }
@@ -598,21 +618,19 @@ int tdx_weights_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const t
   clear_error();
   TDX_REQUIRE(ctx && st && qj && tl && w_bar && occ_bar && eps_bar && eta_bar,
               TDX_ERR_INVALID_ARG, "null argument");
-  TDX_REQUIRE(!tl->paired, TDX_ERR_INVALID_ARG,
-              "reverse mode needs the full (unpaired) transition list");
   TDX_REQUIRE(n_trans >= 0 && n_trans <= tl->capacity, TDX_ERR_SHAPE, "bad sizes");
   TDX_TRY(check_device(ctx));
   if (n_trans == 0) return TDX_OK;
   hipStream_t s = as_stream(stream);
   QTables q;
-  TDX_TRY(q_tables(ctx, st, qj, tl, n_trans, false, s, &q));
+  TDX_TRY(q_tables(ctx, st, qj, tl, 0, n_trans, false, s, &q));
   const long tot = (long)st->n_k * st->nb_max;
   hipLaunchKernelGGL(k_weights_states, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     (const double2 *)w_bar, tl->df, tl->m, q.rowbeg, q.rowend, st->nb, q.kinv,
-                     st->n_k, st->nb_max, occ_bar, eps_bar);
+                     w_bar, tl->m, q.rowbeg, q.rowend, st->nb, q.kinv, st->n_k, st->nb_max,
+                     occ_bar, eps_bar);
   TDX_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_eta_partial, dim3(kRedBlocks), dim3(256), 0, s, (const double2 *)w_bar,
-                     tl->df, (long long)n_trans, q.part);
+  hipLaunchKernelGGL(k_eta_partial, dim3(kRedBlocks), dim3(256), 0, s, w_bar,
+                     (long long)n_trans, q.part);
   TDX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_sum_into, dim3(1), dim3(256), 0, s, q.part, kRedBlocks, eta_bar);
   TDX_HIP(hipGetLastError());
@@ -634,32 +652,33 @@ int tdx_occupations_vjp(tdx_ctx *ctx, const tdx_states *st, const double *occ_ba
 }
 
 int tdx_pair_density_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
-                         const tdx_translist *tl, int64_t n_trans, const int *gbasis, int n_g,
-                         const double *rho_bar, double *coef_bar, tdx_stream stream) {
+                         const tdx_translist *tl, int64_t t_begin, int64_t t_end,
+                         const int *gbasis, int n_g, const double *rho_bar, double *coef_bar,
+                         tdx_stream stream) {
   clear_error();
   TDX_REQUIRE(ctx && st && qj && tl && gbasis && rho_bar && coef_bar, TDX_ERR_INVALID_ARG,
               "null argument");
-  TDX_REQUIRE(!tl->paired, TDX_ERR_INVALID_ARG,
-              "reverse mode needs the full (unpaired) transition list");
-  TDX_REQUIRE(n_g > 0 && n_trans >= 0 && n_trans <= tl->capacity, TDX_ERR_SHAPE, "bad sizes");
+  TDX_REQUIRE(n_g > 0 && t_begin >= 0 && t_begin <= t_end && t_end <= tl->capacity,
+              TDX_ERR_SHAPE, "bad sizes");
   TDX_REQUIRE((size_t)st->nb_max * sizeof(long long) <= 64 * 1024, TDX_ERR_SHAPE,
               "band capacity %d too large for the adjoint kernel", st->nb_max);
   TDX_TRY(check_device(ctx));
-  if (n_trans == 0) return TDX_OK;
+  if (t_end == t_begin) return TDX_OK;
   hipStream_t s = as_stream(stream);
   QTables q;
-  TDX_TRY(q_tables(ctx, st, qj, tl, n_trans, true, s, &q));
+  TDX_TRY(q_tables(ctx, st, qj, tl, t_begin, t_end, true, s, &q));
   const int M0 = st->mmax[0], M1 = st->mmax[1], M2 = st->mmax[2];
   dim3 grid(st->nb_max, st->n_k);
   hipLaunchKernelGGL(k_pd_vjp_out, grid, dim3(256), 0, s, (const double2 *)st->coef, st->miller,
                      st->npw, st->nb_max, st->npw_max, tl->m, q.rowbeg, q.rowend, q.kp, q.gs,
-                     gbasis, n_g, ld_of(n_g), q.lut, q.box, M0, M1, M2, (const double2 *)rho_bar,
-                     (double2 *)coef_bar);
+                     gbasis, n_g, ld_of(n_g), q.lut, q.box, M0, M1, M2, (long long)t_begin,
+                     (const double2 *)rho_bar, (double2 *)coef_bar);
   TDX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_pd_vjp_in, grid, dim3(256), sizeof(long long) * st->nb_max, s,
                      (const double2 *)st->coef, st->miller, st->npw, st->nb, st->nb_max,
                      st->npw_max, tl->m, q.rowbeg, q.rowend, q.kp, q.gs, gbasis, n_g, ld_of(n_g),
-                     q.lut, q.box, M0, M1, M2, (const double2 *)rho_bar, (double2 *)coef_bar);
+                     q.lut, q.box, M0, M1, M2, (long long)t_begin, (const double2 *)rho_bar,
+                     (double2 *)coef_bar);
   TDX_HIP(hipGetLastError());
   return TDX_OK;
 }

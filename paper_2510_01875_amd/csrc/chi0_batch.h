@@ -18,13 +18,27 @@ struct BatchItem {
   int paired;  // time-reversal paired transition list
   int n_g;
   double2 *part;  // [slices][n_w][n_g][n_g]
+  int lc;         // rows and columns of the main tiles (ld, or nm with tail tiles)
+  int nm, tail;   // tail tiles: basis rows nm .. nm + tail - 1 (tail = 0: none)
+  double2 *tpart; // [slices][n_w][tail][2][ld]
 };
 
-// One tile of the work queue.
+// One tile of the work queue; gb < 0 marks a tail tile whose wblk counts
+// groups of virtual rows.
 struct BatchTile {
   int item, wblk, gb, gc;
   long long slice;
 };
+
+// Rows and columns [0, nm) of a basis run in main tiles, rows nm .. n_g - 1
+// (tail of them) in tail tiles; nm = ld and tail = 0 when n_g is a multiple
+// of 16 or the variant is pipelined.
+struct TailSplit {
+  int nm, tail;
+};
+TailSplit bf16x3_split(int v, int n_g);
+// Workgroups of virtual tail rows (2 tail per frequency) for n_w frequencies.
+int bf16x3_tail_groups(int v, int n_w, int tail);
 
 int bf16x3_variant_count();
 // Variant used for a basis size with no tuned entry: the 8-wave 2 x 9 tile
@@ -43,7 +57,8 @@ inline const void *bf16x3_rho(const void *P, long long p_rows, int ld) {
 int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double *delta,
                        const double *df,
                        long long n_trans, long long slice_len, int slices, const double *omega,
-                       int n_w, double eta, int paired, int n_g, double2 *part, hipStream_t s);
+                       int n_w, double eta, int paired, int n_g, double2 *part, double2 *tpart,
+                       hipStream_t s);
 int bf16x3_launch_persistent(int v, const BatchItem *items, const BatchTile *tiles, int n_tiles,
                              int n_blocks, hipStream_t s);
 

@@ -17,41 +17,61 @@ namespace {
 constexpr int kChunkAlign = 32;   // slice lengths are multiples of every variant's chunk
 constexpr int kMinTiles = 2048;   // fill the chip: 256 CUs x 2 workgroups x 4
 
-__global__ void k_reduce_slices(const double2 *part, int n_slices, size_t per_slice, double pref,
-                                double2 *out) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per_slice;
-       i += (size_t)gridDim.x * blockDim.x) {
-    double re = 0.0, im = 0.0;
-    for (int s = 0; s < n_slices; ++s) {
-      const double2 v = part[(size_t)s * per_slice + i];
-      re += v.x;
-      im += v.y;
-    }
-    out[i] = make_double2(pref * re, pref * im);
-  }
-}
-
+// The slice reduction of one q: chi0[w][G][G'] = pref sum over slices, in
+// slice order, of the main partials (G, G' < nm) or, with tail tiles, of the
+// tail rows of H_R and H_A: rows G >= nm are H_R + i H_A of the tail row
+// G - nm, columns G' >= nm (G < nm) are conj(H_R) + i conj(H_A) of the tail
+// row G' - nm at column G (H_R and H_A are Hermitian).
 struct ReduceItem {
   const double2 *part;
   int n_slices;
-  size_t per_slice;
+  int n_w, n_g, nm, tail, ld;
   double pref;
+  const double2 *tpart;
   double2 *out;
 };
+
+__device__ inline void reduce_one(const ReduceItem &it, size_t i) {
+  const size_t per = (size_t)it.n_w * it.n_g * it.n_g;
+  const size_t tper = (size_t)it.n_w * it.tail * 2 * it.ld;
+  const int w = (int)(i / ((size_t)it.n_g * it.n_g));
+  const int rem = (int)(i % ((size_t)it.n_g * it.n_g));
+  const int G = rem / it.n_g, Gp = rem % it.n_g;
+  double re = 0.0, im = 0.0;
+  if (it.tail == 0 || (G < it.nm && Gp < it.nm)) {
+    for (int s = 0; s < it.n_slices; ++s) {
+      const double2 v = it.part[(size_t)s * per + i];
+      re += v.x;
+      im += v.y;
+    }
+  } else {
+    const bool row = G >= it.nm;
+    const int g = row ? G - it.nm : Gp - it.nm, col = row ? Gp : G;
+    const size_t o = (((size_t)w * it.tail + g) * 2) * it.ld + col;
+    for (int s = 0; s < it.n_slices; ++s) {
+      const double2 hr = it.tpart[(size_t)s * tper + o];
+      const double2 ha = it.tpart[(size_t)s * tper + o + it.ld];
+      re += row ? hr.x - ha.y : hr.x + ha.y;
+      im += row ? hr.y + ha.x : ha.x - hr.y;
+    }
+  }
+  it.out[i] = make_double2(it.pref * re, it.pref * im);
+}
+
+__global__ void k_reduce_slices(ReduceItem it) {
+  const size_t n = (size_t)it.n_w * it.n_g * it.n_g;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    reduce_one(it, i);
+}
 
 // Slice reduction of every item of a batch (blockIdx.y = item).
 __global__ void k_reduce_batch(const ReduceItem *items) {
   const ReduceItem it = items[blockIdx.y];
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < it.per_slice;
-       i += (size_t)gridDim.x * blockDim.x) {
-    double re = 0.0, im = 0.0;
-    for (int s = 0; s < it.n_slices; ++s) {
-      const double2 v = it.part[(size_t)s * it.per_slice + i];
-      re += v.x;
-      im += v.y;
-    }
-    it.out[i] = make_double2(it.pref * re, it.pref * im);
-  }
+  const size_t n = (size_t)it.n_w * it.n_g * it.n_g;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    reduce_one(it, i);
 }
 
 int bucket_of(int ld) { return std::min(ld / 16, 63); }
@@ -83,10 +103,14 @@ void slicing(const tdx_ctx *ctx, long long n_trans, int slice_log2, long long ti
   *slices = (int)((n_trans + len - 1) / len);
 }
 
-long long tiles_per_slice(int v, int n_w, int ld) {
+// Main tiles of one slice plus its tail tiles.
+long long tiles_per_slice(int v, int n_w, int n_g) {
   int wb, cols;
   bf16x3_variant_shape(v, &wb, &cols);
-  return (long long)((n_w + wb - 1) / wb) * (ld / 16) * ((ld + cols - 1) / cols);
+  const int ld = (n_g + 15) / 16 * 16;
+  const TailSplit sp = bf16x3_split(v, n_g);
+  return (long long)((n_w + wb - 1) / wb) * (sp.nm / 16) * ((sp.nm + cols - 1) / cols) +
+         (long long)bf16x3_tail_groups(v, n_w, sp.tail) * ((ld + cols - 1) / cols);
 }
 
 }  // namespace
@@ -97,18 +121,21 @@ int chi0_bf16x3_with(tdx_ctx *ctx, int v, int slice_log2, const void *P, long lo
                      double pref, double2 *chi0, hipStream_t s) {
   long long slice_len;
   int slices;
-  slicing(ctx, n_trans, slice_log2, tiles_per_slice(v, n_w, ld), &slice_len, &slices);
+  slicing(ctx, n_trans, slice_log2, tiles_per_slice(v, n_w, n_g), &slice_len, &slices);
   TDX_REQUIRE(slices <= 65535, TDX_ERR_SHAPE, "%d slices exceed the grid (slice length %lld)",
               slices, slice_len);
+  const TailSplit sp = bf16x3_split(v, n_g);
   const size_t out_elems = (size_t)n_w * n_g * n_g;
+  const size_t tail_elems = (size_t)n_w * sp.tail * 2 * ld;
   void *w;
-  TDX_TRY(ws_get(ctx, WS_PARTIAL, sizeof(double2) * out_elems * slices, &w));
+  TDX_TRY(ws_get(ctx, WS_PARTIAL, sizeof(double2) * (out_elems + tail_elems) * slices, &w));
   double2 *part = (double2 *)w;
+  double2 *tpart = part + out_elems * slices;
   TDX_TRY(bf16x3_launch_grid(v, P, bf16x3_rho(P, p_rows, ld), ld, delta, df, n_trans, slice_len,
-                             slices, omega, n_w, eta, paired, n_g, part, s));
+                             slices, omega, n_w, eta, paired, n_g, part, tpart, s));
   const unsigned rb = (unsigned)std::min<size_t>((out_elems + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_reduce_slices, dim3(rb), dim3(256), 0, s, part, slices, out_elems, pref,
-                     chi0);
+  const ReduceItem ri{part, slices, n_w, n_g, sp.nm, sp.tail, ld, pref, tpart, chi0};
+  hipLaunchKernelGGL(k_reduce_slices, dim3(rb), dim3(256), 0, s, ri);
   TDX_HIP(hipGetLastError());
   return TDX_OK;
 }
@@ -226,10 +253,12 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
     pick(ctx, ld, &vi, &sl);
     long long slice_len;
     int slices;
-    slicing(ctx, it.n_trans, sl, tiles_per_slice(v, it.n_w, ld), &slice_len, &slices);
+    slicing(ctx, it.n_trans, sl, tiles_per_slice(v, it.n_w, it.n_g), &slice_len, &slices);
+    const TailSplit sp = bf16x3_split(v, it.n_g);
     const size_t per = (size_t)it.n_w * it.n_g * it.n_g;
+    const size_t tper = (size_t)it.n_w * sp.tail * 2 * ld;
     part_off[i] = part_bytes;
-    part_bytes += per * slices * sizeof(double2);
+    part_bytes += (per + tper) * slices * sizeof(double2);
     p->max_per_slice = std::max(p->max_per_slice, per);
     // the FP32 rows follow the fragment words of all p_rows transitions the
     // buffer was written for, of which the first n_trans are contracted
@@ -237,9 +266,17 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
     bi[i] = BatchItem{it.P,        bf16x3_rho(it.P, rows, ld), ld, it.tl->delta,
                       it.tl->df,   (long long)it.n_trans, slice_len, it.omega,
                       it.n_w,      it.eta,      (int)it.tl->paired,   it.n_g,
+                      nullptr,     sp.nm,       sp.nm,        sp.tail,
                       nullptr};
-    ri[i] = ReduceItem{nullptr, slices, per, it.pref, (double2 *)it.chi0};
-    const int nwb = (it.n_w + wb - 1) / wb, ngb = ld / 16, ncb = (ld + cols - 1) / cols;
+    ri[i] = ReduceItem{nullptr, slices, it.n_w, it.n_g, sp.nm, sp.tail, ld, it.pref, nullptr,
+                       (double2 *)it.chi0};
+    const int nwb = (it.n_w + wb - 1) / wb, ngb = sp.nm / 16, ncb = (sp.nm + cols - 1) / cols;
+    // tail tiles (gb = -1) first, as they hold the most column blocks:
+    // groups of virtual rows over every column tile
+    const int ntg = bf16x3_tail_groups(v, it.n_w, sp.tail), nct = (ld + cols - 1) / cols;
+    for (int s = 0; s < slices; ++s)
+      for (int c = 0; c < nct; ++c)
+        for (int a = 0; a < ntg; ++a) tiles.push_back(BatchTile{i, a, -1, c, s});
     // frequency block fastest: consecutive tiles read the same rho rows
     for (int s = 0; s < slices; ++s)
       for (int g = 0; g < ngb; ++g)
@@ -268,7 +305,10 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
   char *base = (char *)p->mem;
   for (int i = 0; i < n_items; ++i) {
     bi[i].part = (double2 *)(base + part_off[i]);
+    bi[i].tpart = bi[i].part + (size_t)bi[i].n_w * bi[i].n_g * bi[i].n_g *
+                                   ri[i].n_slices;
     ri[i].part = bi[i].part;
+    ri[i].tpart = bi[i].tpart;
   }
   p->items = (BatchItem *)(base + off_items);
   p->reduce = (ReduceItem *)(base + off_reduce);

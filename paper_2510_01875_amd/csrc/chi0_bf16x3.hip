@@ -156,21 +156,106 @@ struct DmaPlan {
   }
 };
 
+// Rows of a tail tile.  When n_g is not a multiple of 16 the basis rows (and
+// columns) nm .. n_g - 1, nm = 16 floor(n_g / 16), would fill only part of a
+// 16-row MFMA block.  chi0 = H_R + i H_A with the Hermitian
+//   H_R = pref sum_t Re(w_t) rho_t rho_t^H,  H_A = pref sum_t Im(w_t) rho_t rho_t^H,
+// so the main tiles cover rows and columns [0, nm) only, and tail tiles
+// compute the rows nm + g of H_R and H_A over every column: virtual rows
+// r = (w tail + g) 2 + p (p = 0: weight Re w_t(w), p = 1: Im w_t(w)) packed
+// 16 to an MFMA block across frequencies.  Those rows give chi0's rows
+// nm + g directly and its columns nm + g through H = H^H (the reduction
+// assembles them).
+struct TailGeom {
+  int nm, tail;     // first tail row of the basis and the tail row count
+  int r0;           // first virtual row of the workgroup
+  double2 *tpart;   // the slice's [n_w][tail][2][ld] FP64 partial
+};
+
+// Fold of a tail tile: output row 4(l/16) + j of block i is virtual row
+// r0 + 16 (wave WPW + i) + 4 (l/16) + j.
+template <int WPW, int SUB>
+__device__ inline void fold_tail(f32x4 (&ar)[WPW][SUB], f32x4 (&ai)[WPW][SUB], const TailGeom &tg,
+                                 int n_w, int ld, int col0, int lane, int wave, bool first) {
+#pragma unroll
+  for (int i = 0; i < WPW; ++i) {
+#pragma unroll
+    for (int b = 0; b < SUB; ++b) {
+      const int col = col0 + b * 16 + (lane & 15);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int v = tg.r0 + 16 * (wave * WPW + i) + 4 * (lane >> 4) + j;
+        const int w = v / (2 * tg.tail);
+        if (w < n_w && col < ld) {
+          double2 *d = tg.tpart + (size_t)v * ld + col;
+          double2 x = make_double2((double)ar[i][b][j], (double)ai[i][b][j]);
+          if (!first) {
+            const double2 o = *d;
+            x.x += o.x;
+            x.y += o.y;
+          }
+          *d = x;
+        }
+      }
+      ar[i][b] = f32x4{0, 0, 0, 0};
+      ai[i][b] = f32x4{0, 0, 0, 0};
+    }
+  }
+}
+
 // One tile: rows row0..row0+15, columns col0..col0+16*NSUB-1, frequencies
 // w0..w0+kWBlock-1, transitions [t_lo, t_hi).  Sums run in FP32 for at most
 // kFoldChunks chunks and are folded into part (the slice's [n_w][n_g][n_g]
 // block, FP64) between runs.  DEPTH LDS buffers: the transfers of chunk
 // c + DEPTH - 1 are issued in iteration c; with three buffers the wait at the
-// end of an iteration leaves that iteration's transfers in flight.
-template <int WPW, int SUB, int CHUNK, int NSUB, int DEPTH, int NW>
+// end of an iteration leaves that iteration's transfers in flight.  A tail
+// tile (TAIL) runs the virtual rows of tg instead (row0 = tg.nm): each lane
+// forms its own weights from the chunk's delta and df, which replace the
+// weight table in LDS.
+template <int WPW, int SUB, int CHUNK, int NSUB, int DEPTH, int NW, bool TAIL = false>
 __device__ __attribute__((always_inline)) void chi0_tile(
     unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
-    int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
+    int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part,
+    TailGeom tg = TailGeom{}) {
   typedef Cfg<WPW, SUB, CHUNK, NW> C;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int kq = lane >> 4;
+  static_assert(!TAIL || 2 * CHUNK * 8 <= C::kWtWords * 4, "delta/df of a chunk fit the weights");
+  // tail tiles: the lane's virtual row of each of its WPW blocks
+  double t_om[WPW];
+  float t_di[WPW];
+  int t_g[WPW];
+  bool t_re[WPW], t_ok[WPW];
+  if constexpr (TAIL) {
+#pragma unroll
+    for (int i = 0; i < WPW; ++i) {
+      const int v = tg.r0 + 16 * (wave * WPW + i) + (lane & 15);
+      const int w = v / (2 * tg.tail), rem = v % (2 * tg.tail);
+      t_ok[i] = w < n_w;
+      t_om[i] = omega[std::min(w, n_w - 1)];
+      t_di[i] = (float)(2.0 * t_om[i] * eta);
+      t_g[i] = rem >> 1;
+      t_re[i] = (rem & 1) == 0;
+    }
+  }
+  // tail tiles: delta and df of one chunk into LDS (thread tid < CHUNK takes
+  // transition tid; zero past the slice, which zeroes the weight)
+  double t_d = 0.0, t_f = 0.0;
+  auto tail_load = [&](long long tc) {
+    const long long t = tc + tid;
+    const bool ok = tid < CHUNK && t < t_hi;
+    t_d = ok ? delta[t] : 0.0;
+    t_f = ok ? df[t] : 0.0;
+  };
+  auto tail_store = [&](unsigned int *buf) {
+    double *dd = (double *)(buf + C::kBWords + C::kRhoWords);
+    if (tid < CHUNK) {
+      dd[tid] = t_d;
+      dd[CHUNK + tid] = t_f;
+    }
+  };
 
   f32x4 ar[WPW][NSUB], ai[WPW][NSUB];
 #pragma unroll
@@ -193,9 +278,14 @@ __device__ __attribute__((always_inline)) void chi0_tile(
   for (int k = 0; k < DEPTH - 1; ++k) {
     if (t_lo + k * CHUNK >= t_hi) break;
     dma.issue((size_t)k * chunk_bytes, lds + k * C::kBufWords);
-    load_weights<C>(pw, delta, df, t_lo + k * CHUNK, t_max, tid);
-    store_weights<C>(pw, (float2 *)(lds + k * C::kBufWords + C::kBWords + C::kRhoWords), om, w_ok,
-                     eta, paired, tid, t_lo + k * CHUNK, t_hi);
+    if constexpr (TAIL) {
+      tail_load(t_lo + k * CHUNK);
+      tail_store(lds + k * C::kBufWords);
+    } else {
+      load_weights<C>(pw, delta, df, t_lo + k * CHUNK, t_max, tid);
+      store_weights<C>(pw, (float2 *)(lds + k * C::kBufWords + C::kBWords + C::kRhoWords), om,
+                       w_ok, eta, paired, tid, t_lo + k * CHUNK, t_hi);
+    }
   }
   wait_vm();
   __syncthreads();
@@ -208,7 +298,12 @@ __device__ __attribute__((always_inline)) void chi0_tile(
       const long long nx = tc + (DEPTH - 1) * CHUNK;
       const bool more = nx < t_hi;
       // weights first: a partial wait below leaves the transfers in flight
-      if (more) load_weights<C>(pw, delta, df, nx, t_max, tid);
+      if (more) {
+        if constexpr (TAIL)
+          tail_load(nx);
+        else
+          load_weights<C>(pw, delta, df, nx, t_max, tid);
+      }
       // the transfers of chunk nx go out one slot per column block of the
       // first K-steps rather than all at once: a burst of them at the top of
       // the chunk stalls the MFMAs of every wave of the CU
@@ -222,8 +317,10 @@ __device__ __attribute__((always_inline)) void chi0_tile(
 #pragma unroll
       for (int s = 0; s < C::kSteps; ++s) {
         float2 rho[4];
+        if constexpr (!TAIL) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) rho[j] = rq[(s * 4 + j) * 64 + lane];
+          for (int j = 0; j < 4; ++j) rho[j] = rq[(s * 4 + j) * 64 + lane];
+        }
         // A and A_rot of the WPW frequencies, split: (hi, lo) words per
         // transition j of the lane's quad
         u32x4 ah[WPW], al[WPW], rh[WPW], rl[WPW];
@@ -231,9 +328,35 @@ __device__ __attribute__((always_inline)) void chi0_tile(
         for (int i = 0; i < WPW; ++i) {
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const float2 w = wt[((s * 4 + j) * C::kWBlock + wave * WPW + i) * 4 + kq];
-            const float are = fmaf(w.x, rho[j].x, -w.y * rho[j].y);
-            const float aim = fmaf(w.x, rho[j].y, w.y * rho[j].x);
+            float are, aim;
+            if constexpr (TAIL) {
+              // the lane's weight, formed as store_weights forms it, then
+              // its real (H_R) or imaginary (H_A) part times rho(nm + g)
+              const double *dd = (const double *)wt;
+              const int tl = 16 * s + 4 * kq + j;
+              const double dl = dd[tl], fv = dd[CHUNK + tl];
+              float wr, wim;
+              if (paired) {
+                const float dr = (float)((t_om[i] - dl) * (t_om[i] + dl) - eta * eta);
+                const float sc = (float)(2.0 * fv * dl) *
+                                 __builtin_amdgcn_rcpf(fmaf(dr, dr, t_di[i] * t_di[i]));
+                wr = sc * dr;
+                wim = -sc * t_di[i];
+              } else {
+                const float x = (float)(t_om[i] - dl), etaf = (float)eta;
+                const float sc = (float)fv * __builtin_amdgcn_rcpf(fmaf(x, x, etaf * etaf));
+                wr = sc * x;
+                wim = -sc * etaf;
+              }
+              const float cw = t_ok[i] ? (t_re[i] ? wr : wim) : 0.f;
+              const float2 rv = rq[(s * 4 + j) * 64 + kq * 16 + t_g[i]];
+              are = cw * rv.x;
+              aim = cw * rv.y;
+            } else {
+              const float2 w = wt[((s * 4 + j) * C::kWBlock + wave * WPW + i) * 4 + kq];
+              are = fmaf(w.x, rho[j].x, -w.y * rho[j].y);
+              aim = fmaf(w.x, rho[j].y, w.y * rho[j].x);
+            }
             const unsigned int h = cvt_pk(are, aim);
             const float dre = are - lo_f(h), dim = aim - hi_f(h);
             ah[i][j] = h;
@@ -274,9 +397,13 @@ __device__ __attribute__((always_inline)) void chi0_tile(
           __builtin_amdgcn_sched_barrier(0);
         }
       }
-      if (more)
-        store_weights<C>(pw, (float2 *)(lds + ahead * C::kBufWords + C::kBWords + C::kRhoWords),
-                         om, w_ok, eta, paired, tid, nx, t_hi);
+      if (more) {
+        if constexpr (TAIL)
+          tail_store(lds + ahead * C::kBufWords);
+        else
+          store_weights<C>(pw, (float2 *)(lds + ahead * C::kBufWords + C::kBWords + C::kRhoWords),
+                           om, w_ok, eta, paired, tid, nx, t_hi);
+      }
       if (DEPTH > 2 && more)
         wait_vm_n<DmaPlan<C, NSUB>::kIssued>();
       else
@@ -285,7 +412,10 @@ __device__ __attribute__((always_inline)) void chi0_tile(
       cur = cur == DEPTH - 1 ? 0 : cur + 1;
       ahead = ahead == DEPTH - 1 ? 0 : ahead + 1;
     }
-    fold<WPW, NSUB>(ar, ai, part, n_w, n_g, w0, row0, col0, lane, wave, first);
+    if constexpr (TAIL)
+      fold_tail<WPW, NSUB>(ar, ai, tg, n_w, ld, col0, lane, wave, first);
+    else
+      fold<WPW, NSUB>(ar, ai, part, n_w, n_g, w0, row0, col0, lane, wave, first);
     first = false;
   }
 }
@@ -293,21 +423,23 @@ __device__ __attribute__((always_inline)) void chi0_tile(
 // The tile routine for the tile's number of 16-column blocks inside the
 // padded basis (ld is a multiple of 16): full tiles run NSUB = SUB, the last
 // tile of a row may run fewer.
-template <int WPW, int SUB, int CHUNK, int DEPTH, int NW, int NSUB = SUB>
+template <int WPW, int SUB, int CHUNK, int DEPTH, int NW, bool TAIL = false, int NSUB = SUB>
 __device__ __attribute__((always_inline)) void chi0_tile_n(
     int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
     const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
-    int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part) {
+    int n_w, double eta, int paired, int n_g, int w0, int row0, int col0, double2 *part,
+    TailGeom tg = TailGeom{}) {
   if constexpr (NSUB > 1) {
     if (nsub < NSUB) {
-      chi0_tile_n<WPW, SUB, CHUNK, DEPTH, NW, NSUB - 1>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo,
-                                                     t_hi, omega, n_w, eta, paired, n_g, w0, row0, col0,
-                                                     part);
+      chi0_tile_n<WPW, SUB, CHUNK, DEPTH, NW, TAIL, NSUB - 1>(
+          nsub, lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega, n_w, eta, paired, n_g, w0,
+          row0, col0, part, tg);
       return;
     }
   }
-  chi0_tile<WPW, SUB, CHUNK, NSUB, DEPTH, NW>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi, omega,
-                                          n_w, eta, paired, n_g, w0, row0, col0, part);
+  chi0_tile<WPW, SUB, CHUNK, NSUB, DEPTH, NW, TAIL>(lds, P, R, ld, delta, df, n_trans, t_lo, t_hi,
+                                                    omega, n_w, eta, paired, n_g, w0, row0, col0,
+                                                    part, tg);
 }
 
 // ---------------------------------------------------------------------------
@@ -608,8 +740,24 @@ __device__ __attribute__((always_inline)) void run_tile(
                                         omega, n_w, eta, paired, n_g, w0, row0, col0, part);
 }
 
-// One tile per workgroup; logical tile = (frequency block fastest, then
-// (G block, G' block), then slice).  OCC = workgroups per CU: 2 for the
+// The tail tile of a variant (plain tiles only: a pipelined variant keeps
+// the padded rows and columns and has no tail tiles).
+template <int WPW, int SUB, int CHUNK, bool PIPE, int DEPTH, int NW>
+__device__ __attribute__((always_inline)) void run_tail_tile(
+    int nsub, unsigned int *lds, const void *P, const void *R, int ld, const double *delta,
+    const double *df, long long n_trans, long long t_lo, long long t_hi, const double *omega,
+    int n_w, double eta, int paired, int n_g, int col0, const TailGeom &tg) {
+  if constexpr (!PIPE)
+    chi0_tile_n<WPW, SUB, CHUNK, DEPTH, NW, true>(nsub, lds, P, R, ld, delta, df, n_trans, t_lo,
+                                                  t_hi, omega, n_w, eta, paired, n_g, 0, tg.nm,
+                                                  col0, nullptr, tg);
+}
+
+// One tile per workgroup: the tail tiles first (logical tiles 0 .. n_tail - 1:
+// virtual-row group fastest, then column tile, then slice; they hold the
+// most column blocks), then the main tiles (frequency block fastest, then
+// (G block, G' block), then slice), so one launch fills the chip with both.
+// OCC = workgroups per CU: 2 for the
 // plain tile (one wave per SIMD without pipelining leaves LDS and dependency
 // latency exposed: about 60 % of the two-wave rate for 16 x 128 and 16 x 144
 // tiles), 1 for the pipelined tile, whose two operand register sets need the
@@ -618,18 +766,31 @@ template <int WPW, int SUB, int CHUNK, int OCC, bool PIPE, int DEPTH, int NW>
 __global__ void __launch_bounds__(64 * NW, OCC)
     k_chi0_bf16x3(const void *P, const void *R, int ld, const double *delta, const double *df,
                   long long n_trans, long long slice_len, const double *omega, int n_w,
-                  double eta, int paired, int n_g, int ncb, double2 *part) {
+                  double eta, int paired, int n_g, int lc, int nx, int ncb, int ny, int n_tail,
+                  int ntg, int nct, int nm, int tail, double2 *part, double2 *tpart) {
+  // main tiles: rows and columns [0, lc) (lc = ld, or nm when tail tiles
+  // cover the rest); grid: n_tail + nx ny slices workgroups
   typedef Cfg<WPW, SUB, CHUNK, NW> C;
   extern __shared__ unsigned int lds[];
-  const int nx = gridDim.x, ny = gridDim.y;
-  const int id = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
-  const int L = xcd_logical(id, nx * ny * gridDim.z);
-  const int bx = L % nx, by = (L / nx) % ny, bz = L / (nx * ny);
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  if (L < n_tail) {
+    const int a = L % ntg, c = (L / ntg) % nct, bz = L / (ntg * nct);
+    const long long t_lo = (long long)bz * slice_len;
+    const long long t_hi = std::min(n_trans, t_lo + slice_len);
+    const int col0 = c * C::kCols;
+    const TailGeom tg{nm, tail, a * 16 * WPW * NW, tpart + (size_t)bz * n_w * tail * 2 * ld};
+    run_tail_tile<WPW, SUB, CHUNK, PIPE, DEPTH, NW>(std::min(SUB, (ld - col0) / 16), lds, P, R,
+                                                    ld, delta, df, n_trans, t_lo, t_hi, omega,
+                                                    n_w, eta, paired, n_g, col0, tg);
+    return;
+  }
+  const int Lm = L - n_tail;
+  const int bx = Lm % nx, by = (Lm / nx) % ny, bz = Lm / (nx * ny);
   const int gb = by / ncb, gc = by % ncb;
   const long long t_lo = (long long)bz * slice_len;
   const long long t_hi = std::min(n_trans, t_lo + slice_len);
   const int col0 = gc * C::kCols;
-  run_tile<WPW, SUB, CHUNK, PIPE, DEPTH, NW>(std::min(SUB, (ld - col0) / 16), lds, P, R, ld, delta, df,
+  run_tile<WPW, SUB, CHUNK, PIPE, DEPTH, NW>(std::min(SUB, (lc - col0) / 16), lds, P, R, ld, delta, df,
                                   n_trans, t_lo, t_hi, omega, n_w, eta, paired, n_g, bx * C::kWBlock,
                                   gb * 16, col0, part + (size_t)bz * n_w * n_g * n_g);
 }
@@ -654,10 +815,21 @@ __global__ void __launch_bounds__(64 * NW, OCC)
     const long long t_lo = tl.slice * it.slice_len;
     const long long t_hi = std::min(it.n_trans, t_lo + it.slice_len);
     const int col0 = tl.gc * C::kCols;
-    run_tile<WPW, SUB, CHUNK, PIPE, DEPTH, NW>(std::min(SUB, (it.ld - col0) / 16), lds, it.P, it.R, it.ld,
-                                    it.delta, it.df, it.n_trans, t_lo, t_hi, it.omega, it.n_w,
-                                    it.eta, it.paired, it.n_g, tl.wblk * C::kWBlock, tl.gb * 16, col0,
-                                    it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
+    if (tl.gb < 0) {
+      // a tail tile: wblk counts groups of 16 WPW NW virtual rows
+      const TailGeom tg{it.nm, it.tail, tl.wblk * 16 * WPW * NW,
+                        it.tpart + (size_t)tl.slice * it.n_w * it.tail * 2 * it.ld};
+      run_tail_tile<WPW, SUB, CHUNK, PIPE, DEPTH, NW>(std::min(SUB, (it.ld - col0) / 16), lds, it.P,
+                                                      it.R, it.ld, it.delta, it.df, it.n_trans,
+                                                      t_lo, t_hi, it.omega, it.n_w, it.eta,
+                                                      it.paired, it.n_g, col0, tg);
+    } else {
+      run_tile<WPW, SUB, CHUNK, PIPE, DEPTH, NW>(std::min(SUB, (it.lc - col0) / 16), lds, it.P, it.R,
+                                                 it.ld, it.delta, it.df, it.n_trans, t_lo, t_hi,
+                                                 it.omega, it.n_w, it.eta, it.paired, it.n_g,
+                                                 tl.wblk * C::kWBlock, tl.gb * 16, col0,
+                                                 it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
+    }
     __syncthreads();  // the next tile's prologue rewrites the LDS buffers
   }
 }
@@ -672,6 +844,7 @@ constexpr size_t variant_lds() {
 
 struct Variant {
   int wpw, sub, chunk, occ, waves;
+  bool pipe;
   size_t lds;
   const void *grid_fn;
   const void *pers_fn;
@@ -679,7 +852,7 @@ struct Variant {
 
 #define TDX_V(W, S, K, O, PIPE, DEPTH, NW)                                               \
   Variant {                                                                              \
-    W, S, K, O, NW, variant_lds<W, S, K, PIPE, DEPTH, NW>(),                             \
+    W, S, K, O, NW, PIPE, variant_lds<W, S, K, PIPE, DEPTH, NW>(),                       \
         (const void *)k_chi0_bf16x3<W, S, K, O, PIPE, DEPTH, NW>,                        \
         (const void *)k_chi0_bf16x3_persistent<W, S, K, O, PIPE, DEPTH, NW>              \
   }
@@ -704,22 +877,40 @@ void bf16x3_variant_shape(int v, int *wblock, int *cols) {
 
 int bf16x3_variant_occupancy(int v) { return kVariants[v].occ; }
 
+TailSplit bf16x3_split(int v, int n_g) {
+  const int ld = (n_g + 15) / 16 * 16;
+  if (kVariants[v].pipe || n_g % 16 == 0) return TailSplit{ld, 0};
+  return TailSplit{n_g / 16 * 16, n_g % 16};
+}
+
+int bf16x3_tail_groups(int v, int n_w, int tail) {
+  const int rows = 16 * kVariants[v].wpw * kVariants[v].waves;
+  return tail > 0 ? (n_w * 2 * tail + rows - 1) / rows : 0;
+}
+
 int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double *delta,
                        const double *df,
                        long long n_trans, long long slice_len, int slices, const double *omega,
-                       int n_w, double eta, int paired, int n_g, double2 *part, hipStream_t s) {
+                       int n_w, double eta, int paired, int n_g, double2 *part, double2 *tpart,
+                       hipStream_t s) {
   const Variant &V = kVariants[v];
-  const int nblk = ld / 16;
-  int ncb = (ld + 16 * V.sub - 1) / (16 * V.sub);
+  const TailSplit sp = bf16x3_split(v, n_g);
+  int lc = sp.nm, nm = sp.nm, tail = sp.tail;
   const int wb = V.waves * V.wpw;
-  dim3 grid((n_w + wb - 1) / wb, nblk * ncb, (unsigned)slices);
+  int ncb = (lc + 16 * V.sub - 1) / (16 * V.sub);
+  int nx = (n_w + wb - 1) / wb, ny = (lc / 16) * ncb;
+  int ntg = bf16x3_tail_groups(v, n_w, tail), nct = (ld + 16 * V.sub - 1) / (16 * V.sub);
+  int n_tail = tail > 0 ? ntg * nct * slices : 0;
+  const long long total = (long long)n_tail + (long long)nx * ny * slices;
+  TDX_REQUIRE(total > 0 && total < (1LL << 31), TDX_ERR_SHAPE, "%lld tiles", total);
   TDX_HIP(hipFuncSetAttribute(V.grid_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)V.lds));
-  void *args[] = {(void *)&P,       (void *)&R,         (void *)&ld,
-                  (void *)&delta,   (void *)&df,
-                  (void *)&n_trans, (void *)&slice_len, (void *)&omega, (void *)&n_w,
-                  (void *)&eta,     (void *)&paired,    (void *)&n_g,   (void *)&ncb,
-                  (void *)&part};
-  TDX_HIP(hipLaunchKernel(V.grid_fn, grid, dim3(64 * V.waves), args, V.lds, s));
+  void *args[] = {(void *)&P,       (void *)&R,         (void *)&ld,    (void *)&delta,
+                  (void *)&df,      (void *)&n_trans,   (void *)&slice_len,
+                  (void *)&omega,   (void *)&n_w,       (void *)&eta,   (void *)&paired,
+                  (void *)&n_g,     (void *)&lc,        (void *)&nx,    (void *)&ncb,
+                  (void *)&ny,      (void *)&n_tail,    (void *)&ntg,   (void *)&nct,
+                  (void *)&nm,      (void *)&tail,      (void *)&part,  (void *)&tpart};
+  TDX_HIP(hipLaunchKernel(V.grid_fn, dim3((unsigned)total), dim3(64 * V.waves), args, V.lds, s));
   return TDX_OK;
 }
 

@@ -94,14 +94,21 @@ constexpr int kShortRow = 16;
 // start of k's own range of the list.  The order inside a group does not
 // change any result (every transition is one MFMA row of its own).
 __global__ void k_cols(const long long *koff, const int *tn, const int *tm, int nb_max,
-                       long long n_trans, const long long *rowbeg, const long long *rowend,
-                       long long *colbeg, long long *colend, long long *perm) {
+                       long long t_lo, long long t_hi, const long long *rowbeg,
+                       const long long *rowend, long long *colbeg, long long *colend,
+                       long long *perm) {
   extern __shared__ int cnt[];  // [nb_max] counts, then [nb_max] cursors
   int *cur = cnt + nb_max;
   const int k = blockIdx.x;
-  const long long t0 = koff[k], t1 = koff[k + 1] < n_trans ? koff[k + 1] : n_trans;
+  const long long t0 = koff[k] > t_lo ? koff[k] : t_lo;
+  const long long t1 = koff[k + 1] < t_hi ? koff[k + 1] : t_hi;
   for (int i = threadIdx.x; i < 2 * nb_max; i += blockDim.x) cnt[i] = 0;
   __syncthreads();
+  if (t1 <= t0) {  // no transition of k in the range: empty groups
+    for (int m = threadIdx.x; m < nb_max; m += blockDim.x)
+      colbeg[(size_t)k * nb_max + m] = colend[(size_t)k * nb_max + m] = 0;
+    return;
+  }
   auto is_short = [&](long long t) {
     const size_t r = (size_t)k * nb_max + tn[t];
     return rowend[r] - rowbeg[r] < kShortRow;
@@ -112,15 +119,15 @@ __global__ void k_cols(const long long *koff, const int *tn, const int *tm, int 
   if (threadIdx.x == 0) {
     int acc = 0;
     for (int m = 0; m < nb_max; ++m) {
-      colbeg[(size_t)k * nb_max + m] = t0 + acc;
-      colend[(size_t)k * nb_max + m] = t0 + acc + cnt[m];
+      colbeg[(size_t)k * nb_max + m] = t0 - t_lo + acc;
+      colend[(size_t)k * nb_max + m] = t0 - t_lo + acc + cnt[m];
       cur[m] = acc;
       acc += cnt[m];
     }
   }
   __syncthreads();
   for (long long t = t0 + threadIdx.x; t < t1; t += blockDim.x)
-    if (is_short(t)) perm[t0 + atomicAdd(&cur[tm[t]], 1)] = t;
+    if (is_short(t)) perm[t0 - t_lo + atomicAdd(&cur[tm[t]], 1)] = t;
 }
 
 // One wavefront per group of transitions that share one side: a row group
@@ -134,20 +141,24 @@ __global__ void k_cols(const long long *koff, const int *tn, const int *tm, int 
 // the group's 16 transitions, the B operand is gathered per lane through the
 // Miller-index lookup box of the fixed side, which sits in LDS next to that
 // side's coefficients (zero outside its basis).  The output element j of
-// lane l is transition row l/16 + 4 j, G column l%16.  W wavefronts share one
+// lane l is transition row l/16 + 4 j, G column l%16; transition t is
+// stored in row t - t_lo of P.  W wavefronts share one
 // group (and its LDS) and take its 16-transition tiles in turn: W = 1 where
 // the LDS of a group is small enough for several groups per CU, W = 8 (two
 // per SIMD) where it is not (about 6300 plane waves: 149 KB, one group per
-// CU).
-template <int FMT, bool COL, int W>
+// CU).  The Miller indices of the A side, which every K-step needs before its
+// lookups, are staged in LDS too (MS) when they fit, else loaded one K-step
+// ahead.
+template <int FMT, bool COL, int W, bool MS>
 __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2, 2)))
     k_pair_density(const double2 *coef, const int *miller, const int *npw, int nb_max,
                    int npw_max, const int *tn, const int *tm, const long long *gbeg,
                    const long long *gend, const long long *perm, const int *kpmap,
                    const int *gsmap, const int *gbasis, int n_g, int ld, const int *lut, long box,
-                   int M0, int M1, int M2, void *P, long long n_trans) {
+                   int M0, int M1, int M2, void *P, long long t_lo, long long n_rows) {
   extern __shared__ double2 cfix[];             // [npw_max] the fixed side
   int *lutf = (int *)(cfix + npw_max);          // [box] lookup of its k-point
+  unsigned *mia = (unsigned *)(lutf + box);     // [npw_max] A-side indices (MS)
   const int band = blockIdx.x, k = blockIdx.y;
   const size_t grp = (size_t)k * nb_max + band;
   const long long p0 = gbeg[grp], p1 = gend[grp];
@@ -165,9 +176,17 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2, 
     cfix[i] = COL ? c : make_double2(c.x, -c.y);
   }
   for (long i = threadIdx.x; i < box; i += 64 * W) lutf[i] = lut[(size_t)kf * box + i];
-  __syncthreads();
   const int W1 = 2 * M1 + 1, W2 = 2 * M2 + 1;
   const int *ma = miller + (size_t)ka * npw_max * 3;
+  // Miller triple of plane wave j of the A side, offset into the lookup box
+  // and packed as three 10-bit fields
+  auto packed_m = [&](int j) {
+    return (unsigned)(ma[3 * j] + M0) | ((unsigned)(ma[3 * j + 1] + M1) << 10) |
+           ((unsigned)(ma[3 * j + 2] + M2) << 20);
+  };
+  if constexpr (MS)
+    for (int i = threadIdx.x; i < npa; i += 64 * W) mia[i] = packed_m(i);
+  __syncthreads();
   const double2 *ca = coef + (size_t)ka * nb_max * npw_max;
   const int *ta = COL ? tn : tm;  // band of the A row of a transition
   const int r = lane & 15, kq = lane >> 4;
@@ -202,12 +221,20 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2, 
         return COL ? make_double2(c.x, -c.y) : c;
       };
       double2 a_next = load_a(0);
+      unsigned pm_next = MS ? 0u : packed_m(std::min((int)kq, npa - 1));
       for (int j0 = 0; j0 < npa; j0 += 4) {
         const int j = j0 + kq;
         const double2 a = a_next;
         a_next = load_a(j0 + 4);
         const int jc = std::min(j, npa - 1);
-        const int m0 = ma[3 * jc] + M0, m1 = ma[3 * jc + 1] + M1, m2 = ma[3 * jc + 2] + M2;
+        unsigned pm;
+        if constexpr (MS) {
+          pm = mia[jc];
+        } else {
+          pm = pm_next;
+          pm_next = packed_m(std::min(j + 4, npa - 1));
+        }
+        const int m0 = (int)(pm & 1023u), m1 = (int)((pm >> 10) & 1023u), m2 = (int)(pm >> 20);
         // B operands of every tile: all lookups first, then all values, with
         // no branches (out-of-range entries read slot 0 and are zeroed); the
         // lookup index is G2 - G - G_s (row group) or G1 + G + G_s (column)
@@ -253,7 +280,8 @@ __global__ void __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2, 
         for (int e = 0; e < 4; ++e) {
           const long long p = q0 + kq + 4 * e;
           if (p < p1)
-            store<FMT>(P, trans(p), (gt0 + q) * 16 + r, ld, n_trans, acr[q][e], aci[q][e]);
+            store<FMT>(P, trans(p) - t_lo, (gt0 + q) * 16 + r, ld, n_rows, acr[q][e],
+                       aci[q][e]);
         }
       }
     };
@@ -288,13 +316,53 @@ size_t tdx_pair_density_bytes(int64_t n_trans, int n_g, int prec) {
   return (size_t)n_trans * ld_of(n_g) * per;
 }
 
-int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const tdx_translist *tl,
-                     int64_t n_trans, const int *gbasis, int n_g, int prec, void *P,
-                     tdx_stream stream) {
-  clear_error();
-  TDX_REQUIRE(ctx && st && qj && tl && gbasis && P, TDX_ERR_INVALID_ARG, "null argument");
+}  // extern "C"
+
+namespace tdx {
+namespace {
+
+// Device tables of one call, carved from one workspace: the Miller lookup
+// boxes, the (k, n) row and (k, m) column ranges, the column permutation and
+// the k + q maps.
+struct PdWork {
+  int *lut;
+  long long *rb, *re, *cb, *ce, *perm;
+  int *kp, *gs;
+};
+
+size_t pd_work_layout(const tdx_states *st, long long n_rows, void *base, PdWork *w) {
+  const int nk = st->n_k, nb_max = st->nb_max;
+  const long box = (long)(2 * st->mmax[0] + 1) * (2 * st->mmax[1] + 1) * (2 * st->mmax[2] + 1);
+  auto r256 = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t lut = r256(sizeof(int) * (size_t)nk * box);
+  // row starts and ends back to back (one fill clears both), then the
+  // column-group starts and ends
+  const size_t tab = r256(sizeof(long long) * 2 * (size_t)nk * nb_max);
+  const size_t perm = r256(sizeof(long long) * (size_t)std::max<long long>(n_rows, 1));
+  const size_t maps = r256(sizeof(int) * 4 * (size_t)nk);
+  if (w) {
+    char *p = (char *)base;
+    w->lut = (int *)p;
+    p += lut;
+    w->rb = (long long *)p;
+    w->re = w->rb + (size_t)nk * nb_max;
+    w->cb = (long long *)(p + tab);
+    w->ce = w->cb + (size_t)nk * nb_max;
+    p += 2 * tab;
+    w->perm = (long long *)p;
+    p += perm;
+    w->kp = (int *)p;
+    w->gs = w->kp + nk;
+  }
+  return lut + 2 * tab + perm + maps;
+}
+
+int pd_check(const tdx_states *st, const int qj[3], const tdx_translist *tl, int64_t t_begin,
+             int64_t t_end, const int *gbasis, int n_g, int prec, const void *P) {
+  TDX_REQUIRE(st && qj && tl && gbasis && P, TDX_ERR_INVALID_ARG, "null argument");
   TDX_REQUIRE(prec >= TDX_PREC_FP64 && prec <= TDX_PREC_BF16X3, TDX_ERR_INVALID_ARG, "bad prec");
-  TDX_REQUIRE(n_g > 0 && n_trans >= 0 && n_trans <= tl->capacity, TDX_ERR_SHAPE, "bad sizes");
+  TDX_REQUIRE(n_g > 0 && t_begin >= 0 && t_begin <= t_end && t_end <= tl->capacity,
+              TDX_ERR_SHAPE, "bad sizes");
   for (int i = 0; i < 3; ++i)
     TDX_REQUIRE(st->mmax[i] < 200, TDX_ERR_SHAPE, "Miller range %d too large", st->mmax[i]);
   TDX_REQUIRE(st->npw_max * sizeof(double2) +
@@ -303,77 +371,128 @@ int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const 
                   150 * 1024,
               TDX_ERR_SHAPE, "plane-wave basis of %d and its lookup box exceed LDS",
               st->npw_max);
-  TDX_TRY(check_device(ctx));
+  return TDX_OK;
+}
+
+// Every launch of one pair-density call, with its tables in `work`: no host
+// copy, memset or synchronisation, so a caller may capture it in a graph.
+int pd_enqueue(const tdx_states *st, const int qj[3], const tdx_translist *tl, int64_t t_begin,
+               int64_t t_end, const int *gbasis, int n_g, int prec, void *P, void *work,
+               hipStream_t s) {
+  const long long n_trans = t_end - t_begin;
   if (n_trans == 0) return TDX_OK;
-  hipStream_t s = as_stream(stream);
   const int nk = st->n_k, nb_max = st->nb_max;
   const int M0 = st->mmax[0], M1 = st->mmax[1], M2 = st->mmax[2];
   const long box = (long)(2 * M0 + 1) * (2 * M1 + 1) * (2 * M2 + 1);
-  std::vector<int> kp, gs;
-  kq_map(st->kgrid, qj, &kp, &gs);
-  void *w1, *w2;
-  const size_t lut_bytes = (sizeof(int) * (size_t)nk * box + 255) / 256 * 256;
-  const size_t row_bytes = sizeof(long long) * 2 * (size_t)nk * nb_max;
-  TDX_TRY(ws_get(ctx, WS_DENS,
-                 lut_bytes + 2 * row_bytes + sizeof(long long) * (size_t)n_trans, &w1));
-  TDX_TRY(ws_get(ctx, WS_MISC, sizeof(int) * 4 * (size_t)nk, &w2));
-  int *d_lut = (int *)w1;
-  long long *d_rb = (long long *)((char *)w1 + lut_bytes);
-  long long *d_re = d_rb + (size_t)nk * nb_max;
-  long long *d_cb = d_re + (size_t)nk * nb_max, *d_ce = d_cb + (size_t)nk * nb_max;
-  long long *d_perm = d_ce + (size_t)nk * nb_max;
-  int *d_kp = (int *)w2, *d_gs = d_kp + nk;
-  TDX_HIP(hipMemcpyAsync(d_kp, kp.data(), sizeof(int) * nk, hipMemcpyHostToDevice, s));
-  TDX_HIP(hipMemcpyAsync(d_gs, gs.data(), sizeof(int) * 3 * nk, hipMemcpyHostToDevice, s));
-  TDX_HIP(hipMemsetAsync(d_lut, 0xff, lut_bytes, s));
-  TDX_HIP(hipMemsetAsync(d_rb, 0, row_bytes, s));
+  PdWork w;
+  pd_work_layout(st, n_trans, work, &w);
+  hipLaunchKernelGGL(k_kq_map, dim3((nk + 255) / 256), dim3(256), 0, s, st->kgrid[0],
+                     st->kgrid[1], st->kgrid[2], qj[0], qj[1], qj[2], w.kp, w.gs);
+  TDX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_fill<int>, dim3(1024), dim3(256), 0, s, w.lut, (long long)nk * box, -1);
+  TDX_HIP(hipGetLastError());
+  // every row start and end (re follows rb directly); k_cols writes every
+  // column-group entry itself
+  hipLaunchKernelGGL(k_fill<long long>, dim3(1024), dim3(256), 0, s, w.rb,
+                     2LL * nk * nb_max, 0LL);
+  TDX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_lut, dim3((st->npw_max + 255) / 256, nk), dim3(256), 0, s, st->miller,
-                     st->npw, st->npw_max, nk, M0, M1, M2, d_lut, box);
+                     st->npw, st->npw_max, nk, M0, M1, M2, w.lut, box);
   TDX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_rows, dim3(nk), dim3(256), 0, s, (const long long *)tl->k_offsets, tl->n,
-                     nb_max, (long long)n_trans, d_rb, d_re);
+                     nb_max, (long long)t_begin, (long long)t_end, w.rb, w.re);
   TDX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_cols, dim3(nk), dim3(256), sizeof(int) * 2 * nb_max, s,
-                     (const long long *)tl->k_offsets, tl->n, tl->m, nb_max, (long long)n_trans,
-                     d_rb, d_re, d_cb, d_ce, d_perm);
+                     (const long long *)tl->k_offsets, tl->n, tl->m, nb_max, (long long)t_begin,
+                     (long long)t_end, w.rb, w.re, w.cb, w.ce, w.perm);
   TDX_HIP(hipGetLastError());
   const int ld = ld_of(n_g);
-  const size_t lds = sizeof(double2) * st->npw_max + sizeof(int) * (size_t)box;
+  const size_t lds0 = sizeof(double2) * st->npw_max + sizeof(int) * (size_t)box;
   dim3 grid(nb_max, nk);
   // eight wavefronts per group when fewer than four groups fit in a CU's LDS
-  const bool wide = lds > 40 * 1024;
+  const bool wide = lds0 > 40 * 1024;
+  // the A side's Miller indices in LDS as well when they fit
+  const bool ms = lds0 + sizeof(unsigned) * st->npw_max <= 150 * 1024;
+  const size_t lds = ms ? lds0 + sizeof(unsigned) * st->npw_max : lds0;
   // long rows, then the column groups of the short ones (disjoint outputs)
-#define TDX_PD2(F, COL, W, B, E)                                                               \
-  TDX_HIP(hipFuncSetAttribute((const void *)k_pair_density<F, COL, W>,                         \
+#define TDX_PD3(F, COL, W, MS, B, E)                                                           \
+  TDX_HIP(hipFuncSetAttribute((const void *)k_pair_density<F, COL, W, MS>,                     \
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));          \
-  hipLaunchKernelGGL((k_pair_density<F, COL, W>), grid, dim3(64 * W), lds, s,                  \
+  hipLaunchKernelGGL((k_pair_density<F, COL, W, MS>), grid, dim3(64 * W), lds, s,              \
                      (const double2 *)st->coef, st->miller, st->npw, nb_max, st->npw_max,      \
-                     tl->n, tl->m, B, E, d_perm, d_kp, d_gs, gbasis, n_g, ld, d_lut, box, M0,  \
-                     M1, M2, P, (long long)n_trans);                                           \
+                     tl->n, tl->m, B, E, w.perm, w.kp, w.gs, gbasis, n_g, ld, w.lut, box, M0,  \
+                     M1, M2, P, (long long)t_begin, n_trans);                                  \
   TDX_HIP(hipGetLastError())
+#define TDX_PD2(F, COL, W, B, E)       \
+  if (ms) {                            \
+    TDX_PD3(F, COL, W, true, B, E);    \
+  } else {                             \
+    TDX_PD3(F, COL, W, false, B, E);   \
+  }
 #define TDX_PD1(F, COL, B, E)       \
   if (wide) {                       \
-    TDX_PD2(F, COL, 8, B, E);       \
+    TDX_PD2(F, COL, 8, B, E)        \
   } else {                          \
-    TDX_PD2(F, COL, 1, B, E);       \
+    TDX_PD2(F, COL, 1, B, E)        \
   }
-#define TDX_PD(F)                     \
-  TDX_PD1(F, false, d_rb, d_re)       \
-  TDX_PD1(F, true, d_cb, d_ce)
+#define TDX_PD(F)                   \
+  TDX_PD1(F, false, w.rb, w.re)     \
+  TDX_PD1(F, true, w.cb, w.ce)
   if (prec == TDX_PREC_FP64) {
     TDX_PD(TDX_PREC_FP64);
   } else if (prec == TDX_PREC_FP32) {
     TDX_PD(TDX_PREC_FP32);
   } else {
-    hipLaunchKernelGGL(k_zero_pad, dim3(64), dim3(256), 0, s, (unsigned int *)P,
-                       (long long)n_trans, ld);
+    hipLaunchKernelGGL(k_zero_pad, dim3(64), dim3(256), 0, s, (unsigned int *)P, n_trans, ld);
     TDX_HIP(hipGetLastError());
     TDX_PD(TDX_PREC_BF16X3);
   }
 #undef TDX_PD
 #undef TDX_PD1
 #undef TDX_PD2
+#undef TDX_PD3
   return TDX_OK;
+}
+
+}  // namespace
+}  // namespace tdx
+
+extern "C" {
+
+size_t tdx_pair_density_work_bytes(const tdx_states *st, int64_t n_trans) {
+  if (!st || n_trans < 0) return 0;
+  return pd_work_layout(st, n_trans, nullptr, nullptr);
+}
+
+int tdx_pair_density_async(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
+                           const tdx_translist *tl, int64_t t_begin, int64_t t_end,
+                           const int *gbasis, int n_g, int prec, void *P, void *work,
+                           size_t work_bytes, tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && work, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_TRY(pd_check(st, qj, tl, t_begin, t_end, gbasis, n_g, prec, P));
+  TDX_REQUIRE(work_bytes >= pd_work_layout(st, t_end - t_begin, nullptr, nullptr), TDX_ERR_SHAPE,
+              "work buffer of %zu bytes below tdx_pair_density_work_bytes", work_bytes);
+  return pd_enqueue(st, qj, tl, t_begin, t_end, gbasis, n_g, prec, P, work, as_stream(stream));
+}
+
+int tdx_pair_density_range(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
+                           const tdx_translist *tl, int64_t t_begin, int64_t t_end,
+                           const int *gbasis, int n_g, int prec, void *P, tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_TRY(pd_check(st, qj, tl, t_begin, t_end, gbasis, n_g, prec, P));
+  TDX_TRY(check_device(ctx));
+  if (t_end == t_begin) return TDX_OK;
+  void *w;
+  TDX_TRY(ws_get(ctx, WS_DENS, pd_work_layout(st, t_end - t_begin, nullptr, nullptr), &w));
+  return pd_enqueue(st, qj, tl, t_begin, t_end, gbasis, n_g, prec, P, w, as_stream(stream));
+}
+
+int tdx_pair_density(tdx_ctx *ctx, const tdx_states *st, const int qj[3], const tdx_translist *tl,
+                     int64_t n_trans, const int *gbasis, int n_g, int prec, void *P,
+                     tdx_stream stream) {
+  return tdx_pair_density_range(ctx, st, qj, tl, 0, n_trans, gbasis, n_g, prec, P, stream);
 }
 
 }  // extern "C"

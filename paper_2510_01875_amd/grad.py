@@ -8,7 +8,12 @@ forward kernels and, in ``backward``, its reverse-mode entry points:
                     -> Dyson, for every q of a workload (one state build);
                     backward: dyson_vjp -> chi0_vjp -> weights_vjp ->
                     occupations_vjp, pair_density_vjp -> potential_vjp.
-                    Pair densities are recomputed in backward, not stored.
+                    The transition lists are time-reversal paired (half
+                    the transitions) unless paired=False.  Pair densities
+                    are not stored for backward: it recomputes them block
+                    by block of the transition list (block_bytes of pair
+                    densities and their cotangents at a time), so the
+                    reverse sweep holds one block, never a whole list.
   DSF(chi00, beta)  S by the fluctuation-dissipation theorem (Eq. 8).
   ITCF(S, beta, tau) F by the two-sided Laplace transform (Eq. 1).
 
@@ -25,8 +30,9 @@ import numpy as np
 import torch
 
 from . import (Context, build_states, chi0, chi0_vjp, dsf, dsf_vjp, dyson, dyson_vjp, itcf,
-               itcf_vjp, kernel_matrix, occupations_vjp, pair_density,
-               pair_density_vjp, potential_vjp, response_basis, transitions, weights_vjp)
+               itcf_vjp, kernel_matrix, occupations, occupations_vjp, pair_density,
+               pair_density_range, pair_density_vjp, potential_vjp, response_basis, transitions,
+               weights_vjp)
 
 
 def _with_shell_values(w, v):
@@ -36,27 +42,51 @@ def _with_shell_values(w, v):
 
 
 class ChainRunner:
-    """Forward and reverse sweeps of chi_00 for every q of a workload."""
+    """Forward and reverse sweeps of chi_00 for every q of a workload.
 
-    def __init__(self, ctx: Context, w):
+    The model is non-self-consistent, so the orbitals depend on the shell
+    values v only: a runner called again with the same v keeps its states
+    and recomputes the occupations for the new temperature."""
+
+    def __init__(self, ctx: Context, w, paired: bool = True, block_bytes: int = 8 << 30):
         if w.xc != "rpa":
             raise ValueError("gradients are implemented for the RPA kernel")
         self.ctx = ctx
         self.w = w
+        self.paired = paired
+        self.block_bytes = int(block_bytes)
         self.saved = None
+        self._st, self._st_v = None, None
+
+    def _states(self, w, T, v):
+        key = None if v is None else tuple(float(x) for x in v)
+        if self._st is not None and self._st_v == key:
+            occupations(self.ctx, self._st, T, w.n_electrons, w.f_trunc)
+        else:
+            self._st = None
+            self._st = build_states(self.ctx, w, T)
+            self._st_v = key
+        return self._st
+
+    def blocks(self, n_trans: int, n_g: int):
+        """Transition ranges of the reverse sweep: each holds at most
+        block_bytes of FP64 pair densities plus their cotangents."""
+        ld = (n_g + 15) // 16 * 16
+        size = max(64, self.block_bytes // (2 * 16 * ld))
+        return [(b, min(n_trans, b + size)) for b in range(0, n_trans, size)]
 
     def forward(self, T: float, eta: float, v: Optional[np.ndarray]) -> torch.Tensor:
         w = self.w if v is None else _with_shell_values(self.w, v)
         w = w.with_(temperatures=tuple(T for _ in w.qs), eta=eta)
         ctx = self.ctx
-        st = build_states(ctx, w, T)
+        st = self._states(w, T, v)
         dev = st.eps.device
         pref = st.chi0_pref
         out, per_q = [], []
         for iq, qj in enumerate(w.qs):
             basis, g0 = response_basis(w.cell, w.kgrid, qj, w.ecut_chi[iq])
             gb = torch.from_numpy(basis).to(dev)
-            tr = transitions(ctx, st, qj, w.f_trans_thr)
+            tr = transitions(ctx, st, qj, w.f_trans_thr, paired=self.paired)
             P = pair_density(ctx, st, qj, tr, gb, "fp64")
             om = torch.as_tensor(w.omega_grid(iq), device=dev)
             c0 = chi0(ctx, tr, P, len(basis), "fp64", om, eta, pref)
@@ -80,16 +110,20 @@ class ChainRunner:
             tr, gb = q["tr"], q["gb"]
             n_g = gb.shape[0]
             u, v = dyson_vjp(ctx, q["chi0"], q["K"], q["g0"], chi00_bar[iq].contiguous())
-            P = pair_density(ctx, st, q["qj"], tr, gb, "fp64")
-            w_bar, rho_bar = chi0_vjp(ctx, tr, P, n_g, q["omega"], sv["eta"], sv["pref"], u, v,
-                                      want_rho=need_v)
-            del P
+            w_bar = torch.empty((max(len(tr), 1), 3), dtype=torch.float64, device=dev)
+            for b0, b1 in self.blocks(len(tr), n_g):
+                P = pair_density_range(ctx, st, q["qj"], tr, gb, b0, b1, "fp64")
+                _, rho_bar = chi0_vjp(ctx, tr, P, n_g, q["omega"], sv["eta"], sv["pref"], u, v,
+                                      want_rho=need_v, t_begin=b0, t_end=b1,
+                                      w_out=w_bar[b0:b1])
+                del P
+                if need_v:
+                    pair_density_vjp(ctx, st, q["qj"], tr, gb, rho_bar, coef_bar,
+                                     t_begin=b0, t_end=b1)
+                del rho_bar
             occ_bar = torch.zeros(occ_shape, dtype=torch.float64, device=dev)
             weights_vjp(ctx, st, q["qj"], tr, w_bar, occ_bar, eps_bar, eta_bar)
             T_bar += float(occupations_vjp(ctx, st, occ_bar, eps_bar)[0])
-            if need_v:
-                pair_density_vjp(ctx, st, q["qj"], tr, gb, rho_bar, coef_bar)
-                del rho_bar
         v_bar = potential_vjp(ctx, w, st, eps_bar, coef_bar) if need_v else None
         return T_bar, float(eta_bar[0]), v_bar
 
@@ -153,10 +187,12 @@ def tau_fractions(w, iq: int) -> np.ndarray:
 
 
 def itcf_differentiable(ctx: Context, w, T: torch.Tensor, eta: torch.Tensor,
-                        v: Optional[torch.Tensor] = None) -> torch.Tensor:
+                        v: Optional[torch.Tensor] = None,
+                        runner: Optional[ChainRunner] = None) -> torch.Tensor:
     """F(q, tau = x beta) [n_q, n_tau] for every q of w, differentiable in
-    T, eta and (if given) the shell values v.  T, eta, v: CPU float64."""
-    runner = ChainRunner(ctx, w)
+    T, eta and (if given) the shell values v.  T, eta, v: CPU float64.  A
+    runner (ChainRunner of w) may be passed to reuse its states and settings."""
+    runner = ChainRunner(ctx, w) if runner is None else runner
     chi00 = Chi00.apply(T, eta, v, runner)
     st = runner.saved["st"]
     dens = st.density

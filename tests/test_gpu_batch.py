@@ -81,8 +81,9 @@ def test_batched_persistent_matches_single_and_oracle(tdx, ctx, paired):
 
 
 def test_plan_replays_in_a_hip_graph(tdx, ctx):
-    """chi0 plan + Dyson + S + F for every q captured once and replayed;
-    each replay, with eager work between replays, equals the eager result."""
+    """Pair densities + chi0 plan + Dyson + S + F for every q captured once
+    and replayed; each replay, with eager work between replays and the pair
+    densities and chi0 cleared before it, equals the eager result."""
     import torch
     _say("graph")
     w = workloads.fcc_c4_small()
@@ -95,9 +96,14 @@ def test_plan_replays_in_a_hip_graph(tdx, ctx):
         p["info"] = torch.empty(n_w, dtype=torch.int32, device="cuda")
         p["chi00"] = torch.empty(n_w, dtype=torch.complex128, device="cuda")
         p["tau"] = torch.as_tensor(w.tau_grid(p["iq"]), device="cuda")
+        p["pdw"] = torch.empty(tdx.pair_density_work_bytes(st, len(p["tr"])), dtype=torch.uint8,
+                               device="cuda")
     dens = st.density
 
     def body():
+        for p in prep:
+            tdx.pair_density_async(ctx, st, w.qs[p["iq"]], p["tr"], p["gb"], p["P"], p["pdw"],
+                                   "bf16x3")
         plan.launch()
         outs = []
         for p in prep:
@@ -122,6 +128,7 @@ def test_plan_replays_in_a_hip_graph(tdx, ctx):
         for p in prep:
             p["item"].out.zero_()
             p["chi00"].zero_()
+            p["P"].zero_()
         g.replay()
         torch.cuda.synchronize()
         for (S, F), (Se, Fe) in zip(captured, eager):

@@ -114,18 +114,20 @@ def test_dyson_vjp_matches_autograd(tdx, ctx):
     assert err < 1e-12
 
 
-def test_chi0_vjp_matches_autograd(tdx, ctx):
+@pytest.mark.parametrize("paired", [False, True])
+def test_chi0_vjp_matches_autograd(tdx, ctx, paired):
     """Transitions and FP64 pair densities of the hydrogen box; a ragged
     count (not a multiple of the 64-transition tile) and a frequency count
-    that is not a multiple of the 64-frequency block."""
+    that is not a multiple of the 64-frequency block.  The paired list's
+    weight is df [1/(w - delta + i eta) - 1/(w + delta + i eta)]."""
     import torch
-    _say("chi0 vjp")
+    _say("chi0 vjp", "paired" if paired else "full")
     w = _w()
     st = tdx.build_states(ctx, w)
     basis, g0 = tdx.response_basis(w.cell, w.kgrid, w.qs[0], w.ecut_chi[0])
     n_g = len(basis)
     gb = torch.from_numpy(basis).cuda()
-    tr_full = tdx.transitions(ctx, st, w.qs[0], w.f_trans_thr)
+    tr_full = tdx.transitions(ctx, st, w.qs[0], w.f_trans_thr, paired=paired)
     P_full = tdx.pair_density(ctx, st, w.qs[0], tr_full, gb, "fp64")
     T_all = len(tr_full) - 37          # ragged tail of the last tile
     n_w = 70
@@ -137,7 +139,7 @@ def test_chi0_vjp_matches_autograd(tdx, ctx):
     v = (torch.randn(n_w, n_g, generator=g, dtype=torch.float64) +
          1j * torch.randn(n_w, n_g, generator=g, dtype=torch.float64))
     w_bar, rho_bar = tdx.chi0_vjp(ctx, tr_full, P_full, n_g, om, eta, pref, u.cuda(), v.cuda(),
-                                  want_rho=True, n_trans=T_all)
+                                  want_rho=True, t_end=T_all)
     torch.cuda.synchronize()
     _say(f"  T = {T_all} (T mod 64 = {T_all % 64}), n_g = {n_g}")
     # reference on a subset of transitions (the kernel result is per transition)
@@ -151,6 +153,8 @@ def test_chi0_vjp_matches_autograd(tdx, ctx):
     Pr = P.clone().requires_grad_()
     omc = om.cpu()
     W = dfr[None, :] / (omc[:, None] - dlr[None, :] + 1j * er)            # [w, t]
+    if paired:
+        W = W - dfr[None, :] / (omc[:, None] + dlr[None, :] + 1j * er)
     # L = Re sum_w sum_GG' conj(u_G conj(v_G')) chi0_GG'
     #   = Re sum_w sum_t pref W (u^H rho_t) conj(v^H rho_t)
     a = u.conj() @ Pr.T                                                     # [w, t]
@@ -158,44 +162,78 @@ def test_chi0_vjp_matches_autograd(tdx, ctx):
     L = (pref * W * a * b.conj()).real.sum()
     g_df, g_dl, g_eta, g_P = torch.autograd.grad(L, (dfr, dlr, er, Pr))
     wb = w_bar[:T_all][sel.cuda()].cpu()
-    np.testing.assert_allclose(wb[:, 0].real.numpy(), g_df.numpy(), rtol=1e-10,
+    np.testing.assert_allclose(wb[:, 0].numpy(), g_df.numpy(), rtol=1e-10,
                                atol=1e-10 * float(g_df.abs().max()))
-    np.testing.assert_allclose((df * wb[:, 1].real).numpy(), g_dl.numpy(), rtol=1e-10,
+    np.testing.assert_allclose(wb[:, 1].numpy(), g_dl.numpy(), rtol=1e-10,
                                atol=1e-10 * float(g_dl.abs().max()))
     rb = rho_bar[:T_all][sel.cuda()][:, :n_g].cpu()
     err = float((rb - g_P).abs().max() / g_P.abs().max())
     _say(f"  rho_bar err {err:.2e}")
     assert err < 1e-11
-    # eta: the kernel's per-transition sums over the subset
-    eta_sub = float((df * wb[:, 1].imag).sum())
-    np.testing.assert_allclose(eta_sub, float(g_eta), rtol=1e-9)
+    # eta: the kernel's per-transition terms summed over the subset
+    np.testing.assert_allclose(float(wb[:, 2].sum()), float(g_eta), rtol=1e-9)
     assert float(rho_bar[:T_all, n_g:].abs().max() if rho_bar.shape[1] > n_g else 0.0) == 0.0
+    # the same rows from blocks of the list: pair densities and cotangents
+    # recomputed per block agree with the whole-list call, and the orbital
+    # cotangents accumulated block by block with the whole-list ones
+    n = len(tr_full)
+    cb_whole = torch.zeros_like(st.coef)
+    wb_all, rb_all = tdx.chi0_vjp(ctx, tr_full, P_full, n_g, om, eta, pref, u.cuda(), v.cuda(),
+                                  want_rho=True)
+    tdx.pair_density_vjp(ctx, st, w.qs[0], tr_full, gb, rb_all, cb_whole)
+    cb_blocks = torch.zeros_like(st.coef)
+    cuts = [0, n // 5, n // 5 + 1, n // 2, n]
+    for b0, b1 in zip(cuts[:-1], cuts[1:]):
+        Pb = tdx.pair_density_range(ctx, st, w.qs[0], tr_full, gb, b0, b1, "fp64")
+        assert float((tdx.pair_density_view(Pb, b1 - b0, n_g, "fp64") -
+                      tdx.pair_density_view(P_full, n, n_g, "fp64")[b0:b1]).abs().max()) <= \
+            1e-13 * float(P_full.view(torch.complex128).abs().max())
+        wbb, rbb = tdx.chi0_vjp(ctx, tr_full, Pb, n_g, om, eta, pref, u.cuda(), v.cuda(),
+                                want_rho=True, t_begin=b0, t_end=b1)
+        assert torch.allclose(wbb, wb_all[b0:b1], rtol=1e-12, atol=1e-12 * float(wb_all.abs().max()))
+        tdx.pair_density_vjp(ctx, st, w.qs[0], tr_full, gb, rbb, cb_blocks, t_begin=b0, t_end=b1)
+    err = float((cb_blocks - cb_whole).abs().max() / cb_whole.abs().max())
+    _say(f"  coef_bar blocks vs whole {err:.2e}")
+    assert err < 1e-12
 
 
 def _loss_weights(n):
     return np.random.default_rng(7).standard_normal(n)
 
 
-def _gpu_loss(tdx, ctx, w, T, eta, v, c):
+def _gpu_loss(tdx, ctx, w, T, eta, v, c, runner=None):
     import torch
     from paper_2510_01875_amd.grad import itcf_differentiable
     Tt = torch.tensor(T, dtype=torch.float64, requires_grad=True)
     et = torch.tensor(eta, dtype=torch.float64, requires_grad=True)
     vt = torch.tensor(v, dtype=torch.float64, requires_grad=True)
-    F = itcf_differentiable(ctx, w, Tt, et, vt)
+    F = itcf_differentiable(ctx, w, Tt, et, vt, runner=runner)
     L = (F.cpu() * torch.as_tensor(c).reshape(F.shape)).sum()
     return L, (Tt, et, vt)
 
 
-def test_gradient_matches_oracle_tangent_and_finite_differences(tdx, ctx):
+@pytest.mark.parametrize("form", ["paired", "full", "paired-blocks"])
+def test_gradient_matches_oracle_tangent_and_finite_differences(tdx, ctx, form):
+    """The reverse sweep over the time-reversal paired list, over the full
+    list, and over the paired list in blocks of about 40 transitions (pair
+    densities and cotangents recomputed per block)."""
     import torch
     from oracle import tangent
-    _say("gradient")
+    from paper_2510_01875_amd.grad import ChainRunner
+    _say("gradient", form)
     w = _w()
     T, eta = w.temperatures[0], w.eta
     v = np.asarray(w.potential.shell_v, dtype=np.float64)
     c = _loss_weights(w.n_tau)
-    L, (Tt, et, vt) = _gpu_loss(tdx, ctx, w, T, eta, v, c)
+    runner = ChainRunner(ctx, w, paired=form != "full",
+                         block_bytes=(40 * 2 * 16 * 64 if form == "paired-blocks" else 8 << 30))
+    L, (Tt, et, vt) = _gpu_loss(tdx, ctx, w, T, eta, v, c, runner=runner)
+    if form == "paired-blocks":
+        q0 = runner.saved["per_q"][0]
+        n_t = len(q0["tr"])
+        nb = len(runner.blocks(n_t, q0["gb"].shape[0]))
+        _say(f"  {nb} blocks of {n_t} paired transitions")
+        assert nb >= 3
     gT, ge, gv = torch.autograd.grad(L, (Tt, et, vt))
     grad = np.concatenate([[float(gT), float(ge)], gv.numpy()])
     _say(f"  grad {grad}")
@@ -218,8 +256,8 @@ def test_gradient_matches_oracle_tangent_and_finite_differences(tdx, ctx):
         p[i] += h
         m[i] -= h
         with torch.no_grad():
-            Lp, _ = _gpu_loss(tdx, ctx, w, p[0], p[1], p[2:], c)
-            Lm, _ = _gpu_loss(tdx, ctx, w, m[0], m[1], m[2:], c)
+            Lp, _ = _gpu_loss(tdx, ctx, w, p[0], p[1], p[2:], c, runner=runner)
+            Lm, _ = _gpu_loss(tdx, ctx, w, m[0], m[1], m[2:], c, runner=runner)
         fd = (float(Lp) - float(Lm)) / (2 * h)
         _say(f"  param {i}: adjoint {grad[i]:.10e} central difference {fd:.10e}")
         assert abs(grad[i] - fd) <= 1e-6 * max(abs(fd), 1e-3 * np.max(np.abs(grad)))
