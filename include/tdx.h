@@ -400,6 +400,22 @@ int tdx_kernel_matrix_from_grid(tdx_ctx *ctx, const tdx_states *st, const int qj
 int tdx_dyson(tdx_ctx *ctx, const double *chi0, const double *K, int n_g,
               int n_w, int i_g0, double *chi00, tdx_stream stream);
 
+/* tdx_dyson for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same per-frequency LU solves and results as tdx_dyson (bitwise), with the
+ * matrices 1 - chi0 K and the pivot status in a fixed library-owned device
+ * array of tdx_dyson_noalloc_max_bytes() bytes (64 MiB; each GPU holds its
+ * own copy until the process ends) instead of the context workspace.  The
+ * frequencies run in passes of as many as the array holds.  Calls no
+ * allocator; the caller passes chi0, K and chi00 as for tdx_dyson.
+ * Synchronises the stream to read the pivot status: NUMERIC if a pivot is
+ * zero or not finite (chi00 NaN for that frequency).  SHAPE if one matrix
+ * (16 n_g^2 bytes) does not fit the array.  Every call on a GPU shares its
+ * array: calls that overlap on one GPU (several streams or threads) race. */
+size_t tdx_dyson_noalloc_max_bytes(void);
+int tdx_dyson_noalloc(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w,
+                      int i_g0, double *chi00, tdx_stream stream);
+
 /* tdx_dyson without allocation or synchronisation (graph-capturable):
  * work is a caller-owned device buffer of tdx_dyson_work_bytes(n_g, n_w)
  * bytes, info a device int [n_w] that receives 0 or the failing column + 1

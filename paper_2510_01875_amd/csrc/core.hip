@@ -153,6 +153,7 @@ int tdx_create(int device, tdx_ctx **out) {
   TDX_REQUIRE(std::strncmp(prop.gcnArchName, "gfx950", 6) == 0, TDX_ERR_UNSUPPORTED,
               "device %d is %s, this library is built for gfx950", device, prop.gcnArchName);
   TDX_HIP(hipSetDevice(device));
+  TDX_TRY(dyson_scratch_init(device));
   tdx_ctx *ctx = new tdx_ctx();
   ctx->device = device;
   ctx->n_cu = prop.multiProcessorCount;

@@ -116,4 +116,8 @@ void gsphere(const Lattice &L, const double kred[3], double ecut, std::vector<in
 
 int check_device(tdx_ctx *ctx);
 
+// Resolves the device address of the no-allocation Dyson scratch for
+// `device` (which must be current); called by tdx_create.
+int dyson_scratch_init(int device);
+
 }  // namespace tdx

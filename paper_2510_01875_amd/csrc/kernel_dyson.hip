@@ -12,7 +12,9 @@
 // Dyson: chi = chi0 + chi0 K chi, column G0 by LU with partial pivoting of
 // (1 - chi0 K), one workgroup per frequency.
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -511,12 +513,118 @@ __global__ void __launch_bounds__(kLuThreads)
   }
 }
 
+// First failing frequency of a chunk of LU solves folded into the running
+// status {frequency, column + 1} (one block; status[0] = INT_MAX: none yet).
+__global__ void k_fold_status(const int *info, int n, int w0, int *status) {
+  __shared__ int best[256];
+  int b = INT_MAX;
+  for (int i = threadIdx.x; i < n; i += 256)
+    if (info[i] != 0) b = min(b, i);
+  best[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) best[threadIdx.x] = min(best[threadIdx.x], best[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && best[0] != INT_MAX && w0 + best[0] < status[0]) {
+    status[0] = w0 + best[0];
+    status[1] = info[best[0]];
+  }
+}
+
+__global__ void k_clear_status(int *status) {
+  if (threadIdx.x == 0) {
+    status[0] = INT_MAX;
+    status[1] = 0;
+  }
+}
+
+// Scratch of the no-allocation Dyson entry point: a file-scope device array
+// of fixed size (every GPU the library runs on holds its own copy until the
+// process ends), laid out as the status words (256 bytes), the per-frequency
+// pivot status of one chunk (rounded to 256 bytes), then the chunk's
+// matrices 1 - chi0 K.  Host code reaches it only through the per-device
+// address resolved below.
+constexpr size_t kDysonScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kDysonScratchBytes];
+void *g_scratch_ptr[kMaxDevices];
+std::mutex g_scratch_mu;
+
+size_t round256(size_t x) { return (x + 255) / 256 * 256; }
+
 }  // namespace
+
+// With `device` current: resolve that device's address of the scratch array
+// (once per device; later calls return at once).
+int dyson_scratch_init(int device) {
+  TDX_REQUIRE(device >= 0 && device < kMaxDevices, TDX_ERR_UNSUPPORTED,
+              "device %d beyond the %d the scratch table holds", device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return TDX_OK;
+  void *p = nullptr;
+  TDX_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  TDX_REQUIRE(p != nullptr, TDX_ERR_HIP, "no device address for the Dyson scratch");
+  g_scratch_ptr[device] = p;
+  return TDX_OK;
+}
+
 }  // namespace tdx
 
 using namespace tdx;
 
 extern "C" {
+
+size_t tdx_dyson_noalloc_max_bytes(void) { return kDysonScratchBytes; }
+
+int tdx_dyson_noalloc(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w,
+                      int i_g0, double *chi00, tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && chi0 && K && chi00, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(n_g > 0 && n_w > 0 && i_g0 >= 0 && i_g0 < n_g, TDX_ERR_SHAPE, "bad sizes");
+  TDX_REQUIRE((size_t)n_g * 2 * sizeof(double2) <= 64 * 1024, TDX_ERR_SHAPE,
+              "n_g %d too large for the LU kernel", n_g);
+  const size_t mat = sizeof(double2) * (size_t)n_g * n_g;
+  // frequencies per pass: the status words, their pivot status and their
+  // matrices must fit in the scratch
+  long long cw = (long long)((kDysonScratchBytes - 512) / (mat + sizeof(int)));
+  cw = std::min<long long>(std::min<long long>(cw, n_w), 65535);
+  while (cw > 0 && 256 + round256(sizeof(int) * (size_t)cw) + mat * (size_t)cw > kDysonScratchBytes)
+    --cw;
+  TDX_REQUIRE(cw >= 1, TDX_ERR_SHAPE,
+              "n_g %d: one %zu-byte matrix exceeds the %zu-byte scratch of this entry point", n_g,
+              mat, kDysonScratchBytes);
+  TDX_TRY(check_device(ctx));
+  TDX_REQUIRE(ctx->device >= 0 && ctx->device < kMaxDevices && g_scratch_ptr[ctx->device],
+              TDX_ERR_HIP, "scratch of device %d not set up", ctx->device);
+  hipStream_t s = as_stream(stream);
+  unsigned char *base = (unsigned char *)g_scratch_ptr[ctx->device];
+  int *status = (int *)base;
+  int *info = (int *)(base + 256);
+  double2 *A = (double2 *)(base + 256 + round256(sizeof(int) * (size_t)cw));
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, status);
+  TDX_HIP(hipGetLastError());
+  const size_t n2 = (size_t)n_g * n_g;
+  for (int w0 = 0; w0 < n_w; w0 += (int)cw) {
+    const int nw = (int)std::min<long long>(cw, n_w - w0);
+    const double2 *c = (const double2 *)chi0 + (size_t)w0 * n2;
+    dim3 g((n_g + kT - 1) / kT, (n_g + kT - 1) / kT, nw);
+    hipLaunchKernelGGL(k_one_minus, g, dim3(kT, kT), 0, s, c, (const double2 *)K, n_g, A);
+    TDX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_lu_solve, dim3(nw), dim3(kLuThreads), sizeof(double2) * 2 * n_g, s, A,
+                       c, n_g, i_g0, (double2 *)chi00 + w0, info);
+    TDX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(256), 0, s, info, nw, w0, status);
+    TDX_HIP(hipGetLastError());
+  }
+  int h[2] = {0, 0};
+  TDX_HIP(hipMemcpyAsync(h, status, sizeof(h), hipMemcpyDeviceToHost, s));
+  TDX_HIP(hipStreamSynchronize(s));
+  TDX_REQUIRE(h[0] == INT_MAX, TDX_ERR_NUMERIC,
+              "Dyson matrix singular at frequency %d (column %d)", h[0], h[1] - 1);
+  return TDX_OK;
+}
+
 
 // Check the density grid against the states and the LDS of the density and
 // FFT kernels.
