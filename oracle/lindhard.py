@@ -147,3 +147,46 @@ def continuum_im_chi0(q, w, T, mu):
 def fermi_energy(n):
     """E_F = (3 pi^2 n)^(2/3) / 2 for the spin-unpolarised electron gas."""
     return 0.5 * (3.0 * math.pi ** 2 * n) ** (2.0 / 3.0)
+
+
+def mp_free_chi0(cell, kgrid, ecut, qj, omegas, eta, T, n_electrons, chunk=1 << 18):
+    """chi0_00(q, w) of the free-electron gas on a Monkhorst-Pack grid with
+    every plane wave of energy <= ecut at every k (no band count), written
+    over the momenta p = k + G of all grid points and plane waves at once:
+      2/(N_k Omega) sum_p [f(p^2/2) - f(|p+q|^2/2)] / (w + p^2/2 - |p+q|^2/2 + i eta),
+    mu from the same momenta at N_e electrons.  q = sum_i qj_i / N_i b_i.
+    Returns (chi0 [n_w], mu).  The same sum as ksampled_chi0 with n_bands = 0
+    and no screening, vectorised so that fine grids stay affordable."""
+    A = np.asarray(cell, dtype=np.float64)
+    omega_cell = abs(np.linalg.det(A))
+    B = 2 * math.pi * np.linalg.inv(A).T
+    N = np.asarray(kgrid)
+    gmax = int(math.ceil(math.sqrt(2 * ecut) * np.max(np.linalg.norm(A, axis=1))
+                         / (2 * math.pi))) + 2
+    rng = np.arange(-gmax, gmax + 1)
+    G = np.array(np.meshgrid(rng, rng, rng, indexing="ij")).reshape(3, -1).T
+    axes = [(2 * np.arange(n) + 1 - n) / (2.0 * n) for n in N]
+    K = np.array(np.meshgrid(*axes, indexing="ij")).reshape(3, -1).T
+    ps, es = [], []
+    for kr in K:
+        p = (kr + G) @ B
+        e = 0.5 * np.sum(p * p, axis=1)
+        sel = e <= ecut
+        ps.append(p[sel])
+        es.append(e[sel])
+    p = np.concatenate(ps)
+    e = np.concatenate(es)
+    n_k = len(K)
+    g = lambda mu: 2.0 / n_k * float(np.sum(_fd(e, mu, T))) - n_electrons
+    mu = optimize.brentq(g, e.min() - 60 * T, e.max() + 60 * T, xtol=1e-15, rtol=1e-15,
+                         maxiter=500)
+    q = (np.asarray(qj, dtype=np.float64) / N) @ B
+    om = np.asarray(omegas, dtype=np.float64)
+    out = np.zeros(len(om), dtype=np.complex128)
+    for lo in range(0, len(e), chunk):
+        e1 = e[lo:lo + chunk]
+        pq = p[lo:lo + chunk] + q
+        e2 = 0.5 * np.sum(pq * pq, axis=1)
+        df = _fd(e1, mu, T) - _fd(e2, mu, T)
+        out += (df[None, :] / (om[:, None] + (e1 - e2)[None, :] + 1j * eta)).sum(axis=1)
+    return out * 2.0 / (n_k * omega_cell), mu

@@ -117,3 +117,55 @@ def test_p2_ksampled_itcf_approaches_continuum():
     f_err = np.max(np.abs(r.F - F) / F)
     assert s_err > 3 * f_err
     assert f_err < 0.05
+
+
+def test_p2_vectorised_mp_sum_equals_band_sum():
+    """The vectorised Monkhorst-Pack free-electron sum is the plane-wave
+    Lindhard sum of ksampled_chi0 with every band kept (at a cutoff high
+    enough that no occupied p + q falls outside it)."""
+    w = workloads.feg_c1().with_(kgrid=(4, 4, 4), qs=((4, 0, 0),))
+    om = np.linspace(0.0, 2.0, 17)
+    T = w.temperatures[0]
+    ref, mu_ref = lindhard.ksampled_chi0(w.cell, w.kgrid, w.ecut_wf, 0, w.qs[0], (0, 0, 0), om,
+                                         w.eta, T, w.n_electrons, 0.0)
+    got, mu = lindhard.mp_free_chi0(w.cell, w.kgrid, w.ecut_wf, w.qs[0], om, w.eta, T,
+                                    w.n_electrons)
+    assert abs(mu - mu_ref) < 1e-13
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.slow
+def test_p2_kgrid_gaps_of_S_and_F_shrink():
+    """Sec. 2's premise stated as numbers: for the electron gas of the
+    metallic workload (r_s of Na-like density, eta = 0.01 Ha, 200 frequencies)
+    at q = 2 pi / a, the gap between the k-sampled and the continuum RPA
+    response, in S(q, w) (largest pointwise error over the peak of S) and in
+    F(q, tau) (largest relative error), on 8^3, 16^3 and 24^3 grids.  Both
+    shrink as the grid is refined, and the F gap stays more than an order of
+    magnitude below the S gap (measured: S 2.35, 0.82, 0.36; F 1.9 %, 1.4 %,
+    0.85 %)."""
+    w = workloads.feg_c1()
+    om = w.omega_grid(0)
+    T = w.temperatures[0]
+    beta = 1.0 / T
+    omega_cell = abs(np.linalg.det(np.asarray(w.cell)))
+    n = w.n_electrons / omega_cell
+    q = 2 * math.pi / np.linalg.norm(np.asarray(w.cell)[0])
+    v = 4 * math.pi / q ** 2
+    taus = w.tau_grid(0)
+    mu = lindhard.continuum_mu(n, T)
+    c0 = np.array([lindhard.continuum_chi0(q, x, w.eta, T, mu) for x in om])
+    Sc = oracle.dsf(c0 / (1 - v * c0), om, beta, n)
+    Fc = oracle.itcf(Sc, om, beta, taus)
+    gaps = []
+    for N in (8, 16, 24):
+        c, _ = lindhard.mp_free_chi0(w.cell, (N,) * 3, w.ecut_wf, (N, 0, 0), om, w.eta, T,
+                                     w.n_electrons)
+        S = oracle.dsf(c / (1 - v * c), om, beta, n)
+        F = oracle.itcf(S, om, beta, taus)
+        gaps.append((np.max(np.abs(S - Sc)) / np.max(Sc), np.max(np.abs(F - Fc) / Fc)))
+        print(f"{N}^3: S gap {gaps[-1][0]:.3f}, F gap {gaps[-1][1]:.4f}")
+    s_gap, f_gap = np.array(gaps).T
+    assert np.all(np.diff(s_gap) < 0) and np.all(np.diff(f_gap) < 0)
+    assert np.all(f_gap < s_gap / 10)
+    assert f_gap[-1] < 0.01
