@@ -151,10 +151,10 @@ TRAFFIC_SOURCES = ["paper_2510_01875_amd/csrc/chi0_bf16x3.hip",
 
 
 def measured_traffic(workload, prec):
-    """HBM bytes per step of the split-BF16 chi0 launches from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (scaled by the plain-copy
-    calibration), or None if that summary was taken on other kernel sources
-    or another workload."""
+    """HBM bytes per launch (one q, averaged over the step's launches) of the
+    split-BF16 chi0 kernel from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary (scaled by the plain-copy calibration), or None if that summary
+    was taken on other kernel sources or another workload."""
     if workload != "fcc_c2" or prec != "bf16x3" or not os.path.exists(TRAFFIC_PROFILE):
         return None
     h = hashlib.sha256()
@@ -169,7 +169,7 @@ def measured_traffic(workload, prec):
                 rec[k.strip()] = v.strip()
     if rec.get("kernel_sources_sha256_16") != h.hexdigest()[:16]:
         return None
-    return float(rec["traffic_bytes_per_step"])
+    return float(rec["traffic_bytes_per_launch"])
 
 
 def errors(S, Sref, F, Fref):
