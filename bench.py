@@ -651,6 +651,23 @@ def main():
                      "conditions and per-degree selection (whole search timed)"}
     log(f"attenuation: {len(windows)} filters in {dt_att * 1e3:.1f} ms")
 
+    # the Kubo-Greenwood conductivity of the states (Sec. A.3's input) on
+    # q0's positive frequencies, then S* from it
+    trk = tdx.transitions(ctx, st, (0, 0, 0), w.f_trans_thr)
+    omk = om0[1:].contiguous()
+    kw = torch.empty(tdx.kg_work_bytes(len(trk), omk.shape[0]), dtype=torch.uint8, device="cuda")
+    tdx.kg_conductivity(ctx, st, omk, w.eta, w.f_trans_thr, tr=trk, work=kw)
+    d0.record(stream)
+    sig = tdx.kg_conductivity(ctx, st, omk, w.eta, w.f_trans_thr, tr=trk, work=kw)
+    Sk = tdx.kg_dsf(ctx, sig, omk, beta0, dens0)
+    d1.record(stream)
+    torch.cuda.synchronize()
+    kg = {"ms": d0.elapsed_time(d1), "n_trans": len(trk), "n_w": int(omk.shape[0]),
+          "finite": bool(torch.isfinite(Sk).all()),
+          "form": "sigma_KG of the states over the q = 0 transitions (trace average, "
+                  "Lorentzian eta), then S*"}
+    del trk, kw, sig, Sk
+
     per_launch = flops_step
     avg_ms = sum(launch_ms) / len(launch_ms)
     line = {
@@ -684,6 +701,7 @@ def main():
         "error_vs_fp64": err,
         "eta_scan": eta_info,
         "dielectric": diel,
+        "kubo_greenwood": kg,
         "attenuation": atten,
         "roofline": {"bound": "mfma", "achieved": per_launch / (avg_ms * 1e-3) / 1e12,
                      "peak": PEAK_TFLOPS[args.prec], "unit": "TFLOP/s",

@@ -579,6 +579,29 @@ int tdx_sg_select(const double *scores, const double *resid, int n_filt, int n_w
 int tdx_kg_dsf(tdx_ctx *ctx, const double *sigma, const double *omega, int n_w, double beta,
                double density, double *S_star, tdx_stream stream);
 
+/* The Kubo-Greenwood conductivity of the states, the input of the route
+ * above (Sec. A.3 starts from it; its eta test broadens it): the trace
+ * average over the three Cartesian directions with every transition's
+ * delta function broadened into a Lorentzian of half-width eta,
+ *   sigma(w) = 2 i / (Omega N_k) sum_t W_t / (w - delta_t + i eta),
+ *   W_t = (df_t / delta_t) (1/3) sum_a |<m k| p_a |n k>|^2,
+ *   <m k| p_a |n k> = sum_G conj(c_mk(G)) (k + G)_a c_nk(G),  p = -i grad,
+ * the factor 2 for the spins.  Re sigma is the usual
+ * (2 pi / (3 Omega w)) sum (f_n - f_m) |p_mn|^2 delta(e_m - e_n - w) per
+ * k-point weight 1/N_k, broadened; Im sigma is its Kramers-Kronig partner.
+ * tl: the transitions of tdx_transitions at qj = (0, 0, 0) for these
+ * states and occupations (delta = e_m - e_n, df = f_n - f_m; the screening
+ * threshold of that call is the conductivity's), the full list (a paired
+ * list is INVALID_ARG); n_trans its count (0 gives sigma = 0).  omega:
+ * device [n_w]; sigma: device complex128 [n_w] (out).  work: device,
+ * caller-owned, at least tdx_kg_work_bytes(n_trans, n_w) bytes (SHAPE if
+ * smaller).  No allocation, memset or host synchronisation: a HIP graph
+ * can hold the call. */
+size_t tdx_kg_work_bytes(int64_t n_trans, int n_w);
+int tdx_kg_conductivity(tdx_ctx *ctx, const tdx_states *st, const tdx_translist *tl,
+                        int64_t n_trans, const double *omega, int n_w, double eta, double *sigma,
+                        void *work, size_t work_bytes, tdx_stream stream);
+
 /* ------------------------------------------------------------------ */
 /* Reverse mode: vector-Jacobian products of F(q,tau) (FP64)           */
 /* ------------------------------------------------------------------ */

@@ -172,6 +172,12 @@ _sgsel = _sig("tdx_sg_select", [c_dbl_p, c_dbl_p, C.c_int, C.c_int, C.c_double, 
                                 C.c_double, C.c_double, C.POINTER(C.c_int)])
 _kgdsf = _sig("tdx_kg_dsf", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
                             C.c_double, C.c_void_p, C.c_void_p])
+_kg_work = _lib.tdx_kg_work_bytes
+_kg_work.restype = C.c_size_t
+_kg_work.argtypes = [C.c_int64, C.c_int]
+_kgsig = _sig("tdx_kg_conductivity", [C.c_void_p, C.POINTER(StatesC), C.POINTER(TransC),
+                                      C.c_int64, C.c_void_p, C.c_int, C.c_double, C.c_void_p,
+                                      C.c_void_p, C.c_size_t, C.c_void_p])
 _eta_ref = _sig("tdx_eta_reference", [c_dbl_p, c_dbl_p, C.c_int, C.c_double,
                                       C.POINTER(C.c_int)])
 _itcf_vjp = _sig("tdx_itcf_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
@@ -205,7 +211,7 @@ EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_chi0", "tdx_kernel_matrix",
             "tdx_xc_kernel_grid", "tdx_kernel_matrix_from_grid",
             "tdx_dyson", "tdx_dyson_noalloc", "tdx_dyson_noalloc_max_bytes", "tdx_dsf",
-            "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_dielectric", "tdx_sg_filter", "tdx_derivative_psd", "tdx_sg_scores", "tdx_residual_itcf", "tdx_sg_select", "tdx_kg_dsf", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
+            "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_dielectric", "tdx_sg_filter", "tdx_derivative_psd", "tdx_sg_scores", "tdx_residual_itcf", "tdx_sg_select", "tdx_kg_dsf", "tdx_kg_work_bytes", "tdx_kg_conductivity", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
             "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
             "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_chi0_set_slice_length", "tdx_autotune_chi0", "tdx_tune_save",
             "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async", "tdx_itcf_vjp",
@@ -713,6 +719,28 @@ def kg_dsf(ctx: Context, sigma: torch.Tensor, omega: torch.Tensor, beta: float, 
     check(_kgdsf(ctx.handle, _ptr(sigma.contiguous()), _ptr(omega), omega.shape[0], beta,
                  density, _ptr(S), _stream(stream)))
     return S
+
+
+def kg_work_bytes(n_trans: int, n_w: int) -> int:
+    return int(_kg_work(int(n_trans), int(n_w)))
+
+
+def kg_conductivity(ctx: Context, st: States, omega: torch.Tensor, eta: float, thr: float,
+                    tr: Optional[Transitions] = None, work: Optional[torch.Tensor] = None,
+                    stream=None) -> torch.Tensor:
+    """Kubo-Greenwood conductivity of the states (complex128 [n_w]), the
+    trace average broadened by eta (Sec. A.3; tdx.h), over the q = 0
+    transitions screened by thr (built here unless `tr` is that list)."""
+    if tr is None:
+        tr = transitions(ctx, st, (0, 0, 0), thr, stream=stream)
+    n_w = omega.shape[0]
+    if work is None:
+        work = torch.empty(max(kg_work_bytes(len(tr), n_w), 1), dtype=torch.uint8,
+                           device=omega.device)
+    sigma = torch.empty(n_w, dtype=torch.complex128, device=omega.device)
+    check(_kgsig(ctx.handle, C.byref(st.c), C.byref(tr.c), len(tr), _ptr(omega), n_w, eta,
+                 _ptr(sigma), _ptr(work), work.numel(), _stream(stream)))
+    return sigma
 
 
 def kg_dielectric(ctx: Context, S_star: torch.Tensor, omega: torch.Tensor, beta: float,
