@@ -527,6 +527,16 @@ def main():
                                  st.chi0_pref)
             v, sl, ms = tdx.autotune_chi0(ctx, probe, max_trans=1 << 22)
             tuned = {"variant": v, "slice_log2": sl, "probe_ms": ms, "source": "autotuned now"}
+            # the FP64 and FP32 tiles of the comparison legs, on the first 2^19
+            # transitions of the same probe
+            for fp in [p for p in args.compare.split(",") if p in ("fp64", "fp32")]:
+                Pf = tdx.pair_density(ctx, st, w.qs[0], tr0, b0, fp, n_trans=1 << 19)
+                pf = tdx.Chi0Item(tr0, Pf, b0.shape[0], setup[0][2], w.eta, st.chi0_pref,
+                                  n_trans=min(len(tr0), 1 << 19))
+                vf, _, msf = tdx.autotune_chi0(ctx, pf, max_trans=1 << 19, prec=fp)
+                tuned[fp] = {"variant": vf, "probe_ms": msf}
+                log(f"autotune {fp}: variant {vf}, {msf:.1f} ms on the probe")
+                del Pf, pf
             out = args.tune_save or args.tune_cache
             os.makedirs(os.path.dirname(os.path.abspath(out)), exist_ok=True)
             tdx.tune_save(ctx, out)

@@ -327,12 +327,14 @@ int tdx_chi0_plan_destroy(tdx_chi0_plan *plan);
 int tdx_chi0_batched(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, int prec,
                      tdx_stream stream);
 
-/* Number of tile variants of a precision (split-BF16: frequencies per wave
- * x G' per workgroup x chunk). */
+/* Number of tile variants of a precision (frequencies per wave x G' per
+ * workgroup x chunk, and for split-BF16 buffering and waves per workgroup). */
 int tdx_chi0_variants(int prec, int *count);
-/* Tile variant (-1 = default: the 8-wave 2 x 9 tile with three LDS buffers)
- * and slice length 2^slice_log2 (default 2^20) used for bases of n_g vectors
- * (size classes of 16). */
+/* Tile variant (-1 = default: for split-BF16 the 8-wave 2 x 9 tile with three
+ * LDS buffers, for FP32 and FP64 variant 0) and slice length 2^slice_log2
+ * (default 2^20; split-BF16 only, the FP32 and FP64 kernels choose their
+ * slices to fill the chip) used for bases of n_g vectors (size classes of
+ * 16), per precision. */
 int tdx_chi0_set_config(tdx_ctx *ctx, int prec, int n_g, int variant, int slice_log2);
 int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slice_log2);
 /* Slice length of every later chi0 contraction on this context (all
@@ -346,15 +348,17 @@ int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slic
  * order and the partial workspace (slices x n_w x n_g^2 x 16 bytes). */
 int tdx_chi0_set_slice_length(tdx_ctx *ctx, int64_t n);
 
-/* Time every variant and slice length 2^{18,20} on the probe item (its
- * first max_trans transitions; probe->chi0 is overwritten) in both launch
- * forms, one grid launch and a one-item plan (the persistent kernel), keep
- * the one with the smallest sum of the two times for the probe's size class
- * in the context and return it (best_ms is that sum).  Allocates the
- * one-item plans; synchronises. */
+/* Time every variant of `prec` on the probe item (its first max_trans
+ * transitions, P in that precision's layout; probe->chi0 is overwritten),
+ * keep the fastest for the probe's size class in the context and return it.
+ * Split-BF16: every variant and slice length 2^{18,20} in both launch forms,
+ * one grid launch and a one-item plan (the persistent kernel), ranked by the
+ * sum of the two times (best_ms); FP32 and FP64: one grid launch per variant
+ * (best_slice_log2 returns the unused stored value).  Allocates; synchronises. */
 int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_t max_trans,
                       int *best_variant, int *best_slice_log2, double *best_ms);
-/* Tuning cache as JSON text keyed by the gfx arch. */
+/* Tuning cache as JSON text keyed by the gfx arch, one entry per precision
+ * and size class. */
 int tdx_tune_save(tdx_ctx *ctx, const char *path);
 int tdx_tune_load(tdx_ctx *ctx, const char *path);
 

@@ -32,8 +32,9 @@ __global__ void k_reduce_slices(const double2 *part, int n_slices, size_t per_sl
 }  // namespace
 
 // FP32 and FP64 paths (chi0_fp.hip).
-void chi0_fp_shape(bool f64, int *wblock, int *cols, int *chunk);
-int chi0_fp_launch(bool f64, const void *P, int ld, const double *delta, const double *df,
+int chi0_fp_variant_count(bool f64);
+void chi0_fp_shape(bool f64, int v, int *wblock, int *cols, int *chunk);
+int chi0_fp_launch(bool f64, int v, const void *P, int ld, const double *delta, const double *df,
                    int paired, long long n_trans, long long slice_len, int slices,
                    const double *omega, int n_w, double eta, int n_g, double2 *part,
                    hipStream_t s);
@@ -76,8 +77,10 @@ extern "C" int tdx_chi0(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, 
                        (double2 *)chi0, s);
   const int nblk = ld / 16;
   const bool f64 = prec == TDX_PREC_FP64;
+  const int tv = ctx->tune[prec][std::min(nblk, 63)].variant;
+  const int v = tv >= 0 && tv < chi0_fp_variant_count(f64) ? tv : 0;
   int wblock, cols, chunk;
-  chi0_fp_shape(f64, &wblock, &cols, &chunk);
+  chi0_fp_shape(f64, v, &wblock, &cols, &chunk);
   const long long base =
       (long long)((n_w + wblock - 1) / wblock) * nblk * ((ld + cols - 1) / cols);
   // enough slices to fill the chip (or the context's fixed length); each
@@ -94,7 +97,7 @@ extern "C" int tdx_chi0(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans, 
   void *w;
   TDX_TRY(ws_get(ctx, WS_PARTIAL, sizeof(double2) * out_elems * slices, &w));
   double2 *part = (double2 *)w;
-  TDX_TRY(chi0_fp_launch(f64, P, ld, tl->delta, tl->df, (int)tl->paired, (long long)n_trans,
+  TDX_TRY(chi0_fp_launch(f64, v, P, ld, tl->delta, tl->df, (int)tl->paired, (long long)n_trans,
                          slice_len, (int)slices, omega, n_w, eta, n_g, part, s));
   TDX_HIP(hipGetLastError());
   const unsigned rb = (unsigned)std::min<size_t>((out_elems + 255) / 256, 8192);

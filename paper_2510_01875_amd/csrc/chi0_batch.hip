@@ -12,6 +12,9 @@
 #include "internal.h"
 
 namespace tdx {
+
+int chi0_fp_variant_count(bool f64);  // chi0_fp.hip
+
 namespace {
 
 constexpr int kChunkAlign = 32;   // slice lengths are multiples of every variant's chunk
@@ -77,9 +80,19 @@ __global__ void k_reduce_batch(const ReduceItem *items) {
 int bucket_of(int ld) { return std::min(ld / 16, 63); }
 
 void pick(const tdx_ctx *ctx, int ld, int *variant, int *slice_log2) {
-  const tdx_chi0_tune &t = ctx->tune[bucket_of(ld)];
+  const tdx_chi0_tune &t = ctx->tune[TDX_PREC_BF16X3][bucket_of(ld)];
   *variant = t.variant >= 0 ? t.variant : bf16x3_default_variant();
   *slice_log2 = t.slice_log2;
+}
+
+// Tile variants of a precision (the FP32 and FP64 ones in chi0_fp.hip).
+int variant_count(int prec) {
+  return prec == TDX_PREC_BF16X3 ? bf16x3_variant_count()
+                                 : chi0_fp_variant_count(prec == TDX_PREC_FP64);
+}
+
+const char *prec_name(int prec) {
+  return prec == TDX_PREC_FP64 ? "fp64" : prec == TDX_PREC_FP32 ? "fp32" : "bf16x3";
 }
 
 // Slices of a transition list: about 2^slice_log2 transitions each, enough
@@ -173,19 +186,20 @@ extern "C" {
 int tdx_chi0_variants(int prec, int *count) {
   clear_error();
   TDX_REQUIRE(count, TDX_ERR_INVALID_ARG, "count is null");
-  *count = prec == TDX_PREC_BF16X3 ? bf16x3_variant_count() : 1;
+  TDX_REQUIRE(prec >= TDX_PREC_FP64 && prec <= TDX_PREC_BF16X3, TDX_ERR_INVALID_ARG, "bad prec");
+  *count = variant_count(prec);
   return TDX_OK;
 }
 
 int tdx_chi0_set_config(tdx_ctx *ctx, int prec, int n_g, int variant, int slice_log2) {
   clear_error();
   TDX_REQUIRE(ctx, TDX_ERR_INVALID_ARG, "ctx is null");
-  TDX_REQUIRE(prec == TDX_PREC_BF16X3, TDX_ERR_UNSUPPORTED, "only split-BF16 has variants");
-  TDX_REQUIRE(variant >= -1 && variant < bf16x3_variant_count(), TDX_ERR_INVALID_ARG,
+  TDX_REQUIRE(prec >= TDX_PREC_FP64 && prec <= TDX_PREC_BF16X3, TDX_ERR_INVALID_ARG, "bad prec");
+  TDX_REQUIRE(variant >= -1 && variant < variant_count(prec), TDX_ERR_INVALID_ARG,
               "bad variant %d", variant);
   TDX_REQUIRE(slice_log2 >= 10 && slice_log2 <= 30, TDX_ERR_INVALID_ARG, "bad slice_log2");
   TDX_REQUIRE(n_g > 0, TDX_ERR_INVALID_ARG, "bad n_g");
-  tdx_chi0_tune &t = ctx->tune[bucket_of((n_g + 15) / 16 * 16)];
+  tdx_chi0_tune &t = ctx->tune[prec][bucket_of((n_g + 15) / 16 * 16)];
   t.variant = variant;
   t.slice_log2 = slice_log2;
   return TDX_OK;
@@ -203,8 +217,14 @@ int tdx_chi0_set_slice_length(tdx_ctx *ctx, int64_t n) {
 int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slice_log2) {
   clear_error();
   TDX_REQUIRE(ctx && variant && slice_log2, TDX_ERR_INVALID_ARG, "null argument");
-  TDX_REQUIRE(prec == TDX_PREC_BF16X3, TDX_ERR_UNSUPPORTED, "only split-BF16 has variants");
-  pick(ctx, (n_g + 15) / 16 * 16, variant, slice_log2);
+  TDX_REQUIRE(prec >= TDX_PREC_FP64 && prec <= TDX_PREC_BF16X3, TDX_ERR_INVALID_ARG, "bad prec");
+  if (prec == TDX_PREC_BF16X3) {
+    pick(ctx, (n_g + 15) / 16 * 16, variant, slice_log2);
+  } else {
+    const tdx_chi0_tune &t = ctx->tune[prec][bucket_of((n_g + 15) / 16 * 16)];
+    *variant = t.variant >= 0 ? t.variant : 0;
+    *slice_log2 = t.slice_log2;
+  }
   return TDX_OK;
 }
 
@@ -378,7 +398,7 @@ int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_
   clear_error();
   TDX_REQUIRE(ctx && probe && best_variant && best_slice_log2 && best_ms, TDX_ERR_INVALID_ARG,
               "null argument");
-  TDX_REQUIRE(prec == TDX_PREC_BF16X3, TDX_ERR_UNSUPPORTED, "only split-BF16 has variants");
+  TDX_REQUIRE(prec >= TDX_PREC_FP64 && prec <= TDX_PREC_BF16X3, TDX_ERR_INVALID_ARG, "bad prec");
   TDX_REQUIRE(probe->tl && probe->P && probe->omega && probe->chi0, TDX_ERR_INVALID_ARG,
               "probe has a null pointer");
   TDX_TRY(check_device(ctx));
@@ -400,7 +420,7 @@ int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_
   tdx_chi0_item one = *probe;
   one.n_trans = nt;
   one.p_rows = p_rows;
-  tdx_chi0_tune &slot = ctx->tune[bucket_of(ld)];
+  tdx_chi0_tune &slot = ctx->tune[prec][bucket_of(ld)];
   const tdx_chi0_tune saved = slot;
   auto timed = [&](auto &&enqueue) {
     double ms_best = 1e300;
@@ -415,7 +435,22 @@ int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_
     }
     return ms_best;
   };
-  for (int v = 0; v < bf16x3_variant_count() && rc == TDX_OK; ++v) {
+  // FP32 / FP64: one grid launch per variant (their slices fill the chip;
+  // there is no persistent form)
+  for (int v = 0; prec != TDX_PREC_BF16X3 && v < variant_count(prec) && rc == TDX_OK; ++v) {
+    slot.variant = v;
+    const double ms_best = timed([&] {
+      return tdx_chi0(ctx, probe->tl, nt, probe->P, probe->n_g, prec, probe->omega, probe->n_w,
+                      probe->eta, probe->pref, probe->chi0, (tdx_stream)s);
+    });
+    slot = saved;
+    if (rc == TDX_OK && ms_best < best) {
+      best = ms_best;
+      bv = v;
+      bs = saved.slice_log2;
+    }
+  }
+  for (int v = 0; prec == TDX_PREC_BF16X3 && v < bf16x3_variant_count() && rc == TDX_OK; ++v) {
     for (int sl : slice_opts) {
       double ms_best = timed([&] {
         return chi0_bf16x3_with(ctx, v, sl, probe->P, p_rows, ld, probe->tl->delta,
@@ -443,7 +478,7 @@ int tdx_autotune_chi0(tdx_ctx *ctx, const tdx_chi0_item *probe, int prec, int64_
   hipEventDestroy(e1);
   hipStreamDestroy(s);
   if (rc != TDX_OK) return rc;
-  tdx_chi0_tune &t = ctx->tune[bucket_of(ld)];
+  tdx_chi0_tune &t = ctx->tune[prec][bucket_of(ld)];
   t.variant = bv;
   t.slice_log2 = bs;
   t.ms = best;
@@ -458,15 +493,18 @@ int tdx_tune_save(tdx_ctx *ctx, const char *path) {
   TDX_REQUIRE(ctx && path, TDX_ERR_INVALID_ARG, "null argument");
   FILE *f = std::fopen(path, "w");
   TDX_REQUIRE(f, TDX_ERR_INVALID_ARG, "cannot write %s", path);
-  std::fprintf(f, "{\"arch\": \"gfx950\", \"prec\": \"bf16x3\", \"entries\": [\n");
+  std::fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [\n");
   bool first = true;
-  for (int b = 0; b < 64; ++b) {
-    const tdx_chi0_tune &t = ctx->tune[b];
-    if (t.variant < 0) continue;
-    std::fprintf(f, "%s  {\"blocks\": %d, \"variant\": %d, \"slice_log2\": %d, \"ms\": %.4f}",
-                 first ? "" : ",\n", b, t.variant, t.slice_log2, t.ms);
-    first = false;
-  }
+  for (int p = TDX_PREC_FP64; p <= TDX_PREC_BF16X3; ++p)
+    for (int b = 0; b < 64; ++b) {
+      const tdx_chi0_tune &t = ctx->tune[p][b];
+      if (t.variant < 0) continue;
+      std::fprintf(f,
+                   "%s  {\"prec\": \"%s\", \"blocks\": %d, \"variant\": %d, \"slice_log2\": %d, "
+                   "\"ms\": %.4f}",
+                   first ? "" : ",\n", prec_name(p), b, t.variant, t.slice_log2, t.ms);
+      first = false;
+    }
   std::fprintf(f, "\n]}\n");
   std::fclose(f);
   return TDX_OK;
@@ -484,10 +522,20 @@ int tdx_tune_load(tdx_ctx *ctx, const char *path) {
     if (std::strstr(line, "\"arch\": \"gfx950\"")) arch_ok = true;
     int b, v, sl;
     double ms;
-    if (arch_ok && std::sscanf(line, " {\"blocks\": %d, \"variant\": %d, \"slice_log2\": %d, "
-                                     "\"ms\": %lf}", &b, &v, &sl, &ms) == 4) {
-      if (b >= 0 && b < 64 && v >= 0 && v < bf16x3_variant_count() && sl >= 10 && sl <= 30) {
-        ctx->tune[b] = tdx_chi0_tune{v, sl, ms};
+    char pn[16] = "bf16x3";
+    // entries name their precision; entries without one (older caches)
+    // are split-BF16
+    const bool with_prec =
+        std::sscanf(line, " {\"prec\": \"%15[a-z0-9]\", \"blocks\": %d, \"variant\": %d, "
+                          "\"slice_log2\": %d, \"ms\": %lf}", pn, &b, &v, &sl, &ms) == 5;
+    if (arch_ok && (with_prec || std::sscanf(line, " {\"blocks\": %d, \"variant\": %d, "
+                                                  "\"slice_log2\": %d, \"ms\": %lf}",
+                                             &b, &v, &sl, &ms) == 4)) {
+      int p = -1;
+      for (int q = TDX_PREC_FP64; q <= TDX_PREC_BF16X3; ++q)
+        if (std::strcmp(pn, prec_name(q)) == 0) p = q;
+      if (p >= 0 && b >= 0 && b < 64 && v >= 0 && v < variant_count(p) && sl >= 10 && sl <= 30) {
+        ctx->tune[p][b] = tdx_chi0_tune{v, sl, ms};
         ++loaded;
       }
     }

@@ -270,12 +270,6 @@ __global__ void __launch_bounds__(256, 2)
                                      part + (size_t)bz * n_w * n_g * n_g);
 }
 
-// Tile shapes: (frequencies per wave, column blocks, transitions per chunk).
-struct FpShape {
-  int wpw, sub, chunk;
-};
-constexpr FpShape kShapeF32{4, 3, 32}, kShapeF64{2, 3, 16};
-
 template <class E, int WPW, int SUB, int CHUNK>
 int launch_fp(const void *P, int ld, const double *delta, const double *df, int paired,
               long long n_trans, long long slice_len, int slices, const double *omega, int n_w,
@@ -292,26 +286,49 @@ int launch_fp(const void *P, int ld, const double *delta, const double *df, int 
   return TDX_OK;
 }
 
+
+// Tile variants: (frequencies per wave, column blocks, transitions per
+// chunk); variant 0 of each precision is the default.
+struct FpVariant {
+  int wpw, sub, chunk;
+  int (*launch)(const void *, int, const double *, const double *, int, long long, long long,
+                int, const double *, int, double, int, double2 *, hipStream_t);
+};
+
+#define TDX_FPV(E, W, S, K) FpVariant{W, S, K, launch_fp<E, W, S, K>}
+const FpVariant kVarF32[] = {TDX_FPV(float, 4, 3, 32), TDX_FPV(float, 4, 2, 32),
+                             TDX_FPV(float, 4, 4, 32), TDX_FPV(float, 2, 3, 32),
+                             TDX_FPV(float, 2, 6, 32)};
+const FpVariant kVarF64[] = {TDX_FPV(double, 2, 3, 16), TDX_FPV(double, 2, 2, 16),
+                             TDX_FPV(double, 2, 4, 16), TDX_FPV(double, 1, 3, 16),
+                             TDX_FPV(double, 1, 6, 16)};
+#undef TDX_FPV
+
+const FpVariant &fp_variant(bool f64, int v) { return f64 ? kVarF64[v] : kVarF32[v]; }
+
 }  // namespace
 
-// Tile shape of the FP32 (f64 = false) or FP64 contraction: frequencies and
-// G' columns per workgroup, transitions per chunk (slices are multiples of it).
-void chi0_fp_shape(bool f64, int *wblock, int *cols, int *chunk) {
-  const FpShape &S = f64 ? kShapeF64 : kShapeF32;
-  *wblock = 4 * S.wpw;
-  *cols = 16 * S.sub;
-  *chunk = S.chunk;
+int chi0_fp_variant_count(bool f64) {
+  return f64 ? (int)(sizeof(kVarF64) / sizeof(kVarF64[0]))
+             : (int)(sizeof(kVarF32) / sizeof(kVarF32[0]));
 }
 
-int chi0_fp_launch(bool f64, const void *P, int ld, const double *delta, const double *df,
+// Tile shape of variant v of the FP32 (f64 = false) or FP64 contraction:
+// frequencies and G' columns per workgroup, transitions per chunk (slices
+// are multiples of it).
+void chi0_fp_shape(bool f64, int v, int *wblock, int *cols, int *chunk) {
+  const FpVariant &V = fp_variant(f64, v);
+  *wblock = 4 * V.wpw;
+  *cols = 16 * V.sub;
+  *chunk = V.chunk;
+}
+
+int chi0_fp_launch(bool f64, int v, const void *P, int ld, const double *delta, const double *df,
                    int paired, long long n_trans, long long slice_len, int slices,
                    const double *omega, int n_w, double eta, int n_g, double2 *part,
                    hipStream_t s) {
-  if (f64)
-    return launch_fp<double, kShapeF64.wpw, kShapeF64.sub, kShapeF64.chunk>(
-        P, ld, delta, df, paired, n_trans, slice_len, slices, omega, n_w, eta, n_g, part, s);
-  return launch_fp<float, kShapeF32.wpw, kShapeF32.sub, kShapeF32.chunk>(
-      P, ld, delta, df, paired, n_trans, slice_len, slices, omega, n_w, eta, n_g, part, s);
+  return fp_variant(f64, v).launch(P, ld, delta, df, paired, n_trans, slice_len, slices, omega,
+                                   n_w, eta, n_g, part, s);
 }
 
 }  // namespace tdx

@@ -45,8 +45,10 @@ struct Workspace {
 
 }  // namespace tdx
 
-// Tile variant and slice length of the split-BF16 chi0 kernel for one
-// response-basis size class (ld / 16 blocks); variant -1 = default.
+// Tile variant and slice length of a chi0 kernel for one precision and
+// response-basis size class (ld / 16 blocks); variant -1 = default.  The
+// FP32 and FP64 kernels choose their slices to fill the chip and use only
+// the variant.
 struct tdx_chi0_tune {
   int variant = -1;  // -1: the default variant
   int slice_log2 = 20;
@@ -59,7 +61,7 @@ struct tdx_ctx {
   rocblas_handle blas = nullptr;
   size_t limit = 0;  // 0 = unlimited
   tdx::Workspace ws[13];
-  tdx_chi0_tune tune[64];
+  tdx_chi0_tune tune[3][64];  // [prec][size class]
   long long slice_len = 0;  // chi0 slice length; 0 = chosen per call to fill the chip
 };
 

@@ -185,3 +185,53 @@ def test_autotuner_picks_a_variant_and_round_trips_the_cache(tdx, ctx):
         _say(f"  variant {var} vs 0: {err:.2e}")
         assert err < 1e-5
     tdx.chi0_set_config(ctx, n_g, -1, 20)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("fp64", 1e-12)])
+def test_fp_variants_tune_and_match_oracle(tdx, ctx, prec, tol):
+    """The FP32 and FP64 tile variants: every one within the precision's bar
+    of the oracle (N_G = 119: 8 column blocks in 2 to 4 column tiles, ragged
+    last ones among them, and several slices), the autotuner's choice stored
+    per precision beside the split-BF16 entry and kept through a save and
+    load of the cache."""
+    import oracle
+    _say("fp variants", prec)
+    w = workloads.fcc_small()
+    w = w.with_(ecut_chi=(w.ecut_chi[0], 8.0, w.ecut_chi[2]))
+    st = tdx.build_states(ctx, w)
+    p = _prepare(tdx, ctx, w.with_(qs=w.qs[1:2], temperatures=w.temperatures[1:2],
+                                   ecut_chi=w.ecut_chi[1:2], omega_max=w.omega_max[1:2]), st,
+                 prec)[0]
+    n_g = len(p["basis"])
+    assert n_g == 119
+    ost = oracle.build_states(w.with_(temperatures=w.temperatures[1:2]))
+    r = oracle.run_q(w, ost, 1)
+    pos = {tuple(x): i for i, x in enumerate(r.basis)}
+    perm = np.array([pos[tuple(x)] for x in p["basis"]])
+    ref = r.chi0[:, perm][:, :, perm]
+    n_var = tdx.chi0_variants(prec)
+    assert n_var >= 4
+    tdx.chi0_set_slice_length(ctx, 512)  # several slices at this size
+    for var in range(n_var):
+        tdx.chi0_set_config(ctx, n_g, var, 20, prec)
+        assert tdx.chi0_get_config(ctx, n_g, prec)[0] == var
+        c = tdx.chi0(ctx, p["tr"], p["P"], n_g, prec, p["om"], w.eta, st.chi0_pref).cpu().numpy()
+        err = np.max(np.abs(c - ref)) / np.max(np.abs(ref))
+        _say(f"  {prec} variant {var}: chi0 err {err:.2e}")
+        assert err < tol
+    tdx.chi0_set_slice_length(ctx, 0)
+    tdx.chi0_set_config(ctx, n_g, -1, 20, prec)
+    v, _, ms = tdx.autotune_chi0(ctx, p["item"], prec=prec)
+    _say(f"  {prec} best variant {v}, {ms:.3f} ms")
+    assert 0 <= v < n_var and ms > 0
+    assert tdx.chi0_get_config(ctx, n_g, prec)[0] == v
+    tdx.chi0_set_config(ctx, n_g, 3, 18, "bf16x3")
+    path = os.path.join(tempfile.mkdtemp(), "tune.json")
+    tdx.tune_save(ctx, path)
+    c2 = tdx.Context(0)
+    tdx.tune_load(c2, path)
+    assert tdx.chi0_get_config(c2, n_g, prec)[0] == v
+    assert tdx.chi0_get_config(c2, n_g, "bf16x3") == (3, 18)
+    c2.close()
+    tdx.chi0_set_config(ctx, n_g, -1, 20, "bf16x3")
+    tdx.chi0_set_config(ctx, n_g, -1, 20, prec)
