@@ -682,7 +682,11 @@ int tdx_occupations_vjp(tdx_ctx *ctx, const tdx_states *st, const double *occ_ba
  * orbital cotangents coef_bar (device complex128 [n_k][nb_max][npw_max],
  * +=) from rho_bar of the transitions t_begin .. t_end - 1 of one q (layout
  * of tdx_chi0_vjp, row 0 = t_begin), so that a list can be swept in blocks.
- * Synchronises. */
+ * Per k of the range the cost is two dense complex products of
+ * n_g x nb x nb x npw (the range's rho_bar scattered into an nb x nb matrix
+ * per G), whatever the number of the k's transitions in the range: ranges
+ * cut at k boundaries avoid repeating them.  Workspace: up to 2 GiB of
+ * products plus nb_max^2 per response vector of a block.  Synchronises. */
 int tdx_pair_density_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
                          const tdx_translist *tl, int64_t t_begin, int64_t t_end,
                          const int *gbasis, int n_g, const double *rho_bar, double *coef_bar,

@@ -4,7 +4,9 @@
 // orbitals, the potential.  Complex cotangents follow dL = Re(conj(zbar) dz).
 // All arithmetic is FP64; every reduction runs in a fixed order, so results
 // are bitwise reproducible.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
 #include "tables.h"
@@ -321,103 +323,58 @@ __global__ void __launch_bounds__(kOccThreads)
   }
 }
 
-// Pair-density adjoint, outgoing side:
-//   coef_bar(k,n)(G1) += sum_{t in row (k,n)} sum_G conj(rhobar_t(G)) c_{m_t,k'}(G1 + G + G_s)
-// over the transitions of the range the row tables cover (rhobar row t - t_lo).
-// One workgroup per (k, n) row; threads over G1.
-__global__ void __launch_bounds__(256)
-    k_pd_vjp_out(const double2 *coef, const int *miller, const int *npw, int nb_max, int npw_max,
-                 const int *tm, const long long *rowbeg, const long long *rowend,
-                 const int *kpmap, const int *gsmap, const int *gbasis, int n_g, int ld,
-                 const int *lut, long box, int M0, int M1, int M2, long long t_lo,
-                 const double2 *rhobar, double2 *coef_bar) {
-  const int n = blockIdx.x, k = blockIdx.y;
-  const long long t0 = rowbeg[(size_t)k * nb_max + n], t1 = rowend[(size_t)k * nb_max + n];
-  if (t1 <= t0) return;
-  const int kp = kpmap[k];
-  const int gs0 = gsmap[3 * k], gs1 = gsmap[3 * k + 1], gs2 = gsmap[3 * k + 2];
-  const int W1 = 2 * M1 + 1, W2 = 2 * M2 + 1;
-  const int *lutp = lut + (size_t)kp * box;
-  const int *mk = miller + (size_t)k * npw_max * 3;
-  const double2 *cp = coef + (size_t)kp * nb_max * npw_max;
-  for (int i = threadIdx.x; i < npw[k]; i += 256) {
-    double ar = 0.0, ai = 0.0;
-    for (int g = 0; g < n_g; ++g) {
-      const int x0 = mk[3 * i] + gbasis[3 * g] + gs0 + M0;
-      const int x1 = mk[3 * i + 1] + gbasis[3 * g + 1] + gs1 + M1;
-      const int x2 = mk[3 * i + 2] + gbasis[3 * g + 2] + gs2 + M2;
-      if (x0 < 0 || x0 > 2 * M0 || x1 < 0 || x1 >= W1 || x2 < 0 || x2 >= W2) continue;
-      const int idx = lutp[((long)x0 * W1 + x1) * W2 + x2];
-      if (idx < 0) continue;
-      for (long long t = t0; t < t1; ++t) {
-        const double2 rb = rhobar[(size_t)(t - t_lo) * ld + g];
-        const double2 c = cp[(size_t)tm[t] * npw_max + idx];
-        ar = fma(rb.x, c.x, fma(rb.y, c.y, ar));
-        ai = fma(rb.x, c.y, fma(-rb.y, c.x, ai));
-      }
-    }
-    double2 &o = coef_bar[((size_t)k * nb_max + n) * npw_max + i];
-    o.x += ar;
-    o.y += ai;
-  }
+// Pair-density adjoint by dense products, per k of the transition range and
+// block of response vectors G_g (g0 <= g < g0 + gB):
+//   S[g][m][n] = rhobar_(k,n,m)(G_g), zero where (k, n, m) is not in the range,
+//   out: Mt[g][n][j] = sum_m conj(S[g][m][n]) c_{m k'}(j)           (zgemm N, C)
+//        coef_bar(k, n)(G1) += sum_g Mt[g][n][L_k'(G1 + G_g + G_s)]
+//   in:  Nt[g][m][i] = sum_n c_{n k}(i) S[g][m][n]                   (zgemm N, N)
+//        coef_bar(k', m)(G2) += sum_g Nt[g][m][L_k(G2 - G_g - G_s)]
+// which is
+//   coef_bar(k,n)(G1) += sum_t sum_G conj(rhobar_t(G)) c_{m_t,k'}(G1 + G + G_s),
+//   coef_bar(k',m)(G2) += sum_{n: (k,n,m)} sum_G rhobar_t(G) c_{n,k}(G2 - G - G_s)
+// with the products on the MFMA (rocBLAS) and one lookup per (band, plane
+// wave, G) instead of one per (transition, plane wave, G).
+
+// S entries of the transitions [t0, t1) of one k (value = rhobar, or zero to
+// clear them again after use).
+__global__ void k_pdv_scatter(const int *tn, const int *tm, long long t0, long long t1,
+                              long long t_lo, const double2 *rhobar, int ld, int g0, int n_g,
+                              int nb_max, bool clear, double2 *S) {
+  const long long t = t0 + blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (t >= t1 || g0 + g >= n_g) return;
+  S[(size_t)g * nb_max * nb_max + (size_t)tm[t] * nb_max + tn[t]] =
+      clear ? make_double2(0.0, 0.0) : rhobar[(size_t)(t - t_lo) * ld + g0 + g];
 }
 
-// Pair-density adjoint, incoming side:
-//   coef_bar(k',m)(G2) += sum_{n: (k,n,m) in T} sum_G rhobar_t(G) c_{n,k}(G2 - G - G_s)
-// One workgroup per (k, m) with k' = k + q; the transition of each n is
-// found first by binary search of m in row (k, n).
+// coef_bar(k, b)(p) += sum_g X[g][b][lut(miller_k(p) + sg G_g + G_s)] for the
+// bands b < nb of k and plane waves p < npw of k (sg = +1: outgoing side with
+// the lookup of k'; sg = -1: incoming side, G_s negated by the caller, with
+// the lookup of k).
 __global__ void __launch_bounds__(256)
-    k_pd_vjp_in(const double2 *coef, const int *miller, const int *npw, const int *nb, int nb_max,
-                int npw_max, const int *tm, const long long *rowbeg, const long long *rowend,
-                const int *kpmap, const int *gsmap, const int *gbasis, int n_g, int ld,
-                const int *lut, long box, int M0, int M1, int M2, long long t_lo,
-                const double2 *rhobar, double2 *coef_bar) {
-  extern __shared__ long long tof[];  // [nb_max] transition of (k, n, m) or -1
-  const int m = blockIdx.x, k = blockIdx.y;
-  const int kp = kpmap[k];
-  if (m >= nb[kp]) return;
-  const int nbk = nb[k];
-  for (int n = threadIdx.x; n < nbk; n += 256) {
-    long long lo = rowbeg[(size_t)k * nb_max + n];
-    const long long end = rowend[(size_t)k * nb_max + n];
-    long long hi = end;
-    while (lo < hi) {
-      const long long mid = (lo + hi) >> 1;
-      if (tm[mid] < m)
-        lo = mid + 1;
-      else
-        hi = mid;
-    }
-    tof[n] = (lo < end && tm[lo] == m) ? lo : -1;
-  }
-  __syncthreads();
-  const int gs0 = gsmap[3 * k], gs1 = gsmap[3 * k + 1], gs2 = gsmap[3 * k + 2];
+    k_pdv_gather(const double2 *X, int npw_max, int nb_max, int gB, int g0, const int *gbasis,
+                 int sg, const int *mk, int npw, int nb, int s0, int s1, int s2, const int *lut,
+                 int M0, int M1, int M2, double2 *cbar) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+  if (p >= npw || b >= nb) return;
   const int W1 = 2 * M1 + 1, W2 = 2 * M2 + 1;
-  const int *lutk = lut + (size_t)k * box;
-  const int *mj = miller + (size_t)kp * npw_max * 3;
-  const double2 *ck = coef + (size_t)k * nb_max * npw_max;
-  for (int i = threadIdx.x; i < npw[kp]; i += 256) {
-    double ar = 0.0, ai = 0.0;
-    for (int g = 0; g < n_g; ++g) {
-      const int x0 = mj[3 * i] - gbasis[3 * g] - gs0 + M0;
-      const int x1 = mj[3 * i + 1] - gbasis[3 * g + 1] - gs1 + M1;
-      const int x2 = mj[3 * i + 2] - gbasis[3 * g + 2] - gs2 + M2;
-      if (x0 < 0 || x0 > 2 * M0 || x1 < 0 || x1 >= W1 || x2 < 0 || x2 >= W2) continue;
-      const int idx = lutk[((long)x0 * W1 + x1) * W2 + x2];
-      if (idx < 0) continue;
-      for (int n = 0; n < nbk; ++n) {
-        const long long t = tof[n];
-        if (t < 0) continue;
-        const double2 rb = rhobar[(size_t)(t - t_lo) * ld + g];
-        const double2 c = ck[(size_t)n * npw_max + idx];
-        ar = fma(rb.x, c.x, fma(-rb.y, c.y, ar));
-        ai = fma(rb.x, c.y, fma(rb.y, c.x, ai));
-      }
-    }
-    double2 &o = coef_bar[((size_t)kp * nb_max + m) * npw_max + i];
-    o.x += ar;
-    o.y += ai;
+  double ar = 0.0, ai = 0.0;
+  for (int g = 0; g < gB; ++g) {
+    const int *G = gbasis + 3 * (g0 + g);
+    const int x0 = mk[3 * p] + sg * G[0] + s0 + M0;
+    const int x1 = mk[3 * p + 1] + sg * G[1] + s1 + M1;
+    const int x2 = mk[3 * p + 2] + sg * G[2] + s2 + M2;
+    if (x0 < 0 || x0 > 2 * M0 || x1 < 0 || x1 >= W1 || x2 < 0 || x2 >= W2) continue;
+    const int j = lut[((long)x0 * W1 + x1) * W2 + x2];
+    if (j < 0) continue;
+    const double2 v = X[((size_t)g * nb_max + b) * npw_max + j];
+    ar += v.x;
+    ai += v.y;
   }
+  double2 &o = cbar[(size_t)b * npw_max + p];
+  o.x += ar;
+  o.y += ai;
 }
 
 // S_i = -Im chi_{j(i)} g_i(beta): j(i) = i, g = 1/(pi n (1 - e^{-beta w})) for
@@ -660,26 +617,88 @@ int tdx_pair_density_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
               "null argument");
   TDX_REQUIRE(n_g > 0 && t_begin >= 0 && t_begin <= t_end && t_end <= tl->capacity,
               TDX_ERR_SHAPE, "bad sizes");
-  TDX_REQUIRE((size_t)st->nb_max * sizeof(long long) <= 64 * 1024, TDX_ERR_SHAPE,
-              "band capacity %d too large for the adjoint kernel", st->nb_max);
   TDX_TRY(check_device(ctx));
   if (t_end == t_begin) return TDX_OK;
   hipStream_t s = as_stream(stream);
   QTables q;
   TDX_TRY(q_tables(ctx, st, qj, tl, t_begin, t_end, true, s, &q));
   const int M0 = st->mmax[0], M1 = st->mmax[1], M2 = st->mmax[2];
-  dim3 grid(st->nb_max, st->n_k);
-  hipLaunchKernelGGL(k_pd_vjp_out, grid, dim3(256), 0, s, (const double2 *)st->coef, st->miller,
-                     st->npw, st->nb_max, st->npw_max, tl->m, q.rowbeg, q.rowend, q.kp, q.gs,
-                     gbasis, n_g, ld_of(n_g), q.lut, q.box, M0, M1, M2, (long long)t_begin,
-                     (const double2 *)rho_bar, (double2 *)coef_bar);
+  const int nk = st->n_k, nb_max = st->nb_max, npw_max = st->npw_max, ld = ld_of(n_g);
+  // host copies of the per-k sizes, the k -> k' map and the list's k offsets
+  std::vector<long long> koff(nk + 1);
+  std::vector<int> nbh(nk), npwh(nk), kp, gs;
+  TDX_HIP(hipMemcpyAsync(koff.data(), tl->k_offsets, sizeof(long long) * (nk + 1),
+                         hipMemcpyDeviceToHost, s));
+  TDX_HIP(hipMemcpyAsync(nbh.data(), st->nb, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
+  TDX_HIP(hipMemcpyAsync(npwh.data(), st->npw, sizeof(int) * nk, hipMemcpyDeviceToHost, s));
+  TDX_HIP(hipStreamSynchronize(s));
+  kq_map(st->kgrid, qj, &kp, &gs);
+  // response vectors per block: the products of a block take at most 2 GiB
+  const size_t per_g = (size_t)nb_max * npw_max * sizeof(double2);
+  const int gB = (int)std::max<size_t>(1, std::min<size_t>(n_g, ((size_t)2 << 30) / per_g));
+  const size_t s_bytes = ((size_t)gB * nb_max * nb_max * sizeof(double2) + 255) / 256 * 256;
+  void *w;
+  TDX_TRY(ws_get(ctx, WS_ADJ2, s_bytes + (size_t)gB * per_g, &w));
+  double2 *S = (double2 *)w;
+  double2 *X = (double2 *)((char *)w + s_bytes);
+  const long long ns = (long long)gB * nb_max * nb_max;
+  hipLaunchKernelGGL(k_fill<double2>, dim3((unsigned)std::min<long long>((ns + 255) / 256, 65535)),
+                     dim3(256), 0, s, S, ns, make_double2(0.0, 0.0));
   TDX_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_pd_vjp_in, grid, dim3(256), sizeof(long long) * st->nb_max, s,
-                     (const double2 *)st->coef, st->miller, st->npw, st->nb, st->nb_max,
-                     st->npw_max, tl->m, q.rowbeg, q.rowend, q.kp, q.gs, gbasis, n_g, ld_of(n_g),
-                     q.lut, q.box, M0, M1, M2, (long long)t_begin, (const double2 *)rho_bar,
-                     (double2 *)coef_bar);
-  TDX_HIP(hipGetLastError());
+  TDX_REQUIRE(rocblas_set_stream(ctx->blas, s) == rocblas_status_success, TDX_ERR_HIP,
+              "rocblas_set_stream failed");
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  const double2 *coef = (const double2 *)st->coef;
+  double2 *cbar = (double2 *)coef_bar;
+  for (int k = 0; k < nk; ++k) {
+    const long long t0 = std::max<long long>(koff[k], t_begin);
+    const long long t1 = std::min<long long>(koff[k + 1], t_end);
+    if (t1 <= t0) continue;
+    const int k2 = kp[k];
+    const int nb1 = nbh[k], nb2 = nbh[k2], np1 = npwh[k], np2 = npwh[k2];
+    const double2 *c1 = coef + (size_t)k * nb_max * npw_max;
+    const double2 *c2 = coef + (size_t)k2 * nb_max * npw_max;
+    const dim3 sgrid((unsigned)((t1 - t0 + 255) / 256), gB);
+    for (int g0 = 0; g0 < n_g; g0 += gB) {
+      const int gb = std::min(gB, n_g - g0);
+      hipLaunchKernelGGL(k_pdv_scatter, sgrid, dim3(256), 0, s, tl->n, tl->m, t0, t1,
+                         (long long)t_begin, (const double2 *)rho_bar, ld, g0, n_g, nb_max, false,
+                         S);
+      TDX_HIP(hipGetLastError());
+      // outgoing side: Mt = c_k'^T conj(S)^T, gathered into coef_bar(k, n)
+      rocblas_status rs = rocblas_zgemm_strided_batched(
+          ctx->blas, rocblas_operation_none, rocblas_operation_conjugate_transpose, np2, nb1, nb2,
+          &one, (const rocblas_double_complex *)c2, npw_max, 0,
+          (const rocblas_double_complex *)S, nb_max, (rocblas_stride)nb_max * nb_max, &zero,
+          (rocblas_double_complex *)X, npw_max, (rocblas_stride)nb_max * npw_max, gb);
+      TDX_REQUIRE(rs == rocblas_status_success, TDX_ERR_HIP, "rocblas_zgemm failed (%d)",
+                  (int)rs);
+      hipLaunchKernelGGL(k_pdv_gather, dim3((np1 + 255) / 256, nb1), dim3(256), 0, s, X, npw_max,
+                         nb_max, gb, g0, gbasis, 1, st->miller + (size_t)k * npw_max * 3, np1,
+                         nb1, gs[3 * k], gs[3 * k + 1], gs[3 * k + 2], q.lut + (size_t)k2 * q.box,
+                         M0, M1, M2, cbar + (size_t)k * nb_max * npw_max);
+      TDX_HIP(hipGetLastError());
+      // incoming side: Nt = c_k^T S, gathered into coef_bar(k', m)
+      rs = rocblas_zgemm_strided_batched(
+          ctx->blas, rocblas_operation_none, rocblas_operation_none, np1, nb2, nb1, &one,
+          (const rocblas_double_complex *)c1, npw_max, 0, (const rocblas_double_complex *)S,
+          nb_max, (rocblas_stride)nb_max * nb_max, &zero, (rocblas_double_complex *)X, npw_max,
+          (rocblas_stride)nb_max * npw_max, gb);
+      TDX_REQUIRE(rs == rocblas_status_success, TDX_ERR_HIP, "rocblas_zgemm failed (%d)",
+                  (int)rs);
+      hipLaunchKernelGGL(k_pdv_gather, dim3((np2 + 255) / 256, nb2), dim3(256), 0, s, X, npw_max,
+                         nb_max, gb, g0, gbasis, -1, st->miller + (size_t)k2 * npw_max * 3, np2,
+                         nb2, -gs[3 * k], -gs[3 * k + 1], -gs[3 * k + 2],
+                         q.lut + (size_t)k * q.box, M0, M1, M2,
+                         cbar + (size_t)k2 * nb_max * npw_max);
+      TDX_HIP(hipGetLastError());
+      // S back to zero for the next block or k
+      hipLaunchKernelGGL(k_pdv_scatter, sgrid, dim3(256), 0, s, tl->n, tl->m, t0, t1,
+                         (long long)t_begin, (const double2 *)rho_bar, ld, g0, n_g, nb_max, true,
+                         S);
+      TDX_HIP(hipGetLastError());
+    }
+  }
   return TDX_OK;
 }
 

@@ -68,12 +68,24 @@ class ChainRunner:
             self._st_v = key
         return self._st
 
-    def blocks(self, n_trans: int, n_g: int):
+    def blocks(self, n_trans: int, n_g: int, k_offsets=None):
         """Transition ranges of the reverse sweep: each holds at most
-        block_bytes of FP64 pair densities plus their cotangents."""
+        block_bytes of FP64 pair densities plus their cotangents, and ends
+        at a k boundary where one fits (the orbital adjoint's cost per k does
+        not depend on how many of the k's transitions a range holds)."""
         ld = (n_g + 15) // 16 * 16
         size = max(64, self.block_bytes // (2 * 16 * ld))
-        return [(b, min(n_trans, b + size)) for b in range(0, n_trans, size)]
+        if k_offsets is None:
+            return [(b, min(n_trans, b + size)) for b in range(0, n_trans, size)]
+        ko = [int(x) for x in k_offsets]
+        out, b = [], 0
+        while b < n_trans:
+            e = min(n_trans, b + size)
+            cut = max((x for x in ko if b < x <= e), default=e)
+            e = cut if e < n_trans else e
+            out.append((b, e))
+            b = e
+        return out
 
     def forward(self, T: float, eta: float, v: Optional[np.ndarray]) -> torch.Tensor:
         w = self.w if v is None else _with_shell_values(self.w, v)
@@ -111,7 +123,7 @@ class ChainRunner:
             n_g = gb.shape[0]
             u, v = dyson_vjp(ctx, q["chi0"], q["K"], q["g0"], chi00_bar[iq].contiguous())
             w_bar = torch.empty((max(len(tr), 1), 3), dtype=torch.float64, device=dev)
-            for b0, b1 in self.blocks(len(tr), n_g):
+            for b0, b1 in self.blocks(len(tr), n_g, tr.k_offsets.cpu().numpy()):
                 P = pair_density_range(ctx, st, q["qj"], tr, gb, b0, b1, "fp64")
                 _, rho_bar = chi0_vjp(ctx, tr, P, n_g, q["omega"], sv["eta"], sv["pref"], u, v,
                                       want_rho=need_v, t_begin=b0, t_end=b1,
