@@ -26,8 +26,13 @@ are different algorithms.  For a direction (dT, deta, dv):
   weights       w_t = df_t / D_t, D_t = w - Delta_t + i eta:
                 dw_t = d df_t / D_t + df_t (d Delta_t - i d eta) / D_t^2.
   chi0          d chi0 = pref sum_t [dw_t rho rho^H + w_t (d rho rho^H + rho d rho^H)].
-  Dyson         chi = A^{-1} chi0, A = 1 - chi0 K, K fixed (RPA):
-                d chi = A^{-1} d chi0 (1 + K chi).
+  kernel        RPA: K = v(q + G) delta_GG' has no tangent.  ALDA: K adds
+                f_xc(n)(G - G') with n the density of the states on the
+                real-space grid; n is linear in f and sesquilinear in c, so
+                dn = n(f = df) + [n(c + dc) - n(c - dc)] / 2 at fixed f,
+                and dK_xc is the same transform of f_xc'(n) dn.
+  Dyson         chi = A^{-1} chi0, A = 1 - chi0 K:
+                d chi = A^{-1} [d chi0 (1 + K chi) + chi0 dK chi].
   DSF           S = -Im chi_00 g(beta, w), beta = 1/T (w = 0 from the next
                 point, as in the forward path).
   ITCF          F(tau_j) = sum_i c_i S_i (e^{-tau_j w_i} + e^{-(beta - tau_j) w_i})
@@ -44,6 +49,7 @@ from .lattice import reciprocal, volume, mp_kpoints, gsphere, response_basis
 from .states import (DEGEN_TOL, States, fermi, find_mu, hamiltonian,
                      potential_fourier, snap_band_count)
 from .response import pair_densities, transitions, trapezoid_weights
+from .xc import density_on_grid, fxc_alda, fxc_alda_deriv, kernel_from_real
 
 
 def with_shell_values(w, v):
@@ -108,11 +114,11 @@ def itcf_tangent(w, iq, T, eta, dT=0.0, deta=0.0, dv=None, omegas=None):
     """F(q_iq, tau) and its directional derivative along (dT, deta, dv).
 
     States are built at T with the workload's shell values; tau runs over
-    the workload's grid scaled to beta = 1/T.  RPA kernel only.
+    the workload's grid scaled to beta = 1/T.  RPA or ALDA kernel.
     Returns (F, dF, taus).
     """
-    if w.xc != "rpa":
-        raise ValueError("tangents are defined for the RPA kernel")
+    if w.xc not in ("rpa", "alda"):
+        raise ValueError(f"no tangent for the kernel {w.xc!r}")
     dv = np.zeros(len(w.potential.shell_v)) if dv is None else np.asarray(dv, float)
     st, deps, dcoef, docc = states_and_tangents(w, T, dT, dv)
     qj = tuple(w.qs[iq])
@@ -136,6 +142,15 @@ def itcf_tangent(w, iq, T, eta, dT=0.0, deta=0.0, dv=None, omegas=None):
     pref = 2.0 / (st.n_k * st.omega)
     p = (qred + basis) @ st.B
     K = np.diag(4 * math.pi / np.einsum("ij,ij->i", p, p)).astype(np.complex128)
+    dK = np.zeros_like(K)
+    if w.xc == "alda":
+        grid = w.dens_grid
+        nr = density_on_grid(st, grid)
+        dn = (density_on_grid(dataclasses.replace(st, occ=docc), grid) +
+              0.5 * (density_on_grid(_with_coef(st, plus), grid) -
+                     density_on_grid(_with_coef(st, minus), grid)))
+        K = K + kernel_from_real(fxc_alda(nr), grid, basis)
+        dK = kernel_from_real(fxc_alda_deriv(nr) * dn, grid, basis)
     I = np.eye(len(basis))
     n = w.n_electrons / st.omega
     chi00 = np.empty(len(om), complex)
@@ -151,7 +166,7 @@ def itcf_tangent(w, iq, T, eta, dT=0.0, deta=0.0, dv=None, omegas=None):
         A = I - c0 @ K
         chi = np.linalg.solve(A, c0)
         chi00[i] = chi[iG0, iG0]
-        dchi00[i] = np.linalg.solve(A, dc0 @ (I + K @ chi))[iG0, iG0]
+        dchi00[i] = np.linalg.solve(A, dc0 @ (I + K @ chi) + c0 @ dK @ chi)[iG0, iG0]
     S = np.empty(len(om))
     dS = np.empty(len(om))
     for i, wv in enumerate(om):

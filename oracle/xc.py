@@ -137,6 +137,27 @@ def fxc_alda(n):
     return fx + fc
 
 
+def fxc_deriv_parts(n, h=1e-30):
+    """(d f_x/dn, d f_c/dn), the third derivatives of n eps_x and n eps_c:
+    the hyper-dual evaluation of fxc_parts at the complex point n (1 + i h),
+    whose imaginary part over h n is the derivative up to O(h^2) with no
+    cancellation (the complex-step derivative, Squire and Trapp, SIAM Rev.
+    40, 110 (1998)); the second derivative stays exact in the hyper-dual
+    parts."""
+    n = np.asarray(n, dtype=np.float64)
+    z = n * (1.0 + 1j * h)
+    x = HyperDual(z, np.ones_like(z), np.ones_like(z), np.zeros_like(z))
+    fx, fc = (x * _ex(x)).d, (x * _ec(x)).d
+    return fx.imag / (h * n), fc.imag / (h * n)
+
+
+def fxc_alda_deriv(n):
+    """d f_xc / dn = d^3 (n eps_xc) / dn^3 (the ALDA kernel's response to
+    the density, needed by its tangent)."""
+    dx, dc = fxc_deriv_parts(n)
+    return dx + dc
+
+
 def density_on_grid(st, grid):
     """n(r_j) on the real-space grid (bohr^-3)."""
     N = np.asarray(grid)
@@ -156,12 +177,17 @@ def density_on_grid(st, grid):
     return rho * 2.0 / (st.n_k * st.omega)
 
 
-def fxc_matrix(st, grid, basis):
-    """K_xc[G, G'] = f_xc(G - G')."""
+def kernel_from_real(fr, grid, basis):
+    """M[G, G'] = g(G - G') for a real-space function fr on the grid, with
+    g(G) = (1/N_r) sum_j fr(r_j) exp(-i G.r_j)."""
     N = np.asarray(grid)
     Nr = int(np.prod(N))
-    fr = fxc_alda(density_on_grid(st, grid))
     fg = np.fft.fftn(fr) / Nr
     d = basis[:, None, :] - basis[None, :, :]
     d = np.mod(d, N)
     return fg[d[..., 0], d[..., 1], d[..., 2]]
+
+
+def fxc_matrix(st, grid, basis):
+    """K_xc[G, G'] = f_xc(G - G')."""
+    return kernel_from_real(fxc_alda(density_on_grid(st, grid)), grid, basis)

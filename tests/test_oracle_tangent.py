@@ -58,3 +58,31 @@ def test_tangent_is_linear_in_the_direction():
     _, g3, _ = tangent.itcf_tangent(w, 0, T, eta, 2 * d1[0] - d2[0], 2 * d1[1] - d2[1],
                                     2 * d1[2] - d2[2])
     np.testing.assert_allclose(g3, 2 * g1 - g2, rtol=1e-9, atol=1e-12 * np.max(np.abs(g1)))
+
+
+def _w_alda():
+    return _w().with_(xc="alda", dens_grid=(12, 12, 12))
+
+
+@pytest.mark.parametrize("direction", ["T", "v"])
+def test_alda_tangent_matches_central_differences(direction):
+    """With the ALDA kernel the density of the states moves with T (through
+    the occupations) and with v (through orbitals and occupations), and K
+    with it: the tangent's dK = [f_xc'(n) dn](G - G') against central
+    differences of the forward pipeline, which rebuilds n and K."""
+    w = _w_alda()
+    T, eta = w.temperatures[0], w.eta
+    v = np.asarray(w.potential.shell_v)
+    rng = np.random.default_rng(13)
+    dT = 1.0 if direction == "T" else 0.0
+    dv = rng.standard_normal(len(v)) * np.abs(v) if direction == "v" else np.zeros(len(v))
+    F, dF, _ = tangent.itcf_tangent(w, 0, T, eta, dT, 0.0, dv)
+    F0 = tangent.itcf_value(w, 0, T, eta, v)
+    np.testing.assert_allclose(F, F0, rtol=1e-12, atol=0)
+    fd = _fd(w, T, eta, v, dT, 0.0, dv)
+    err = np.max(np.abs(dF - fd)) / np.max(np.abs(fd))
+    assert err < 1e-6, err
+    # the kernel's share of the tangent is not negligible: the RPA tangent
+    # along the same direction differs
+    _, dF_rpa, _ = tangent.itcf_tangent(_w(), 0, T, eta, dT, 0.0, dv)
+    assert np.max(np.abs(dF - dF_rpa)) > 1e-3 * np.max(np.abs(dF))

@@ -110,3 +110,26 @@ def test_fxc_matrix_is_hermitian_and_matches_direct_dft():
     d = basis[3] - basis[7]
     direct = np.mean(f.reshape(-1) * np.exp(-2j * math.pi * (j @ (d / N))))
     assert abs(direct - K[3, 7]) < 1e-13 * np.abs(K).max()
+
+
+@pytest.mark.parametrize("n", [1e-4, 7.0826e-3, 0.027, 0.5])
+def test_p11_exchange_kernel_derivative_closed_form(n):
+    """d f_x/dn of Slater exchange: (2/9)(3/pi)^(1/3) n^(-5/3)."""
+    dx, _ = xc.fxc_deriv_parts(n)
+    ref = (2.0 / 9.0) * (3.0 / math.pi) ** (1.0 / 3.0) * n ** (-5.0 / 3.0)
+    assert abs(dx - ref) < 1e-13 * ref
+
+
+@pytest.mark.parametrize("n", [1e-3, 7.0826e-3, 0.03, 0.3])
+def test_fxc_derivative_against_finite_differences(n):
+    """The complex-step third derivative against a fourth-order central
+    difference of the hyper-dual second derivative."""
+    h = 1e-3 * n
+    f = xc.fxc_alda
+    fd4 = (f(n - 2 * h) - 8 * f(n - h) + 8 * f(n + h) - f(n + 2 * h)) / (12 * h)
+    got = xc.fxc_alda_deriv(n)
+    assert abs(fd4 - got) < 1e-7 * abs(got)
+    _, dc = xc.fxc_deriv_parts(n)
+    fc = lambda x: xc.fxc_parts(x)[1]
+    fd4c = (fc(n - 2 * h) - 8 * fc(n - h) + 8 * fc(n + h) - fc(n + 2 * h)) / (12 * h)
+    assert abs(fd4c - dc) < 1e-6 * abs(dc)
