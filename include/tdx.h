@@ -616,8 +616,9 @@ int tdx_kg_conductivity(tdx_ctx *ctx, const tdx_states *st, const tdx_translist 
  *   itcf_vjp -> dsf_vjp -> dyson_vjp -> chi0_vjp -> weights_vjp
  *   -> occupations_vjp, pair_density_vjp (per q) -> potential_vjp (once).
  * A real cotangent xbar means dL = sum xbar dx; a complex one zbar means
- * dL = Re sum conj(zbar) dz.  The kernel K is held fixed (RPA: it does not
- * depend on T, eta or v).  Temperature enters through beta = 1/T in S and
+ * dL = Re sum conj(zbar) dz.  The RPA kernel depends on none of T, eta,
+ * v; the ALDA kernel's dependence through the density has three calls of
+ * its own (after tdx_potential_vjp below).  Temperature enters through beta = 1/T in S and
  * F (the caller chains beta_bar and tau_bar) and through the occupations
  * (occupations_vjp).  Calls that accumulate ("+=") leave zeroing to the
  * caller so that several q can share one set of state cotangents. */
@@ -703,6 +704,43 @@ int tdx_pair_density_vjp(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
 int tdx_potential_vjp(tdx_ctx *ctx, const tdx_model *md, const tdx_states *st,
                       const double *eps_bar, const double *coef_bar, double *v_bar,
                       tdx_stream stream);
+
+/* The adiabatic kernel's share of the reverse pass (ALDA, Sec. A.1): K
+ * depends on the density of the states, n(r_j) =
+ * 2/(N_k Omega) sum_kn f_nk |u_nk(r_j)|^2, through
+ * K[a][b] = 4 pi/|q+G_a|^2 delta_ab + (1/N_r) sum_j f_xc(n(r_j)) e^{-i(G_a-G_b).r_j},
+ * and n on the occupations (so on T) and the orbitals (so on v).  Three
+ * calls, per q then once:
+ *   dyson_kernel_vjp -> kernel_matrix_vjp (per q, accumulating fxc_bar on
+ *   the grid) -> density_vjp (once: occ_bar and coef_bar, which then join
+ *   the RPA chain's occupations_vjp and potential_vjp). */
+
+/* K_bar += sum_w p_w x_w^H with x_w = A^{-1} chi0 e and p_w = chi0(w)^H u_w,
+ * u_w = chi00_bar conj(A^{-T} e) (the cotangent of K through chi00 =
+ * [A^{-1} chi0 e]_{g0}, A = 1 - chi0 K).  K_bar: device complex128
+ * [n_g][n_g] (+=).  Workspace from the context; synchronises; NUMERIC if a
+ * Dyson matrix is singular. */
+int tdx_dyson_kernel_vjp(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w,
+                         int i_g0, const double *chi00_bar, double *K_bar, tdx_stream stream);
+
+/* fxc_bar[j] += (1/N_r) Re sum_ab conj(K_bar[a][b]) e^{-i(G_a - G_b).r_j}: the
+ * cotangent of f_xc(r_j) from the ALDA part of K (the Coulomb part depends
+ * on no parameter).  gbasis: device int [n_g][3] (the basis K was built on);
+ * dens_grid: host [3], the grid of tdx_xc_kernel_grid; fxc_bar: device
+ * [N_r] (+=), grid order (j_0 N_1 + j_1) N_2 + j_2.  Synchronises. */
+int tdx_kernel_matrix_vjp(tdx_ctx *ctx, const tdx_states *st, const int *gbasis, int n_g,
+                          const int dens_grid[3], const double *K_bar, double *fxc_bar,
+                          tdx_stream stream);
+
+/* From fxc_bar: nbar = fxc_bar f_xc'(n) (f_xc' = d^3(n eps_xc)/dn^3), then
+ *   occ_bar[k][n] += 2/(N_k Omega) sum_j nbar_j |u_nk(r_j)|^2,
+ *   coef_bar[k][n](G) += 2 (2/(N_k Omega)) f_nk sum_j nbar_j u_nk(r_j) e^{-iG.r_j}
+ * over the bands the density sums (f >= 1e-20).  occ_bar: device
+ * [n_k][nb_max] (+=); coef_bar: device complex128 [n_k][nb_max][npw_max]
+ * (+=) or null (temperature and broadening only).  Synchronises. */
+int tdx_density_vjp(tdx_ctx *ctx, const tdx_states *st, const int dens_grid[3],
+                    const double *fxc_bar, double *occ_bar, double *coef_bar,
+                    tdx_stream stream);
 
 #ifdef __cplusplus
 }

@@ -200,6 +200,12 @@ _occ_vjp = _sig("tdx_occupations_vjp", [C.c_void_p, C.POINTER(StatesC), C.c_void
 _pair_vjp = _sig("tdx_pair_density_vjp", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3,
                                           C.POINTER(TransC), C.c_int64, C.c_int64, C.c_void_p,
                                           C.c_int, C.c_void_p, C.c_void_p, C.c_void_p])
+_dyson_k_vjp = _sig("tdx_dyson_kernel_vjp", [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                           C.c_int, C.c_void_p, C.c_void_p, C.c_void_p])
+_kmat_vjp = _sig("tdx_kernel_matrix_vjp", [C.c_void_p, C.POINTER(StatesC), C.c_void_p, C.c_int,
+                                           C.c_int * 3, C.c_void_p, C.c_void_p, C.c_void_p])
+_dens_vjp = _sig("tdx_density_vjp", [C.c_void_p, C.POINTER(StatesC), C.c_int * 3, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p])
 _pot_vjp = _sig("tdx_potential_vjp", [C.c_void_p, C.POINTER(Model), C.POINTER(StatesC),
                                       C.c_void_p, C.c_void_p, c_dbl_p, C.c_void_p])
 
@@ -216,7 +222,8 @@ EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_chi0_set_slice_length", "tdx_autotune_chi0", "tdx_tune_save",
             "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async", "tdx_itcf_vjp",
             "tdx_dsf_vjp", "tdx_dyson_vjp", "tdx_chi0_vjp", "tdx_weights_vjp",
-            "tdx_occupations_vjp", "tdx_pair_density_vjp", "tdx_potential_vjp"]
+            "tdx_occupations_vjp", "tdx_pair_density_vjp", "tdx_potential_vjp",
+            "tdx_dyson_kernel_vjp", "tdx_kernel_matrix_vjp", "tdx_density_vjp"]
 
 
 def check(code):
@@ -855,6 +862,33 @@ def potential_vjp(ctx: Context, w, st: States, eps_bar: torch.Tensor, coef_bar: 
     check(_pot_vjp(ctx.handle, C.byref(m), C.byref(st.c), _ptr(eps_bar), _ptr(coef_bar),
                    out.ctypes.data_as(c_dbl_p), _stream(stream)))
     return out
+
+
+def dyson_kernel_vjp(ctx: Context, chi0_t: torch.Tensor, K: torch.Tensor, i_g0: int,
+                     chi00_bar: torch.Tensor, K_bar: Optional[torch.Tensor] = None,
+                     stream=None) -> torch.Tensor:
+    """K_bar (+=, complex128 [n_g][n_g]) of chi00 = [(1 - chi0 K)^{-1} chi0]_{g0 g0}."""
+    n_w, n_g, _ = chi0_t.shape
+    if K_bar is None:
+        K_bar = torch.zeros((n_g, n_g), dtype=torch.complex128, device=chi0_t.device)
+    check(_dyson_k_vjp(ctx.handle, _ptr(chi0_t), _ptr(K), n_g, n_w, i_g0,
+                       _ptr(chi00_bar.contiguous()), _ptr(K_bar), _stream(stream)))
+    return K_bar
+
+
+def kernel_matrix_vjp(ctx: Context, st: States, gbasis: torch.Tensor, dens_grid,
+                      K_bar: torch.Tensor, fxc_bar: torch.Tensor, stream=None):
+    """fxc_bar (+=, float64 [N_r], grid order) from the ALDA part of K."""
+    check(_kmat_vjp(ctx.handle, C.byref(st.c), _ptr(gbasis), gbasis.shape[0],
+                    (C.c_int * 3)(*dens_grid), _ptr(K_bar), _ptr(fxc_bar), _stream(stream)))
+
+
+def density_vjp(ctx: Context, st: States, dens_grid, fxc_bar: torch.Tensor,
+                occ_bar: torch.Tensor, coef_bar: Optional[torch.Tensor] = None, stream=None):
+    """occ_bar (+=) and coef_bar (+=, optional) through the density from fxc_bar."""
+    check(_dens_vjp(ctx.handle, C.byref(st.c), (C.c_int * 3)(*dens_grid), _ptr(fxc_bar),
+                    _ptr(occ_bar), None if coef_bar is None else _ptr(coef_bar),
+                    _stream(stream)))
 
 
 # --------------------------------------------------------------- pipeline

@@ -146,6 +146,41 @@ __global__ void k_fxc_real(const double *dens, int nk, int Nr, double scale, dou
   fx[j] = make_double2(fxv + fcv, 0.0);
 }
 
+// Third derivative of the PW92 correlation in rs (for the kernel's density
+// response): with eps = g L(Q), g = -2A(1 + a1 rs) linear in rs,
+//   d3 eps = 3 g' L2 + g L3,
+//   L3 = -Q3/D + 3 Q1 Q2 (1 + 2Q)/D^2 + 2 Q1^3/D^2 - 2 Q1^3 (1 + 2Q)^2/D^3,
+// D = Q(1 + Q), Qj and Lj the j-th derivatives in rs.
+__device__ double pw92_e3(double rs) {
+  const double A = 0.031091, a1 = 0.21370;
+  const double b1 = 7.5957, b2 = 3.5876, b3 = 1.6382, b4 = 0.49294;
+  const double s = sqrt(rs);
+  const double Q = 2 * A * (b1 * s + b2 * rs + b3 * rs * s + b4 * rs * rs);
+  const double Q1 = 2 * A * (0.5 * b1 / s + b2 + 1.5 * b3 * s + 2 * b4 * rs);
+  const double Q2 = 2 * A * (-0.25 * b1 / (rs * s) + 0.75 * b3 / s + 2 * b4);
+  const double Q3 = 2 * A * (0.375 * b1 / (rs * rs * s) - 0.375 * b3 / (rs * s));
+  const double D = Q + Q * Q, T = 1 + 2 * Q;
+  const double L2 = -Q2 / D + Q1 * Q1 * T / (D * D);
+  const double L3 = -Q3 / D + 3 * Q1 * Q2 * T / (D * D) + 2 * Q1 * Q1 * Q1 / (D * D) -
+                    2 * Q1 * Q1 * Q1 * T * T / (D * D * D);
+  const double g = -2 * A * (1 + a1 * rs), g1 = -2 * A * a1;
+  return 3 * g1 * L2 + g * L3;
+}
+
+// d f_xc / dn = d^3(n eps_xc)/dn^3: exchange (2/9)(3/pi)^(1/3) n^(-5/3);
+// correlation, with f_c = (rs^2 e2 - 2 rs e1)/(9n) and d rs/dn = -rs/(3n),
+//   d f_c/dn = -(rs^3 e3/3 + rs^2 e2 - (8/3) rs e1) / (9 n^2).
+__device__ double fxc_deriv(double n) {
+  const double dx = (2.0 / 9.0) * cbrt(3.0 / M_PI) * pow(n, -5.0 / 3.0);
+  const double rs = cbrt(3.0 / (4.0 * M_PI * n));
+  double e, e1, e2;
+  pw92(rs, &e, &e1, &e2);
+  const double e3 = pw92_e3(rs);
+  const double dc =
+      -(rs * rs * rs * e3 / 3.0 + rs * rs * e2 - (8.0 / 3.0) * rs * e1) / (9.0 * n * n);
+  return dx + dc;
+}
+
 // Forward transform of f_xc on the box (one workgroup), scaled by 1/N_r.
 __global__ void __launch_bounds__(256)
     k_fxc_forward(double2 *fx, int N0, int N1, int N2) {
@@ -370,7 +405,7 @@ __device__ inline void block_dot(double re, double im, double *sr, double *si) {
 
 __global__ void __launch_bounds__(kLuThreads)
     k_lu_vjp(double2 *Aall, const double2 *chi0, const double2 *K, int n, int g0,
-             const double2 *cbar, double2 *u, double2 *v, int *info) {
+             const double2 *cbar, double2 *u, double2 *v, int *info, double2 *xout) {
   extern __shared__ double2 sm[];
   double2 *x = sm;                   // [n]
   double2 *y = sm + n;               // [n]
@@ -459,6 +494,8 @@ __global__ void __launch_bounds__(kLuThreads)
     if (t == 0) x[r] = cdiv(make_double2(x[r].x - sr[0], x[r].y - si[0]), A[(size_t)r * n + r]);
     __syncthreads();
   }
+  if (xout)
+    for (int i = t; i < n; i += kLuThreads) xout[(size_t)w * n + i] = x[i];
   // v = e + K x
   for (int i = t; i < n; i += kLuThreads) {
     double re = i == g0 ? 1.0 : 0.0, im = 0.0;
@@ -510,6 +547,153 @@ __global__ void __launch_bounds__(kLuThreads)
   for (int i = t; i < n; i += kLuThreads) {
     const double2 a = y[i];  // u = cbar conj(a)
     uw[i] = make_double2(cb.x * a.x + cb.y * a.y, cb.y * a.x - cb.x * a.y);
+  }
+}
+
+// ------------------------------------------------- ALDA kernel adjoint
+// The cotangent of the kernel matrix from the Dyson solve, then of f_xc on
+// the grid, then of the density and through it of the occupations and the
+// orbitals.  With x = A^{-1} chi0 e, a = A^{-T} e and u = chi00_bar conj(a)
+// (k_lu_vjp), d chi00 = (chi0^T a)^T dK x, so
+//   Kbar[G][G'] = sum_w p_w[G] conj(x_w[G']),  p_w = chi0(w)^H u_w.
+
+// p_w = chi0(w)^H u_w (row-major chi0: p[G] = sum_H conj(chi0[H][G]) u[H]).
+__global__ void k_chi0h_u(const double2 *chi0, const double2 *u, int n, double2 *p) {
+  const int w = blockIdx.y, g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const double2 *C = chi0 + (size_t)w * n * n;
+  const double2 *uw = u + (size_t)w * n;
+  double re = 0.0, im = 0.0;
+  for (int h = 0; h < n; ++h) {
+    const double2 c = C[(size_t)h * n + g], a = uw[h];
+    re = fma(c.x, a.x, fma(c.y, a.y, re));
+    im = fma(c.x, a.y, fma(-c.y, a.x, im));
+  }
+  p[(size_t)w * n + g] = make_double2(re, im);
+}
+
+// Kbar[G][G'] += sum_w p_w[G] conj(x_w[G']), frequencies in order.
+__global__ void k_kbar(const double2 *p, const double2 *x, int n, int n_w, double2 *Kbar) {
+  const int i = blockIdx.y, j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double re = 0.0, im = 0.0;
+  for (int w = 0; w < n_w; ++w) {
+    const double2 a = p[(size_t)w * n + i], b = x[(size_t)w * n + j];
+    re = fma(a.x, b.x, fma(a.y, b.y, re));
+    im = fma(a.y, b.x, fma(-a.x, b.y, im));
+  }
+  double2 &o = Kbar[(size_t)i * n + j];
+  o.x += re;
+  o.y += im;
+}
+
+// Phi[j][b] = exp(i G_b . r_j) = exp(2 pi i m_b . (j_0/N0, j_1/N1, j_2/N2)),
+// the phases of the forward transform (integer products reduced mod N).
+__global__ void k_phi(const int *gb, int n_g, int N0, int N1, int N2, double2 *Phi) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+  if (b >= n_g) return;
+  const int j0 = j / (N1 * N2), j1 = (j / N2) % N1, j2 = j % N2;
+  const int p0 = ((gb[3 * b] * j0) % N0 + N0) % N0;
+  const int p1 = ((gb[3 * b + 1] * j1) % N1 + N1) % N1;
+  const int p2 = ((gb[3 * b + 2] * j2) % N2 + N2) % N2;
+  double sn, cs;
+  sincospi(2.0 * ((double)p0 / N0 + (double)p1 / N1 + (double)p2 / N2), &sn, &cs);
+  Phi[(size_t)j * n_g + b] = make_double2(cs, sn);
+}
+
+// fbar[j] += (1/N_r) Re sum_a conj(Phi[j][a]) T[j][a], T[j][a] =
+// sum_b conj(Kbar[a][b]) Phi[j][b]: the cotangent of f_xc(r_j) from
+// K[a][b] = (1/N_r) sum_j f_xc(r_j) exp(-i (G_a - G_b) . r_j).
+__global__ void k_fbar(const double2 *Phi, const double2 *T, int n_g, int Nr, double *fbar) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Nr) return;
+  double re = 0.0;
+  for (int a = 0; a < n_g; ++a) {
+    const double2 f = Phi[(size_t)j * n_g + a], t = T[(size_t)j * n_g + a];
+    re = fma(f.x, t.x, fma(f.y, t.y, re));
+  }
+  fbar[j] += re / Nr;
+}
+
+// nbar[j] = fbar[j] f_xc'(n(r_j)), n from the per-k partials in k order.
+__global__ void k_nbar(const double *dens, int nk, int Nr, double scale, const double *fbar,
+                       double *nbar) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Nr) return;
+  double s = 0.0;
+  for (int k = 0; k < nk; ++k) s += dens[(size_t)k * Nr + j];
+  nbar[j] = fbar[j] * fxc_deriv(s * scale);
+}
+
+// Density adjoint per k (the bands the forward density summed):
+//   occ_bar[k][n] += scale sum_j nbar_j |u_nk(r_j)|^2,
+//   coef_bar[k][n](G) += 2 scale f_nk sum_j nbar_j u_nk(r_j) e^{-i G.r_j}
+// (the second a forward transform of nbar u on the box, read at the basis).
+__global__ void __launch_bounds__(256)
+    k_density_vjp(const double2 *coef, const double *occ, const int *nb, const int *npw,
+                  const int *miller, int nb_max, int npw_max, int N0, int N1, int N2,
+                  double scale, const double *nbar, double *occ_bar, double2 *coef_bar) {
+  extern __shared__ double2 sm[];
+  __shared__ double red[256];
+  const int Nr = N0 * N1 * N2;
+  double2 *box = sm;
+  double2 *tw = sm + Nr;
+  const int k = blockIdx.x;
+  make_twiddles(tw, N0, N1, N2);
+  const int nbk = nb[k], np = npw[k];
+  const int *mk = miller + (size_t)k * npw_max * 3;
+  for (int n = 0; n < nbk; ++n) {
+    const double f = occ[(size_t)k * nb_max + n];
+    if (!(f >= kOccSkip)) continue;
+    __syncthreads();
+    for (int j = threadIdx.x; j < Nr; j += blockDim.x) box[j] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const double2 *c = coef + ((size_t)k * nb_max + n) * npw_max;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+      const int a = ((mk[3 * i] % N0) + N0) % N0;
+      const int b = ((mk[3 * i + 1] % N1) + N1) % N1;
+      const int d = ((mk[3 * i + 2] % N2) + N2) % N2;
+      box[(a * N1 + b) * N2 + d] = c[i];
+    }
+    __syncthreads();
+    dft_pass(box, tw + N0 + N1, N0, N1, N2, 2, 1.0);
+    __syncthreads();
+    dft_pass(box, tw + N0, N0, N1, N2, 1, 1.0);
+    __syncthreads();
+    dft_pass(box, tw, N0, N1, N2, 0, 1.0);
+    __syncthreads();
+    double s = 0.0;
+    for (int j = threadIdx.x; j < Nr; j += blockDim.x) {
+      const double2 u = box[j];
+      const double w = nbar[j];
+      s = fma(w, u.x * u.x + u.y * u.y, s);
+      box[j] = make_double2(w * u.x, w * u.y);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) occ_bar[(size_t)k * nb_max + n] += scale * red[0];
+    if (coef_bar) {
+      dft_pass(box, tw + N0 + N1, N0, N1, N2, 2, -1.0);
+      __syncthreads();
+      dft_pass(box, tw + N0, N0, N1, N2, 1, -1.0);
+      __syncthreads();
+      dft_pass(box, tw, N0, N1, N2, 0, -1.0);
+      __syncthreads();
+      double2 *cb = coef_bar + ((size_t)k * nb_max + n) * npw_max;
+      const double g = 2.0 * scale * f;
+      for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        const int a = ((mk[3 * i] % N0) + N0) % N0;
+        const int b = ((mk[3 * i + 1] % N1) + N1) % N1;
+        const int d = ((mk[3 * i + 2] % N2) + N2) % N2;
+        const double2 v = box[(a * N1 + b) * N2 + d];
+        cb[i].x += g * v.x;
+        cb[i].y += g * v.y;
+      }
+    }
   }
 }
 
@@ -788,8 +972,121 @@ int tdx_dyson_vjp(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, in
   TDX_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_lu_vjp, dim3(n_w), dim3(kLuThreads), lds, s, A, (const double2 *)chi0,
                      (const double2 *)K, n_g, i_g0, (const double2 *)chi00_bar, (double2 *)u,
-                     (double2 *)v, info);
+                     (double2 *)v, info, (double2 *)nullptr);
   TDX_HIP(hipGetLastError());
+  return TDX_OK;
+}
+
+int tdx_dyson_kernel_vjp(tdx_ctx *ctx, const double *chi0, const double *K, int n_g, int n_w,
+                         int i_g0, const double *chi00_bar, double *K_bar, tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && chi0 && K && chi00_bar && K_bar, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(n_g > 0 && n_w > 0 && i_g0 >= 0 && i_g0 < n_g, TDX_ERR_SHAPE, "bad sizes");
+  const size_t lds = (sizeof(double2) * 2 + sizeof(int)) * (size_t)n_g;
+  TDX_REQUIRE(lds <= 64 * 1024, TDX_ERR_SHAPE, "n_g %d too large for the LU kernel", n_g);
+  TDX_REQUIRE(n_w <= 65535 && n_g <= 65535, TDX_ERR_SHAPE, "sizes above the grid");
+  TDX_TRY(check_device(ctx));
+  hipStream_t s = as_stream(stream);
+  const size_t mat = sizeof(double2) * (size_t)n_w * n_g * n_g;
+  const size_t vec = sizeof(double2) * (size_t)n_w * n_g;
+  const size_t ints = (sizeof(int) * ((size_t)n_w + 2) + 255) / 256 * 256;
+  void *w;
+  TDX_TRY(ws_get(ctx, WS_DYSON, mat + 4 * vec + ints, &w));
+  double2 *A = (double2 *)w;
+  double2 *u = (double2 *)((char *)w + mat), *v = u + (size_t)n_w * n_g;
+  double2 *x = v + (size_t)n_w * n_g, *p = x + (size_t)n_w * n_g;
+  int *info = (int *)(p + (size_t)n_w * n_g), *status = info + n_w;
+  dim3 g((n_g + kT - 1) / kT, (n_g + kT - 1) / kT, n_w);
+  hipLaunchKernelGGL(k_one_minus, g, dim3(kT, kT), 0, s, (const double2 *)chi0,
+                     (const double2 *)K, n_g, A);
+  TDX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_lu_vjp, dim3(n_w), dim3(kLuThreads), lds, s, A, (const double2 *)chi0,
+                     (const double2 *)K, n_g, i_g0, (const double2 *)chi00_bar, u, v, info, x);
+  TDX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, s, status);
+  hipLaunchKernelGGL(k_fold_status, dim3(1), dim3(256), 0, s, info, n_w, 0, status);
+  TDX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_chi0h_u, dim3((n_g + 63) / 64, n_w), dim3(64), 0, s, (const double2 *)chi0,
+                     u, n_g, p);
+  TDX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_kbar, dim3((n_g + 63) / 64, n_g), dim3(64), 0, s, p, x, n_g, n_w,
+                     (double2 *)K_bar);
+  TDX_HIP(hipGetLastError());
+  int h[2] = {0, 0};
+  TDX_HIP(hipMemcpyAsync(h, status, sizeof(h), hipMemcpyDeviceToHost, s));
+  TDX_HIP(hipStreamSynchronize(s));
+  TDX_REQUIRE(h[0] == INT_MAX, TDX_ERR_NUMERIC,
+              "Dyson matrix singular at frequency %d (column %d)", h[0], h[1] - 1);
+  return TDX_OK;
+}
+
+int tdx_kernel_matrix_vjp(tdx_ctx *ctx, const tdx_states *st, const int *gbasis, int n_g,
+                          const int dens_grid[3], const double *K_bar, double *fxc_bar,
+                          tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && st && gbasis && K_bar && fxc_bar, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(n_g > 0 && n_g <= 65535, TDX_ERR_SHAPE, "bad n_g");
+  TDX_TRY(check_device(ctx));
+  int Nr;
+  size_t lds;
+  TDX_TRY(check_grid(st, dens_grid, &Nr, &lds));
+  hipStream_t s = as_stream(stream);
+  const int N0 = dens_grid[0], N1 = dens_grid[1], N2 = dens_grid[2];
+  const size_t mat = sizeof(double2) * (size_t)Nr * n_g;
+  void *w;
+  TDX_TRY(ws_get(ctx, WS_ADJ2, 2 * mat, &w));
+  double2 *Phi = (double2 *)w, *T = (double2 *)((char *)w + mat);
+  hipLaunchKernelGGL(k_phi, dim3((n_g + 63) / 64, Nr), dim3(64), 0, s, gbasis, n_g, N0, N1, N2,
+                     Phi);
+  TDX_HIP(hipGetLastError());
+  TDX_REQUIRE(rocblas_set_stream(ctx->blas, s) == rocblas_status_success, TDX_ERR_HIP,
+              "rocblas_set_stream failed");
+  const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+  // T (column-major n_g x N_r) = Kbar_cm^H Phi_cm, Kbar_cm(b, a) = Kbar[a][b]
+  const rocblas_status rs = rocblas_zgemm(
+      ctx->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, n_g, Nr, n_g, &one,
+      (const rocblas_double_complex *)K_bar, n_g, (const rocblas_double_complex *)Phi, n_g, &zero,
+      (rocblas_double_complex *)T, n_g);
+  TDX_REQUIRE(rs == rocblas_status_success, TDX_ERR_HIP, "rocblas_zgemm failed (%d)", (int)rs);
+  hipLaunchKernelGGL(k_fbar, dim3((Nr + 255) / 256), dim3(256), 0, s, Phi, T, n_g, Nr, fxc_bar);
+  TDX_HIP(hipGetLastError());
+  TDX_HIP(hipStreamSynchronize(s));  // the workspace may be reused after return
+  return TDX_OK;
+}
+
+int tdx_density_vjp(tdx_ctx *ctx, const tdx_states *st, const int dens_grid[3],
+                    const double *fxc_bar, double *occ_bar, double *coef_bar,
+                    tdx_stream stream) {
+  clear_error();
+  TDX_REQUIRE(ctx && st && fxc_bar && occ_bar, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_TRY(check_device(ctx));
+  int Nr;
+  size_t lds;
+  TDX_TRY(check_grid(st, dens_grid, &Nr, &lds));
+  TDX_REQUIRE(lds + 256 * sizeof(double) <= 160 * 1024, TDX_ERR_SHAPE,
+              "density grid of %d points exceeds LDS", Nr);
+  hipStream_t s = as_stream(stream);
+  const int N0 = dens_grid[0], N1 = dens_grid[1], N2 = dens_grid[2];
+  void *w;
+  TDX_TRY(ws_get(ctx, WS_DENS, sizeof(double) * ((size_t)st->n_k + 1) * Nr, &w));
+  double *dens = (double *)w, *nbar = dens + (size_t)st->n_k * Nr;
+  TDX_HIP(hipFuncSetAttribute((const void *)k_density, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+  TDX_HIP(hipFuncSetAttribute((const void *)k_density_vjp,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_density, dim3(st->n_k), dim3(256), lds, s, (const double2 *)st->coef,
+                     st->occ, st->nb, st->npw, st->miller, st->nb_max, st->npw_max, N0, N1, N2,
+                     dens);
+  TDX_HIP(hipGetLastError());
+  const double scale = 2.0 / (st->n_k * st->omega_cell);
+  hipLaunchKernelGGL(k_nbar, dim3((Nr + 255) / 256), dim3(256), 0, s, dens, st->n_k, Nr, scale,
+                     fxc_bar, nbar);
+  TDX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_density_vjp, dim3(st->n_k), dim3(256), lds, s, (const double2 *)st->coef,
+                     st->occ, st->nb, st->npw, st->miller, st->nb_max, st->npw_max, N0, N1, N2,
+                     scale, nbar, occ_bar, (double2 *)coef_bar);
+  TDX_HIP(hipGetLastError());
+  TDX_HIP(hipStreamSynchronize(s));  // the density workspace may be reused after return
   return TDX_OK;
 }
 

@@ -20,7 +20,10 @@ forward kernels and, in ``backward``, its reverse-mode entry points:
 beta = 1/T and tau = x beta are ordinary torch arithmetic, so the explicit
 temperature dependence of S and F reaches T through autograd.  One
 temperature is used for every q (the states are built once).  The kernel
-is the RPA Coulomb kernel, which depends on none of the parameters.
+is RPA, which depends on none of the parameters, or ALDA, whose dependence
+on the density adds to backward: dyson_kernel_vjp -> kernel_matrix_vjp per
+q, then density_vjp once, feeding the same occupations_vjp and
+potential_vjp.
 """
 from __future__ import annotations
 
@@ -29,10 +32,10 @@ from typing import Optional
 import numpy as np
 import torch
 
-from . import (Context, build_states, chi0, chi0_vjp, dsf, dsf_vjp, dyson, dyson_vjp, itcf,
-               itcf_vjp, kernel_matrix, occupations, occupations_vjp, pair_density,
-               pair_density_range, pair_density_vjp, potential_vjp, response_basis, transitions,
-               weights_vjp)
+from . import (Context, build_states, chi0, chi0_vjp, density_vjp, dsf, dsf_vjp, dyson,
+               dyson_kernel_vjp, dyson_vjp, itcf, itcf_vjp, kernel_matrix, kernel_matrix_vjp,
+               occupations, occupations_vjp, pair_density, pair_density_range, pair_density_vjp,
+               potential_vjp, response_basis, transitions, weights_vjp)
 
 
 def _with_shell_values(w, v):
@@ -49,8 +52,8 @@ class ChainRunner:
     and recomputes the occupations for the new temperature."""
 
     def __init__(self, ctx: Context, w, paired: bool = True, block_bytes: int = 8 << 30):
-        if w.xc != "rpa":
-            raise ValueError("gradients are implemented for the RPA kernel")
+        if w.xc not in ("rpa", "alda"):
+            raise ValueError(f"no gradient for the kernel {w.xc!r}")
         self.ctx = ctx
         self.w = w
         self.paired = paired
@@ -103,7 +106,7 @@ class ChainRunner:
             om = torch.as_tensor(w.omega_grid(iq), device=dev)
             c0 = chi0(ctx, tr, P, len(basis), "fp64", om, eta, pref)
             del P
-            K = kernel_matrix(ctx, st, qj, gb, "rpa")
+            K = kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid)
             out.append(dyson(ctx, c0, K, g0))
             per_q.append(dict(qj=tuple(qj), gb=gb, g0=g0, tr=tr, chi0=c0, K=K, omega=om))
         self.saved = dict(w=w, st=st, pref=pref, eta=eta, per_q=per_q)
@@ -118,10 +121,18 @@ class ChainRunner:
         eta_bar = torch.zeros(1, dtype=torch.float64, device=dev)
         coef_bar = torch.zeros_like(st.coef) if need_v else None
         T_bar = 0.0
+        alda = w.xc == "alda"
+        if alda:
+            fxc_bar = torch.zeros(int(np.prod(w.dens_grid)), dtype=torch.float64, device=dev)
         for iq, q in enumerate(sv["per_q"]):
             tr, gb = q["tr"], q["gb"]
             n_g = gb.shape[0]
             u, v = dyson_vjp(ctx, q["chi0"], q["K"], q["g0"], chi00_bar[iq].contiguous())
+            if alda:
+                K_bar = dyson_kernel_vjp(ctx, q["chi0"], q["K"], q["g0"],
+                                         chi00_bar[iq].contiguous())
+                kernel_matrix_vjp(ctx, st, gb, w.dens_grid, K_bar, fxc_bar)
+                del K_bar
             w_bar = torch.empty((max(len(tr), 1), 3), dtype=torch.float64, device=dev)
             for b0, b1 in self.blocks(len(tr), n_g, tr.k_offsets.cpu().numpy()):
                 P = pair_density_range(ctx, st, q["qj"], tr, gb, b0, b1, "fp64")
@@ -135,6 +146,10 @@ class ChainRunner:
                 del rho_bar
             occ_bar = torch.zeros(occ_shape, dtype=torch.float64, device=dev)
             weights_vjp(ctx, st, q["qj"], tr, w_bar, occ_bar, eps_bar, eta_bar)
+            T_bar += float(occupations_vjp(ctx, st, occ_bar, eps_bar)[0])
+        if alda:
+            occ_bar = torch.zeros(occ_shape, dtype=torch.float64, device=dev)
+            density_vjp(ctx, st, w.dens_grid, fxc_bar, occ_bar, coef_bar)
             T_bar += float(occupations_vjp(ctx, st, occ_bar, eps_bar)[0])
         v_bar = potential_vjp(ctx, w, st, eps_bar, coef_bar) if need_v else None
         return T_bar, float(eta_bar[0]), v_bar

@@ -114,6 +114,33 @@ def test_dyson_vjp_matches_autograd(tdx, ctx):
     assert err < 1e-12
 
 
+def test_dyson_kernel_vjp_matches_autograd(tdx, ctx):
+    """K_bar of chi00 = [(1 - chi0 K)^{-1} chi0]_{g0 g0} with a full complex
+    K (the ALDA kernel is not diagonal), accumulated onto a given K_bar."""
+    import torch
+    _say("dyson kernel vjp")
+    g = torch.Generator().manual_seed(5)
+    n_w, n_g, g0 = 6, 21, 4
+    c0 = (torch.randn(n_w, n_g, n_g, generator=g, dtype=torch.float64) +
+          1j * torch.randn(n_w, n_g, n_g, generator=g, dtype=torch.float64)) * 0.05
+    K = (torch.randn(n_g, n_g, generator=g, dtype=torch.float64) +
+         1j * torch.randn(n_g, n_g, generator=g, dtype=torch.float64)) * 0.1
+    K = K + torch.diag(torch.rand(n_g, generator=g, dtype=torch.float64) + 0.5)
+    cbar = torch.randn(n_w, generator=g, dtype=torch.float64) + \
+        1j * torch.randn(n_w, generator=g, dtype=torch.float64)
+    Kr = K.clone().requires_grad_()
+    I = torch.eye(n_g, dtype=torch.complex128)
+    x = torch.linalg.solve(I - c0 @ Kr, c0[:, :, g0:g0 + 1])[:, g0, 0]
+    L = (cbar.conj() * x).real.sum()
+    (gK,) = torch.autograd.grad(L, (Kr,))
+    base = torch.full((n_g, n_g), 0.25 - 0.5j, dtype=torch.complex128)
+    got = tdx.dyson_kernel_vjp(ctx, c0.cuda(), K.cuda(), g0, cbar.cuda(),
+                               K_bar=base.clone().cuda()).cpu() - base
+    err = float((got - gK).abs().max() / gK.abs().max())
+    _say(f"  K cotangent err {err:.2e}")
+    assert err < 1e-12
+
+
 @pytest.mark.parametrize("paired", [False, True])
 def test_chi0_vjp_matches_autograd(tdx, ctx, paired):
     """Transitions and FP64 pair densities of the hydrogen box; a ragged
@@ -212,16 +239,19 @@ def _gpu_loss(tdx, ctx, w, T, eta, v, c, runner=None):
     return L, (Tt, et, vt)
 
 
-@pytest.mark.parametrize("form", ["paired", "full", "paired-blocks"])
+@pytest.mark.parametrize("form", ["paired", "full", "paired-blocks", "alda"])
 def test_gradient_matches_oracle_tangent_and_finite_differences(tdx, ctx, form):
     """The reverse sweep over the time-reversal paired list, over the full
-    list, and over the paired list in blocks of about 40 transitions (pair
-    densities and cotangents recomputed per block)."""
+    list, over the paired list in blocks of about 40 transitions (pair
+    densities and cotangents recomputed per block), and with the ALDA kernel
+    (paired list), whose density moves with T and v."""
     import torch
     from oracle import tangent
     from paper_2510_01875_amd.grad import ChainRunner
     _say("gradient", form)
     w = _w()
+    if form == "alda":
+        w = w.with_(xc="alda", dens_grid=(12, 12, 12))
     T, eta = w.temperatures[0], w.eta
     v = np.asarray(w.potential.shell_v, dtype=np.float64)
     c = _loss_weights(w.n_tau)
