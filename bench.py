@@ -446,6 +446,60 @@ def batched_graph_run(tdx, ctx, w, args, budget_bytes=200 << 30, slice_log2=22):
     return line
 
 
+def gradient_run(tdx, ctx, w, prec="bf16x3"):
+    """The gradient workload at its full configuration (h16_c5: the
+    16-proton system, 4 q, 1000 frequencies, 64 imaginary times on
+    [0, beta/2]): the adjoint of a seeded linear functional of F(q, tau) for
+    all q with respect to (T, eta, v_1..v_3), time-reversal paired lists,
+    pair densities recomputed block by block in the reverse sweep.  The
+    forward chi0 runs in `prec` (the reverse sweep is FP64).  Times the
+    forward and the reverse pass (wall clock around synchronised steps)."""
+    import torch
+    from paper_2510_01875_amd.grad import ChainRunner, itcf_differentiable
+    T, eta = w.temperatures[0], w.eta
+    v0 = np.array(w.potential.shell_v, dtype=np.float64)
+    c = np.random.default_rng(11).standard_normal((len(w.qs), w.n_tau))
+    runner = ChainRunner(ctx, w, paired=True, block_bytes=8 << 30, prec=prec)
+    Tt = torch.tensor(T, dtype=torch.float64, requires_grad=True)
+    et = torch.tensor(eta, dtype=torch.float64, requires_grad=True)
+    vt = torch.tensor(v0, dtype=torch.float64, requires_grad=True)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    t0 = time.perf_counter()
+    F = itcf_differentiable(ctx, w, Tt, et, vt, runner=runner)
+    L = (F.cpu() * torch.as_tensor(c)).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    peak_f = torch.cuda.max_memory_allocated()
+    log(f"forward: {len(w.qs)} q, {t1 - t0:.1f} s")
+    torch.cuda.reset_peak_memory_stats()
+    gT, ge, gv = torch.autograd.grad(L, (Tt, et, vt))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"reverse: {t2 - t1:.1f} s")
+    per_q = runner.saved["per_q"]
+    n_t = [len(q["tr"]) for q in per_q]
+    n_g = [int(q["gb"].shape[0]) for q in per_q]
+    flops = sum(f_alg(w.n_omega, g, t) for g, t in zip(n_g, n_t))
+    return {
+        "metric": "chi0 TFLOP/s + S(q,w) eval/s at stated error vs FP64, plain vs split-BF16",
+        "value": flops / (t1 - t0) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": (t2 - t0) * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": prec,
+        "data": "synthetic (seeded model system; no paper data)",
+        "config": {"workload": w.name, "kgrid": list(w.kgrid), "n_q": len(w.qs),
+                   "n_omega": w.n_omega, "n_tau": w.n_tau, "n_g": n_g, "n_trans": n_t,
+                   "transitions": "one per time-reversal pair",
+                   "form": "F(q, tau) for all q and its adjoint in (T, eta, v_1..v_3); value = "
+                           "F_alg of the forward chi0 / forward wall time (states, pair "
+                           "densities, Dyson, S, F included)"},
+        "forward_s": t1 - t0, "reverse_s": t2 - t1,
+        "peak_gib": {"forward": peak_f / 2 ** 30,
+                     "reverse": torch.cuda.max_memory_allocated() / 2 ** 30},
+        "grad": {"T": float(gT), "eta": float(ge), "v": [float(x) for x in gv]},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -500,6 +554,13 @@ def main():
     ctx = tdx.Context(0)
     if args.workload == "fcc_c4":
         line = batched_graph_run(tdx, ctx, w, args)
+        ctx.close()
+        print(json.dumps(line), flush=True)
+        return
+    if args.workload == "h16_c5":
+        if os.path.exists(args.tune_cache):
+            tdx.tune_load(ctx, args.tune_cache)
+        line = gradient_run(tdx, ctx, w, args.prec)
         ctx.close()
         print(json.dumps(line), flush=True)
         return

@@ -51,13 +51,17 @@ class ChainRunner:
     values v only: a runner called again with the same v keeps its states
     and recomputes the occupations for the new temperature."""
 
-    def __init__(self, ctx: Context, w, paired: bool = True, block_bytes: int = 8 << 30):
+    def __init__(self, ctx: Context, w, paired: bool = True, block_bytes: int = 8 << 30,
+                 prec: str = "fp64"):
         if w.xc not in ("rpa", "alda"):
             raise ValueError(f"no gradient for the kernel {w.xc!r}")
         self.ctx = ctx
         self.w = w
         self.paired = paired
         self.block_bytes = int(block_bytes)
+        # precision of the forward chi0 (the reverse sweep is FP64 whatever
+        # it is; split-BF16 moves the gradient by its ~1e-5 forward error)
+        self.prec = prec
         self.saved = None
         self._st, self._st_v = None, None
 
@@ -102,9 +106,9 @@ class ChainRunner:
             basis, g0 = response_basis(w.cell, w.kgrid, qj, w.ecut_chi[iq])
             gb = torch.from_numpy(basis).to(dev)
             tr = transitions(ctx, st, qj, w.f_trans_thr, paired=self.paired)
-            P = pair_density(ctx, st, qj, tr, gb, "fp64")
+            P = pair_density(ctx, st, qj, tr, gb, self.prec)
             om = torch.as_tensor(w.omega_grid(iq), device=dev)
-            c0 = chi0(ctx, tr, P, len(basis), "fp64", om, eta, pref)
+            c0 = chi0(ctx, tr, P, len(basis), self.prec, om, eta, pref)
             del P
             K = kernel_matrix(ctx, st, qj, gb, w.xc, w.dens_grid)
             out.append(dyson(ctx, c0, K, g0))
