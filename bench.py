@@ -249,6 +249,37 @@ def gpu_vs_oracle(tdx, ctx, ws, om, r, precs, paired):
     return out
 
 
+def c1_leg(tdx, ctx):
+    """The free-electron configuration (feg_c1: 8^3 k, 56 bands on plane
+    waves to 10 Ha, 200 frequencies, RPA, one q): states, then the whole
+    step (transitions, pair densities, chi0, K, Dyson, S, F) in FP64 and in
+    split-BF16, each timed after a warm-up; the split-BF16 S and F against
+    the FP64 ones."""
+    import torch
+    import workloads
+    w = workloads.feg_c1()
+    t0 = time.perf_counter()
+    st = tdx.build_states(ctx, w, w.temperatures[0])
+    torch.cuda.synchronize()
+    t_states = time.perf_counter() - t0
+    out = {"workload": w.name, "kgrid": list(w.kgrid), "n_omega": w.n_omega,
+           "build_states_s": t_states}
+    res = {}
+    for prec in ("fp64", "bf16x3"):
+        tdx.run_q(ctx, w, st, 0, prec=prec, keep_chi0=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = tdx.run_q(ctx, w, st, 0, prec=prec, keep_chi0=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[prec] = r
+        out[prec] = {"step_ms": dt * 1e3, "s_eval_per_s": w.n_omega / dt,
+                     "n_trans": r.n_trans, "n_g": len(r.basis)}
+    out["error_vs_fp64"] = errors(res["bf16x3"].S.cpu().numpy(), res["fp64"].S.cpu().numpy(),
+                                  res["bf16x3"].F.cpu().numpy(), res["fp64"].F.cpu().numpy())
+    return out
+
+
 def h16_leg(tdx, ctx, sample_every=50):
     """The 16-proton system at full size (h16_c3: 64 k, about 6290 plane waves
     and 860 bands per k, 304 G, 1000 frequencies on [0, 5] Ha, RPA): q0 with
@@ -783,6 +814,10 @@ def main():
                      "issued_mfma_frac": (3.0 if args.prec == "bf16x3" else 1.0)
                      * per_launch / (avg_ms * 1e-3) / 1e12 / PEAK_TFLOPS[args.prec]},
     }
+    log("feg_c1 leg ...")
+    line["feg_c1"] = c1_leg(tdx, ctx)
+    log(f"feg_c1: FP64 step {line['feg_c1']['fp64']['step_ms']:.1f} ms, split-BF16 "
+        f"{line['feg_c1']['bf16x3']['step_ms']:.1f} ms, errors {line['feg_c1']['error_vs_fp64']}")
     if args.h16:
         del st
         torch.cuda.empty_cache()
