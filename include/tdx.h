@@ -309,18 +309,23 @@ typedef struct tdx_chi0_plan tdx_chi0_plan;
 
 /* Build the work queue of a ragged batch: for TDX_PREC_BF16X3 every
  * (q, frequency block, G block, G' block, transition slice) tile, ordered
- * longest first, plus the slice-partial buffers, in one device allocation
- * owned by the plan.  The tile shape is the configured one (see
+ * by predicted cost, costliest first, plus the slice-partial buffers and the
+ * queue counter, in one device allocation owned by the plan.  A lone item is
+ * sliced as a grid launch would slice it; several items share one slice-count
+ * factor on their minimum counts, chosen for the least predicted queue time.  The tile shape is the configured one (see
  * tdx_chi0_set_config / tdx_autotune_chi0) of the widest basis in the batch.
  * Other precisions run their items one launch each.  Items must stay valid
  * until the plan is destroyed. */
 int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, int prec,
                          tdx_chi0_plan **out);
-/* Enqueue the plan: ONE persistent kernel (two workgroups per CU) that walks
- * the longest-first tile list round-robin, and one batched slice reduction.  No allocation, host synchronisation or memset:
- * the launch can be captured into a HIP graph and replayed.  Results are
- * independent of which workgroup ran which tile (fixed-order FP64 slice
- * reduction). */
+/* Enqueue the plan: ONE persistent kernel (the variant's workgroups per CU
+ * on every CU) whose workgroups take tiles off the list one at a time
+ * through the plan's atomic counter, which the kernel sets back to zero as it
+ * ends, and one batched slice reduction.  No allocation, host
+ * synchronisation or memset: the launch can be captured into a HIP graph and
+ * replayed.  Results are independent of which workgroup ran which tile
+ * (fixed-order FP64 slice reduction).  Launches of one plan must not overlap
+ * (they share its partials and counter). */
 int tdx_chi0_plan_launch(tdx_ctx *ctx, tdx_chi0_plan *plan, tdx_stream stream);
 int tdx_chi0_plan_destroy(tdx_chi0_plan *plan);
 /* create + launch + synchronise + destroy */
@@ -342,7 +347,8 @@ int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slic
  * q is cut into slices of n transitions (rounded up to the kernel's chunk),
  * the last one shorter, whatever the tile count; n = 0 (the default) lets
  * each call choose the length (the tuned 2^slice_log2, shortened until the
- * tiles fill the chip).  Within a slice the sums run in FP32 over runs of
+ * tiles fill the chip; then, for split-BF16, the slice count up to 4 times
+ * that whose rounds of tiles leave the least predicted idle time).  Within a slice the sums run in FP32 over runs of
  * chunks (split-BF16, FP32) and in FP64 across runs; the slices' FP64
  * partials are reduced in a fixed order, so the length fixes the rounding
  * order and the partial workspace (slices x n_w x n_g^2 x 16 bytes). */

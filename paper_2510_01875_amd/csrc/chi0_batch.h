@@ -30,6 +30,16 @@ struct BatchTile {
   long long slice;
 };
 
+// The persistent kernel's work, in device memory: the tile list, its items
+// and two counter words (next tile, workgroups done), zero before the first
+// launch and left zero by every launch.
+struct TileQueue {
+  const BatchItem *items;
+  const BatchTile *tiles;
+  int n_tiles;
+  int *counter;
+};
+
 // Rows and columns [0, nm) of a basis run in main tiles, rows nm .. n_g - 1
 // (tail of them) in tail tiles; nm = ld and tail = 0 when n_g is a multiple
 // of 16 or the variant is pipelined.
@@ -59,7 +69,6 @@ int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double
                        long long n_trans, long long slice_len, int slices, const double *omega,
                        int n_w, double eta, int paired, int n_g, double2 *part, double2 *tpart,
                        hipStream_t s);
-int bf16x3_launch_persistent(int v, const BatchItem *items, const BatchTile *tiles, int n_tiles,
-                             int n_blocks, hipStream_t s);
+int bf16x3_launch_persistent(int v, const TileQueue *queue, int n_blocks, hipStream_t s);
 
 }  // namespace tdx

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "chi0_batch.h"
@@ -95,35 +96,135 @@ const char *prec_name(int prec) {
   return prec == TDX_PREC_FP64 ? "fp64" : prec == TDX_PREC_FP32 ? "fp32" : "bf16x3";
 }
 
-// Slices of a transition list: about 2^slice_log2 transitions each, enough
-// of them that the tile count fills the chip, a multiple of the chunk; or,
-// with a fixed length set on the context, slices of that length.
-void slicing(const tdx_ctx *ctx, long long n_trans, int slice_log2, long long tiles_per_slice,
-             long long *slice_len, int *slices) {
-  if (ctx->slice_len > 0) {
-    const long long len = (ctx->slice_len + kChunkAlign - 1) / kChunkAlign * kChunkAlign;
-    *slice_len = len;
-    *slices = (int)std::max<long long>(1, (n_trans + len - 1) / len);
-    return;
-  }
-  long long ns = std::max<long long>((n_trans + (1LL << slice_log2) - 1) >> slice_log2,
-                                     (kMinTiles + tiles_per_slice - 1) / tiles_per_slice);
-  ns = std::max<long long>(1, std::min<long long>(ns, (n_trans + kChunkAlign - 1) / kChunkAlign));
-  ns = std::min<long long>(ns, 8192);
-  long long len = (n_trans + ns - 1) / ns;
-  len = (len + kChunkAlign - 1) / kChunkAlign * kChunkAlign;
-  *slice_len = len;
-  *slices = (int)((n_trans + len - 1) / len);
+// Tiles of one slice for the round model below: main tiles (one row block,
+// column tile and frequency block each) and tail tiles, and the cost of a
+// tail tile relative to a main one (its column blocks over the main tile's,
+// and about a fifth more for the weights each lane forms itself).
+struct SliceTiles {
+  long long main, tail;
+  double tail_cost;
+};
+SliceTiles slice_tiles(int v, int n_w, int n_g);
+
+// Fixed cost of a tile (prologue and fold) in transition-equivalents.
+constexpr double kTileFixed = 1024.0;
+
+long long chunk_len(long long n_trans, long long ns) {
+  const long long len = (n_trans + ns - 1) / ns;
+  return (len + kChunkAlign - 1) / kChunkAlign * kChunkAlign;
 }
 
-// Main tiles of one slice plus its tail tiles.
-long long tiles_per_slice(int v, int n_w, int n_g) {
+// Tile costs of a list cut into slices of len transitions, as (cost, count)
+// groups: a tile costs its slice's transitions plus kTileFixed, times
+// tail_cost for a tail tile.
+void add_tile_groups(std::vector<std::pair<double, long long>> &g, long long n_trans,
+                     long long len, const SliceTiles &t) {
+  const long long ns = (n_trans + len - 1) / len, last = n_trans - (ns - 1) * len;
+  const double full = (double)len + kTileFixed, part = (double)last + kTileFixed;
+  g.push_back({full * t.tail_cost, (ns - 1) * t.tail});
+  g.push_back({part * t.tail_cost, t.tail});
+  g.push_back({full, (ns - 1) * t.main});
+  g.push_back({part, t.main});
+}
+
+// Predicted end of a queue of tiles on `slots` workgroup slots, each tile
+// starting on the slot that frees first, the costliest first.  Tiles of one
+// cost fill the slots level by level, so the slots are kept as groups of
+// equal finishing time.
+double makespan(std::vector<std::pair<double, long long>> g, int slots) {
+  std::sort(g.begin(), g.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+  std::map<double, long long> at;  // finishing time -> slots
+  at[0.0] = slots;
+  for (const auto &x : g) {
+    long long count = x.second;
+    while (count > 0) {
+      auto it = at.begin();
+      const double t0 = it->first;
+      const long long m = it->second, k = std::min(m, count);
+      if (k == m)
+        at.erase(it);
+      else
+        it->second = m - k;
+      at[t0 + x.first] += k;
+      count -= k;
+    }
+  }
+  return at.rbegin()->first;
+}
+
+// Slice counts allowed for a list: from the minimum, about 2^slice_log2
+// transitions a slice but at least enough tiles to fill the chip, up to 4
+// times that, with the slice partials held within 4 times the minimum's or
+// 16 GiB, whichever is larger than the minimum's own.
+struct SliceRange {
+  long long ns0, ns_hi;
+};
+SliceRange slice_range(long long n_trans, int slice_log2, const SliceTiles &tiles,
+                       size_t bytes_per_slice) {
+  const long long tps = std::max<long long>(1, tiles.main + tiles.tail);
+  const long long ns_cap = std::max<long long>(
+      1, std::min<long long>((n_trans + kChunkAlign - 1) / kChunkAlign, 8192));
+  long long ns0 = std::max<long long>((n_trans + (1LL << slice_log2) - 1) >> slice_log2,
+                                      (kMinTiles + tps - 1) / tps);
+  ns0 = std::max<long long>(1, std::min<long long>(ns0, ns_cap));
+  const size_t cap_bytes = std::max<size_t>(
+      (size_t)ns0 * bytes_per_slice, std::min<size_t>(4 * ns0 * bytes_per_slice, (size_t)16 << 30));
+  long long ns_hi = std::min<long long>(4 * ns0, ns_cap);
+  if (bytes_per_slice > 0)
+    ns_hi = std::min<long long>(ns_hi, (long long)(cap_bytes / bytes_per_slice));
+  return SliceRange{ns0, std::max(ns_hi, ns0)};
+}
+
+// Slices of a transition list, a multiple of the chunk long; with a fixed
+// length set on the context, slices of that length.  Tiles run in rounds of
+// one per workgroup slot, so a count just past a whole number of rounds
+// leaves most of the chip idle in the last one (the crystal's N_G = 129
+// basis: 8 slices of 260 tiles on 256 slots are 8.1 rounds); the slice
+// count in slice_range that minimises the makespan is taken, the fewest
+// within 0.5 % of the best.  Lists of many rounds keep the minimum, whose
+// last round is a small share.
+void slicing(const tdx_ctx *ctx, long long n_trans, int slice_log2, const SliceTiles &tiles,
+             int slots, size_t bytes_per_slice, long long *slice_len, int *slices) {
+  long long len;
+  if (ctx->slice_len > 0) {
+    len = (ctx->slice_len + kChunkAlign - 1) / kChunkAlign * kChunkAlign;
+  } else {
+    const SliceRange r = slice_range(n_trans, slice_log2, tiles, bytes_per_slice);
+    long long best_ns = r.ns0;
+    if (slots > 0 && r.ns0 * (tiles.main + tiles.tail) < 64LL * slots) {
+      std::vector<std::pair<long long, double>> cand;
+      double best = 1e300;
+      for (long long ns = r.ns0; ns <= r.ns_hi; ++ns) {
+        if (ns > r.ns0 && chunk_len(n_trans, ns) == chunk_len(n_trans, ns - 1)) continue;
+        std::vector<std::pair<double, long long>> g;
+        add_tile_groups(g, n_trans, chunk_len(n_trans, ns), tiles);
+        const double t = makespan(g, slots);
+        cand.push_back({ns, t});
+        best = std::min(best, t);
+      }
+      for (const auto &c : cand)
+        if (c.second <= 1.005 * best) {
+          best_ns = c.first;
+          break;
+        }
+    }
+    len = chunk_len(n_trans, best_ns);
+  }
+  *slice_len = len;
+  *slices = (int)std::max<long long>(1, (n_trans + len - 1) / len);
+}
+
+SliceTiles slice_tiles(int v, int n_w, int n_g) {
   int wb, cols;
   bf16x3_variant_shape(v, &wb, &cols);
   const int ld = (n_g + 15) / 16 * 16;
   const TailSplit sp = bf16x3_split(v, n_g);
-  return (long long)((n_w + wb - 1) / wb) * (sp.nm / 16) * ((sp.nm + cols - 1) / cols) +
-         (long long)bf16x3_tail_groups(v, n_w, sp.tail) * ((ld + cols - 1) / cols);
+  SliceTiles t;
+  t.main = (long long)((n_w + wb - 1) / wb) * (sp.nm / 16) * ((sp.nm + cols - 1) / cols);
+  t.tail = (long long)bf16x3_tail_groups(v, n_w, sp.tail) * ((ld + cols - 1) / cols);
+  const int main_blocks = std::min(sp.nm / 16, cols / 16), tail_blocks = std::min(ld / 16, cols / 16);
+  t.tail_cost = main_blocks > 0 ? 1.2 * tail_blocks / main_blocks : 1.2;
+  return t;
 }
 
 }  // namespace
@@ -134,12 +235,14 @@ int chi0_bf16x3_with(tdx_ctx *ctx, int v, int slice_log2, const void *P, long lo
                      double pref, double2 *chi0, hipStream_t s) {
   long long slice_len;
   int slices;
-  slicing(ctx, n_trans, slice_log2, tiles_per_slice(v, n_w, n_g), &slice_len, &slices);
-  TDX_REQUIRE(slices <= 65535, TDX_ERR_SHAPE, "%d slices exceed the grid (slice length %lld)",
-              slices, slice_len);
   const TailSplit sp = bf16x3_split(v, n_g);
   const size_t out_elems = (size_t)n_w * n_g * n_g;
   const size_t tail_elems = (size_t)n_w * sp.tail * 2 * ld;
+  slicing(ctx, n_trans, slice_log2, slice_tiles(v, n_w, n_g),
+          bf16x3_variant_occupancy(v) * std::max(ctx->n_cu, 1),
+          sizeof(double2) * (out_elems + tail_elems), &slice_len, &slices);
+  TDX_REQUIRE(slices <= 65535, TDX_ERR_SHAPE, "%d slices exceed the grid (slice length %lld)",
+              slices, slice_len);
   void *w;
   TDX_TRY(ws_get(ctx, WS_PARTIAL, sizeof(double2) * (out_elems + tail_elems) * slices, &w));
   double2 *part = (double2 *)w;
@@ -175,6 +278,7 @@ struct tdx_chi0_plan {
   tdx::BatchTile *tiles = nullptr;
   tdx::ReduceItem *reduce = nullptr;
   int *counter = nullptr;
+  tdx::TileQueue *queue = nullptr;
   size_t max_per_slice = 0;
   std::vector<tdx_chi0_item> host_items;  // for the non-persistent precisions
 };
@@ -261,6 +365,52 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
   p->variant = v;
   int wb, cols;
   bf16x3_variant_shape(v, &wb, &cols);
+  // slice counts: a list alone takes its own choice; pooled lists share one
+  // queue and take the common factor f = 1, 9/8, ..., 4 on their minimum
+  // counts (each held in its range) that minimises the queue's makespan
+  const int slots = bf16x3_variant_occupancy(v) * std::max(ctx->n_cu, 1);
+  std::vector<long long> slen(n_items);
+  std::vector<SliceTiles> stiles(n_items);
+  std::vector<SliceRange> range(n_items);
+  long long pooled_tiles = 0;
+  for (int i = 0; i < n_items; ++i) {
+    const tdx_chi0_item &it = items[i];
+    const int ld = (it.n_g + 15) / 16 * 16;
+    int vi, sl;
+    pick(ctx, ld, &vi, &sl);
+    const TailSplit sp = bf16x3_split(v, it.n_g);
+    stiles[i] = slice_tiles(v, it.n_w, it.n_g);
+    const size_t bytes = sizeof(double2) * ((size_t)it.n_w * it.n_g * it.n_g +
+                                            (size_t)it.n_w * sp.tail * 2 * ld);
+    int ns;
+    slicing(ctx, it.n_trans, sl, stiles[i], n_items == 1 ? slots : 0, bytes, &slen[i], &ns);
+    range[i] = slice_range(it.n_trans, sl, stiles[i], bytes);
+    pooled_tiles += range[i].ns0 * (stiles[i].main + stiles[i].tail);
+  }
+  if (n_items > 1 && ctx->slice_len <= 0 && pooled_tiles < 64LL * slots) {
+    auto lens = [&](int j, std::vector<long long> &out) {
+      for (int i = 0; i < n_items; ++i) {
+        const long long ns = std::min(
+            range[i].ns_hi,
+            std::max(range[i].ns0, (long long)std::ceil(range[i].ns0 * (1.0 + j / 8.0))));
+        out[i] = chunk_len(items[i].n_trans, ns);
+      }
+    };
+    std::vector<double> t(25);
+    std::vector<long long> l(n_items);
+    for (int j = 0; j < 25; ++j) {
+      lens(j, l);
+      std::vector<std::pair<double, long long>> g;
+      for (int i = 0; i < n_items; ++i) add_tile_groups(g, items[i].n_trans, l[i], stiles[i]);
+      t[j] = makespan(g, slots);
+    }
+    const double best = *std::min_element(t.begin(), t.end());
+    for (int j = 0; j < 25; ++j)
+      if (t[j] <= 1.005 * best) {
+        lens(j, slen);
+        break;
+      }
+  }
   std::vector<BatchItem> bi(n_items);
   std::vector<ReduceItem> ri(n_items);
   std::vector<BatchTile> tiles;
@@ -269,12 +419,9 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
   for (int i = 0; i < n_items; ++i) {
     const tdx_chi0_item &it = items[i];
     const int ld = (it.n_g + 15) / 16 * 16;
-    int vi, sl;
-    pick(ctx, ld, &vi, &sl);
-    long long slice_len;
-    int slices;
-    slicing(ctx, it.n_trans, sl, tiles_per_slice(v, it.n_w, it.n_g), &slice_len, &slices);
     const TailSplit sp = bf16x3_split(v, it.n_g);
+    const long long slice_len = slen[i];
+    const int slices = (int)((it.n_trans + slice_len - 1) / slice_len);
     const size_t per = (size_t)it.n_w * it.n_g * it.n_g;
     const size_t tper = (size_t)it.n_w * sp.tail * 2 * ld;
     part_off[i] = part_bytes;
@@ -303,20 +450,23 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
         for (int c = 0; c < ncb; ++c)
           for (int a = 0; a < nwb; ++a) tiles.push_back(BatchTile{i, a, g, c, s});
   }
-  // longest tiles first (the last slice of an item is shorter)
+  // costliest tiles first (tail tiles hold more column blocks, the last
+  // slice of an item is shorter)
   std::stable_sort(tiles.begin(), tiles.end(), [&](const BatchTile &a, const BatchTile &b) {
-    auto len = [&](const BatchTile &t) {
+    auto cost = [&](const BatchTile &t) {
       const BatchItem &x = bi[t.item];
-      return std::min(x.slice_len, x.n_trans - t.slice * x.slice_len);
+      const double len = (double)std::min(x.slice_len, x.n_trans - t.slice * x.slice_len);
+      return (len + kTileFixed) * (t.gb < 0 ? stiles[t.item].tail_cost : 1.0);
     };
-    return len(a) > len(b);
+    return cost(a) > cost(b);
   });
   TDX_REQUIRE(tiles.size() < (size_t)1 << 30, TDX_ERR_SHAPE, "too many tiles");
   const size_t off_items = (part_bytes + 255) / 256 * 256;
   const size_t off_reduce = off_items + (sizeof(BatchItem) * n_items + 255) / 256 * 256;
   const size_t off_tiles = off_reduce + (sizeof(ReduceItem) * n_items + 255) / 256 * 256;
   const size_t off_counter = off_tiles + (sizeof(BatchTile) * tiles.size() + 255) / 256 * 256;
-  const size_t total = off_counter + 256;
+  const size_t off_queue = off_counter + 256;
+  const size_t total = off_queue + (sizeof(TileQueue) + 255) / 256 * 256;
   hipError_t e = hipMalloc(&p->mem, total);
   if (e != hipSuccess) {
     delete p;
@@ -334,10 +484,14 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
   p->reduce = (ReduceItem *)(base + off_reduce);
   p->tiles = (BatchTile *)(base + off_tiles);
   p->counter = (int *)(base + off_counter);
+  p->queue = (TileQueue *)(base + off_queue);
   p->n_tiles = (int)tiles.size();
   p->n_blocks = std::max(8, bf16x3_variant_occupancy(v) * std::max(ctx->n_cu, 1)) / 8 * 8;  // a multiple of the XCD count
   int rc = TDX_OK;
-  if (hipMemcpy(p->items, bi.data(), sizeof(BatchItem) * n_items, hipMemcpyHostToDevice) !=
+  const TileQueue q{p->items, p->tiles, p->n_tiles, p->counter};
+  if (hipMemset(p->counter, 0, 256) != hipSuccess ||
+      hipMemcpy(p->queue, &q, sizeof q, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->items, bi.data(), sizeof(BatchItem) * n_items, hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(p->reduce, ri.data(), sizeof(ReduceItem) * n_items, hipMemcpyHostToDevice) !=
           hipSuccess ||
@@ -363,7 +517,7 @@ int tdx_chi0_plan_launch(tdx_ctx *ctx, tdx_chi0_plan *p, tdx_stream stream) {
                        it.pref, it.chi0, stream));
     return TDX_OK;
   }
-  TDX_TRY(bf16x3_launch_persistent(p->variant, p->items, p->tiles, p->n_tiles, p->n_blocks, s));
+  TDX_TRY(bf16x3_launch_persistent(p->variant, p->queue, p->n_blocks, s));
   const unsigned rb = (unsigned)std::min<size_t>((p->max_per_slice + 255) / 256, 4096);
   hipLaunchKernelGGL(k_reduce_batch, dim3(rb, p->n_items), dim3(256), 0, s, p->reduce);
   TDX_HIP(hipGetLastError());

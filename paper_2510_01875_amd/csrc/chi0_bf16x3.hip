@@ -795,23 +795,37 @@ __global__ void __launch_bounds__(64 * NW, OCC)
                                   gb * 16, col0, part + (size_t)bz * n_w * n_g * n_g);
 }
 
-// Persistent form: a fixed grid (OCC workgroups per CU) walks the
-// longest-first tile list in rounds of gridDim.x tiles (XCD-aware within a
-// round), so every workgroup runs a similar amount of work and leaves when it
-// passes the end.  No LDS beyond the tile's double buffer (two workgroups still fit per
-// CU) and no atomics; the assignment is deterministic.
+template <int W, int S, int K, bool PIPE, int DEPTH, int NW>
+constexpr size_t variant_lds() {
+  if constexpr (PIPE)
+    return PipeLds<W, S, K, NW>::kBytes;
+  else
+    return (size_t)DEPTH * Cfg<W, S, K, NW>::kBufWords * 4;
+}
+
+// Persistent form: a fixed grid (OCC workgroups per CU) takes tiles from
+// the costliest-first tile list one at a time through an atomic counter, so
+// a workgroup that finishes early takes the next tile.  Tiles in flight at
+// one time are neighbours in the list, mostly of one slice, so they share
+// its pair-density rows in L2 whichever XCD runs them.  Every workgroup
+// leaves once the counter has passed the end; the last one out (counted in
+// the second word) sets both words back to zero for the next launch, so the
+// queue needs no clearing between launches or graph replays.  The tile
+// index is passed on through one word after the tile's LDS buffers (a static
+// LDS variable would shift the dynamic buffers off their 16-byte alignment,
+// which ran three times slower).
 template <int WPW, int SUB, int CHUNK, int OCC, bool PIPE, int DEPTH, int NW>
-__global__ void __launch_bounds__(64 * NW, OCC)
-    k_chi0_bf16x3_persistent(const BatchItem *items, const BatchTile *tiles, int n_tiles) {
+__global__ void __launch_bounds__(64 * NW, OCC) k_chi0_bf16x3_persistent(const TileQueue *q) {
   typedef Cfg<WPW, SUB, CHUNK, NW> C;
   extern __shared__ unsigned int lds[];
-  const int G = gridDim.x;
-  for (int base = 0; base < n_tiles; base += G) {
-    // round `base`: logical tiles base..base+G-1, a contiguous block per XCD
-    const int idx = base + xcd_logical(blockIdx.x, G);
-    if (idx >= n_tiles) break;
-    const BatchTile tl = tiles[idx];
-    const BatchItem it = items[tl.item];
+  int *next_tile = (int *)(lds + variant_lds<WPW, SUB, CHUNK, PIPE, DEPTH, NW>() / 4);
+  for (;;) {
+    if (threadIdx.x == 0) *next_tile = atomicAdd(&q->counter[0], 1);
+    __syncthreads();
+    const int idx = *next_tile;
+    if (idx >= q->n_tiles) break;
+    const BatchTile tl = q->tiles[idx];
+    const BatchItem it = q->items[tl.item];
     const long long t_lo = tl.slice * it.slice_len;
     const long long t_hi = std::min(it.n_trans, t_lo + it.slice_len);
     const int col0 = tl.gc * C::kCols;
@@ -830,16 +844,17 @@ __global__ void __launch_bounds__(64 * NW, OCC)
                                                  tl.wblk * C::kWBlock, tl.gb * 16, col0,
                                                  it.part + (size_t)tl.slice * it.n_w * it.n_g * it.n_g);
     }
-    __syncthreads();  // the next tile's prologue rewrites the LDS buffers
+    // the next tile's prologue rewrites the LDS buffers, and thread 0 the
+    // tile index every thread has read
+    __syncthreads();
   }
-}
-
-template <int W, int S, int K, bool PIPE, int DEPTH, int NW>
-constexpr size_t variant_lds() {
-  if constexpr (PIPE)
-    return PipeLds<W, S, K, NW>::kBytes;
-  else
-    return (size_t)DEPTH * Cfg<W, S, K, NW>::kBufWords * 4;
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&q->counter[1], 1) == (int)gridDim.x - 1) {
+      atomicExch(&q->counter[0], 0);
+      atomicExch(&q->counter[1], 0);
+    }
+  }
 }
 
 struct Variant {
@@ -914,12 +929,12 @@ int bf16x3_launch_grid(int v, const void *P, const void *R, int ld, const double
   return TDX_OK;
 }
 
-int bf16x3_launch_persistent(int v, const BatchItem *items, const BatchTile *tiles, int n_tiles,
-                             int n_blocks, hipStream_t s) {
+int bf16x3_launch_persistent(int v, const TileQueue *queue, int n_blocks, hipStream_t s) {
   const Variant &V = kVariants[v];
-  TDX_HIP(hipFuncSetAttribute(V.pers_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)V.lds));
-  void *args[] = {(void *)&items, (void *)&tiles, (void *)&n_tiles};
-  TDX_HIP(hipLaunchKernel(V.pers_fn, dim3(n_blocks), dim3(64 * V.waves), args, V.lds, s));
+  const size_t lds = V.lds + 16;  // the tile-index word after the buffers
+  TDX_HIP(hipFuncSetAttribute(V.pers_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  void *args[] = {(void *)&queue};
+  TDX_HIP(hipLaunchKernel(V.pers_fn, dim3(n_blocks), dim3(64 * V.waves), args, lds, s));
   return TDX_OK;
 }
 
