@@ -41,8 +41,10 @@ struct TileQueue {
 };
 
 // Rows and columns [0, nm) of a basis run in main tiles, rows nm .. n_g - 1
-// (tail of them) in tail tiles; nm = ld and tail = 0 when n_g is a multiple
-// of 16 or the variant is pipelined.
+// (tail of them, at most 16) in tail tiles.  nm = 16 floor(n_g / 16) when
+// n_g is not a multiple of 16; for a multiple of 16, nm = n_g - 16 and
+// tail = 16 when the last block would otherwise be a main column tile of
+// its own, else nm = ld and tail = 0; a pipelined variant has no tail.
 struct TailSplit {
   int nm, tail;
 };

@@ -158,7 +158,8 @@ struct DmaPlan {
 
 // Rows of a tail tile.  When n_g is not a multiple of 16 the basis rows (and
 // columns) nm .. n_g - 1, nm = 16 floor(n_g / 16), would fill only part of a
-// 16-row MFMA block.  chi0 = H_R + i H_A with the Hermitian
+// 16-row MFMA block (and a whole last block that would be a column tile of
+// its own is taken the same way, nm = n_g - 16).  chi0 = H_R + i H_A with the Hermitian
 //   H_R = pref sum_t Re(w_t) rho_t rho_t^H,  H_A = pref sum_t Im(w_t) rho_t rho_t^H,
 // so the main tiles cover rows and columns [0, nm) only, and tail tiles
 // compute the rows nm + g of H_R and H_A over every column: virtual rows
@@ -894,8 +895,14 @@ int bf16x3_variant_occupancy(int v) { return kVariants[v].occ; }
 
 TailSplit bf16x3_split(int v, int n_g) {
   const int ld = (n_g + 15) / 16 * 16;
-  if (kVariants[v].pipe || n_g % 16 == 0) return TailSplit{ld, 0};
-  return TailSplit{n_g / 16 * 16, n_g % 16};
+  if (kVariants[v].pipe) return TailSplit{ld, 0};
+  if (n_g % 16 != 0) return TailSplit{n_g / 16 * 16, n_g % 16};
+  // a whole last block that would make a main column tile of its own (the
+  // 16-proton basis, N_G = 304: 19 blocks as 9 + 9 + 1) runs as 16 tail
+  // rows instead, so the main tiles keep full width
+  const int blocks = n_g / 16;
+  if (blocks > 1 && blocks % kVariants[v].sub == 1) return TailSplit{n_g - 16, 16};
+  return TailSplit{ld, 0};
 }
 
 int bf16x3_tail_groups(int v, int n_w, int tail) {

@@ -98,3 +98,49 @@ def test_small_cases_match_the_oracle(tdx, ctx, crystal, case):
         err = np.max(np.abs(c0 - ref)) / np.max(np.abs(ref))
         _say(f"  {prec}: {err:.2e}")
         assert err < tol
+
+
+@pytest.mark.parametrize("variant", [0, 2, None])
+def test_whole_last_block_as_tail_rows(tdx, ctx, crystal, variant):
+    """A basis of whole 16-row blocks whose last block would make a column
+    tile of its own runs that block as 16 tail rows (N_G = 80: five blocks,
+    4 + 1 for the 2 x 4 tile of variant 0, 2 + 2 + 1 for the 4 x 2 tile of
+    variant 2; the default 2 x 9 tile covers all five in one).  chi0 in the
+    grid and persistent forms against the oracle on q2 of the crystal."""
+    import torch
+    w0, st, ost, _, _, _ = crystal
+    w = w0.with_(qs=(w0.qs[2],), ecut_chi=(6.0,), temperatures=(w0.temperatures[2],),
+                 omega_max=(w0.omega_max[2],))
+    basis, _ = tdx.response_basis(w.cell, w.kgrid, w.qs[0], w.ecut_chi[0])
+    n_g = len(basis)
+    assert n_g == 80
+    _say(f"whole last block: N_G {n_g}, variant {variant}")
+    omegas = w.omega_grid(0)[::7]
+    obasis, ref = _oracle_chi0(ost, w, None, omegas)
+    pos = {tuple(x): i for i, x in enumerate(obasis)}
+    p = np.array([pos[tuple(x)] for x in basis])
+    ref = ref[:, p][:, :, p]
+    tdx.occupations(ctx, st, w.temperatures[0], w.n_electrons, w.f_trunc)
+    tr = tdx.transitions(ctx, st, w.qs[0], w.f_trans_thr)
+    gb = torch.from_numpy(basis).cuda()
+    om = torch.as_tensor(omegas, device="cuda")
+    v0, sl0 = tdx.chi0_get_config(ctx, n_g)
+    if variant is not None:
+        tdx.chi0_set_config(ctx, n_g, variant, sl0)
+    try:
+        P = tdx.pair_density(ctx, st, w.qs[0], tr, gb, "bf16x3")
+        c0 = tdx.chi0(ctx, tr, P, n_g, "bf16x3", om, w.eta, st.chi0_pref)
+        it = tdx.Chi0Item(tr, P, n_g, om, w.eta, st.chi0_pref)
+        plan = tdx.Chi0Plan(ctx, [it], "bf16x3")
+        plan.launch()
+        torch.cuda.synchronize()
+        c1 = it.out.clone()
+        plan.close()
+    finally:
+        tdx.chi0_set_config(ctx, n_g, v0, sl0)
+        tdx.occupations(ctx, st, w0.temperatures[0], w0.n_electrons, w0.f_trunc)
+    for name, c in (("grid", c0), ("persistent", c1)):
+        c = c.cpu().numpy()
+        err = np.max(np.abs(c - ref)) / np.max(np.abs(ref))
+        _say(f"  {name}: {err:.2e}")
+        assert err < 1e-4
