@@ -773,7 +773,20 @@ __global__ void __launch_bounds__(64 * NW, OCC)
   // cover the rest); grid: n_tail + nx ny slices workgroups
   typedef Cfg<WPW, SUB, CHUNK, NW> C;
   extern __shared__ unsigned int lds[];
-  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  // XCD x runs a contiguous range of logical tiles; its range holds an
+  // eighth of the tail tiles (first) and then its share of the main tiles,
+  // so the costlier tail tiles are spread over the XCDs
+  const int id = blockIdx.x, per = gridDim.x / 8;
+  int L;
+  if (id < 8 * per && (n_tail + 7) / 8 <= per) {
+    const int x = id % 8, j = id / 8;
+    const int t0 = (int)((long long)n_tail * x / 8), t1 = (int)((long long)n_tail * (x + 1) / 8);
+    L = j < t1 - t0 ? t0 + j : n_tail + x * per - t0 + (j - (t1 - t0));
+  } else if (id >= 8 * per && (n_tail + 7) / 8 <= per) {
+    L = id;
+  } else {
+    L = xcd_logical(id, gridDim.x);
+  }
   if (L < n_tail) {
     const int a = L % ntg, c = (L / ntg) % nct, bz = L / (ntg * nct);
     const long long t_lo = (long long)bz * slice_len;
