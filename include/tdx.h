@@ -310,9 +310,9 @@ typedef struct tdx_chi0_plan tdx_chi0_plan;
 /* Build the work queue of a ragged batch: for TDX_PREC_BF16X3 every
  * (q, frequency block, G block, G' block, transition slice) tile, ordered
  * by predicted cost, costliest first, plus the slice-partial buffers and the
- * queue counter, in one device allocation owned by the plan.  A lone item is
- * sliced as a grid launch would slice it; several items share one slice-count
- * factor on their minimum counts, chosen for the least predicted queue time.  The tile shape is the configured one (see
+ * queue counter, in one device allocation owned by the plan.  Every item is
+ * sliced as a grid launch of it would be, so the plan's results are bitwise
+ * those of one tdx_chi0 call per item (same configuration).  The tile shape is the configured one (see
  * tdx_chi0_set_config / tdx_autotune_chi0) of the widest basis in the batch.
  * Other precisions run their items one launch each.  Items must stay valid
  * until the plan is destroyed. */

@@ -365,14 +365,11 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
   p->variant = v;
   int wb, cols;
   bf16x3_variant_shape(v, &wb, &cols);
-  // slice counts: a list alone takes its own choice; pooled lists share one
-  // queue and take the common factor f = 1, 9/8, ..., 4 on their minimum
-  // counts (each held in its range) that minimises the queue's makespan
+  // slice counts: each list as a grid launch of it would slice it, so the
+  // plan's results are bitwise those of one launch per list
   const int slots = bf16x3_variant_occupancy(v) * std::max(ctx->n_cu, 1);
   std::vector<long long> slen(n_items);
   std::vector<SliceTiles> stiles(n_items);
-  std::vector<SliceRange> range(n_items);
-  long long pooled_tiles = 0;
   for (int i = 0; i < n_items; ++i) {
     const tdx_chi0_item &it = items[i];
     const int ld = (it.n_g + 15) / 16 * 16;
@@ -383,33 +380,7 @@ int tdx_chi0_plan_create(tdx_ctx *ctx, const tdx_chi0_item *items, int n_items, 
     const size_t bytes = sizeof(double2) * ((size_t)it.n_w * it.n_g * it.n_g +
                                             (size_t)it.n_w * sp.tail * 2 * ld);
     int ns;
-    slicing(ctx, it.n_trans, sl, stiles[i], n_items == 1 ? slots : 0, bytes, &slen[i], &ns);
-    range[i] = slice_range(it.n_trans, sl, stiles[i], bytes);
-    pooled_tiles += range[i].ns0 * (stiles[i].main + stiles[i].tail);
-  }
-  if (n_items > 1 && ctx->slice_len <= 0 && pooled_tiles < 64LL * slots) {
-    auto lens = [&](int j, std::vector<long long> &out) {
-      for (int i = 0; i < n_items; ++i) {
-        const long long ns = std::min(
-            range[i].ns_hi,
-            std::max(range[i].ns0, (long long)std::ceil(range[i].ns0 * (1.0 + j / 8.0))));
-        out[i] = chunk_len(items[i].n_trans, ns);
-      }
-    };
-    std::vector<double> t(25);
-    std::vector<long long> l(n_items);
-    for (int j = 0; j < 25; ++j) {
-      lens(j, l);
-      std::vector<std::pair<double, long long>> g;
-      for (int i = 0; i < n_items; ++i) add_tile_groups(g, items[i].n_trans, l[i], stiles[i]);
-      t[j] = makespan(g, slots);
-    }
-    const double best = *std::min_element(t.begin(), t.end());
-    for (int j = 0; j < 25; ++j)
-      if (t[j] <= 1.005 * best) {
-        lens(j, slen);
-        break;
-      }
+    slicing(ctx, it.n_trans, sl, stiles[i], slots, bytes, &slen[i], &ns);
   }
   std::vector<BatchItem> bi(n_items);
   std::vector<ReduceItem> ri(n_items);
