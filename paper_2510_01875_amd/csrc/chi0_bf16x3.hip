@@ -773,16 +773,21 @@ __global__ void __launch_bounds__(64 * NW, OCC)
   // cover the rest); grid: n_tail + nx ny slices workgroups
   typedef Cfg<WPW, SUB, CHUNK, NW> C;
   extern __shared__ unsigned int lds[];
-  // XCD x runs a contiguous range of logical tiles; its range holds an
-  // eighth of the tail tiles (first) and then its share of the main tiles,
-  // so the costlier tail tiles are spread over the XCDs
+  // XCD x runs a contiguous range of logical tiles.  The tail tiles come
+  // first in the logical order, so XCD 0's range holds them all; where they
+  // would load it with more than a tenth of a range's work beyond the
+  // others' (a tail tile costs about 1.35 main ones), each range starts with
+  // an eighth of them instead (fcc_c2 q0, 240 tail tiles in ranges of 414:
+  // 4 % faster; with 108 in ranges of 877 the spread took 40 % more L2
+  // misses and 1 % longer, so smaller shares stay in XCD 0)
   const int id = blockIdx.x, per = gridDim.x / 8;
+  const bool spread = (n_tail + 7) / 8 <= per && 7LL * n_tail > 2LL * per;
   int L;
-  if (id < 8 * per && (n_tail + 7) / 8 <= per) {
+  if (spread && id < 8 * per) {
     const int x = id % 8, j = id / 8;
     const int t0 = (int)((long long)n_tail * x / 8), t1 = (int)((long long)n_tail * (x + 1) / 8);
     L = j < t1 - t0 ? t0 + j : n_tail + x * per - t0 + (j - (t1 - t0));
-  } else if (id >= 8 * per && (n_tail + 7) / 8 <= per) {
+  } else if (spread) {
     L = id;
   } else {
     L = xcd_logical(id, gridDim.x);
