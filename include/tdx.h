@@ -353,6 +353,17 @@ int tdx_chi0_get_config(tdx_ctx *ctx, int prec, int n_g, int *variant, int *slic
  * partials are reduced in a fixed order, so the length fixes the rounding
  * order and the partial workspace (slices x n_w x n_g^2 x 16 bytes). */
 int tdx_chi0_set_slice_length(tdx_ctx *ctx, int64_t n);
+/* The slicing a split-BF16 contraction takes with no fixed length set (host
+ * only, no device or context needed): for a list of n_trans transitions, a
+ * basis of n_g vectors, n_w frequencies, tile variant `variant`
+ * (0 .. tdx_chi0_variants - 1), minimum slice length 2^slice_log2 and n_cu
+ * compute units, the slice length (*slice_len, a multiple of the 32-transition
+ * chunk) and count (*slices) whose rounds of tiles leave the least predicted
+ * idle time; the count lies between the minimum (2^slice_log2 transitions a
+ * slice, at least 2048 tiles) and 4 times it.  TDX_ERR_INVALID_ARG for null
+ * outputs or sizes out of range. */
+int tdx_chi0_bf16x3_slicing(int n_cu, int variant, int64_t n_trans, int n_g, int n_w,
+                            int slice_log2, int64_t *slice_len, int *slices);
 
 /* Time every variant of `prec` on the probe item (its first max_trans
  * transitions, P in that precision's layout; probe->chi0 is overwritten),

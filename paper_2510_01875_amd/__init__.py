@@ -141,6 +141,9 @@ _batched = _sig("tdx_chi0_batched", [C.c_void_p, C.POINTER(Chi0ItemC), C.c_int, 
 _variants = _sig("tdx_chi0_variants", [C.c_int, C.POINTER(C.c_int)])
 _set_cfg = _sig("tdx_chi0_set_config", [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int])
 _set_slice = _sig("tdx_chi0_set_slice_length", [C.c_void_p, C.c_int64])
+_bf_slicing = _sig("tdx_chi0_bf16x3_slicing", [C.c_int, C.c_int, C.c_int64, C.c_int, C.c_int,
+                                                C.c_int, C.POINTER(C.c_int64),
+                                                C.POINTER(C.c_int)])
 _get_cfg = _sig("tdx_chi0_get_config", [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int),
                                         C.POINTER(C.c_int)])
 _autotune = _sig("tdx_autotune_chi0", [C.c_void_p, C.POINTER(Chi0ItemC), C.c_int, C.c_int64,
@@ -219,7 +222,7 @@ EXPORTED = ["tdx_create", "tdx_destroy", "tdx_last_error", "tdx_abi_version",
             "tdx_dyson", "tdx_dyson_noalloc", "tdx_dyson_noalloc_max_bytes", "tdx_dsf",
             "tdx_itcf", "tdx_itcf_metrics", "tdx_eta_reference", "tdx_dielectric", "tdx_sg_filter", "tdx_derivative_psd", "tdx_sg_scores", "tdx_residual_itcf", "tdx_sg_select", "tdx_kg_dsf", "tdx_kg_work_bytes", "tdx_kg_conductivity", "tdx_chi0_plan_create", "tdx_chi0_plan_launch",
             "tdx_chi0_plan_destroy", "tdx_chi0_batched", "tdx_chi0_variants",
-            "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_chi0_set_slice_length", "tdx_autotune_chi0", "tdx_tune_save",
+            "tdx_chi0_set_config", "tdx_chi0_get_config", "tdx_chi0_set_slice_length", "tdx_chi0_bf16x3_slicing", "tdx_autotune_chi0", "tdx_tune_save",
             "tdx_tune_load", "tdx_dyson_work_bytes", "tdx_dyson_async", "tdx_itcf_vjp",
             "tdx_dsf_vjp", "tdx_dyson_vjp", "tdx_chi0_vjp", "tdx_weights_vjp",
             "tdx_occupations_vjp", "tdx_pair_density_vjp", "tdx_potential_vjp",
@@ -1015,6 +1018,16 @@ def chi0_set_config(ctx: Context, n_g: int, variant: int, slice_log2: int, prec:
 def chi0_set_slice_length(ctx: Context, n: int):
     """Fixed chi0 slice length for later calls on ctx (0: chosen per call)."""
     check(_set_slice(ctx.handle, int(n)))
+
+
+def chi0_bf16x3_slicing(n_cu: int, variant: int, n_trans: int, n_g: int, n_w: int,
+                        slice_log2: int = 20):
+    """(slice length, slice count) a split-BF16 contraction takes with no fixed
+    length (host only; tdx_chi0_bf16x3_slicing)."""
+    ln, ns = C.c_int64(), C.c_int()
+    check(_bf_slicing(int(n_cu), int(variant), int(n_trans), int(n_g), int(n_w),
+                      int(slice_log2), C.byref(ln), C.byref(ns)))
+    return ln.value, ns.value
 
 
 def chi0_get_config(ctx: Context, n_g: int, prec: str = "bf16x3"):

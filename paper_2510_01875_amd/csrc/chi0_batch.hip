@@ -183,11 +183,12 @@ SliceRange slice_range(long long n_trans, int slice_log2, const SliceTiles &tile
 // count in slice_range that minimises the makespan is taken, the fewest
 // within 0.5 % of the best.  Lists of many rounds keep the minimum, whose
 // last round is a small share.
-void slicing(const tdx_ctx *ctx, long long n_trans, int slice_log2, const SliceTiles &tiles,
-             int slots, size_t bytes_per_slice, long long *slice_len, int *slices) {
+void slicing_fixed(long long fixed_len, long long n_trans, int slice_log2,
+                   const SliceTiles &tiles, int slots, size_t bytes_per_slice,
+                   long long *slice_len, int *slices) {
   long long len;
-  if (ctx->slice_len > 0) {
-    len = (ctx->slice_len + kChunkAlign - 1) / kChunkAlign * kChunkAlign;
+  if (fixed_len > 0) {
+    len = (fixed_len + kChunkAlign - 1) / kChunkAlign * kChunkAlign;
   } else {
     const SliceRange r = slice_range(n_trans, slice_log2, tiles, bytes_per_slice);
     long long best_ns = r.ns0;
@@ -212,6 +213,12 @@ void slicing(const tdx_ctx *ctx, long long n_trans, int slice_log2, const SliceT
   }
   *slice_len = len;
   *slices = (int)std::max<long long>(1, (n_trans + len - 1) / len);
+}
+
+void slicing(const tdx_ctx *ctx, long long n_trans, int slice_log2, const SliceTiles &tiles,
+             int slots, size_t bytes_per_slice, long long *slice_len, int *slices) {
+  slicing_fixed(ctx->slice_len, n_trans, slice_log2, tiles, slots, bytes_per_slice, slice_len,
+                slices);
 }
 
 SliceTiles slice_tiles(int v, int n_w, int n_g) {
@@ -315,6 +322,29 @@ int tdx_chi0_set_slice_length(tdx_ctx *ctx, int64_t n) {
   TDX_REQUIRE(n >= 0 && n <= (1LL << 40), TDX_ERR_INVALID_ARG, "bad slice length %lld",
               (long long)n);
   ctx->slice_len = (long long)n;
+  return TDX_OK;
+}
+
+int tdx_chi0_bf16x3_slicing(int n_cu, int variant, int64_t n_trans, int n_g, int n_w,
+                            int slice_log2, int64_t *slice_len, int *slices) {
+  clear_error();
+  TDX_REQUIRE(slice_len && slices, TDX_ERR_INVALID_ARG, "null argument");
+  TDX_REQUIRE(n_cu > 0 && n_trans > 0 && n_g > 0 && n_w > 0, TDX_ERR_INVALID_ARG,
+              "bad sizes (n_cu %d, n_trans %lld, n_g %d, n_w %d)", n_cu, (long long)n_trans, n_g,
+              n_w);
+  TDX_REQUIRE(variant >= 0 && variant < bf16x3_variant_count(), TDX_ERR_INVALID_ARG,
+              "bad variant %d", variant);
+  TDX_REQUIRE(slice_log2 >= 10 && slice_log2 <= 30, TDX_ERR_INVALID_ARG, "bad slice_log2");
+  const int ld = (n_g + 15) / 16 * 16;
+  const TailSplit sp = bf16x3_split(variant, n_g);
+  long long len;
+  int ns;
+  slicing_fixed(0, n_trans, slice_log2, slice_tiles(variant, n_w, n_g),
+                bf16x3_variant_occupancy(variant) * n_cu,
+                sizeof(double2) * ((size_t)n_w * n_g * n_g + (size_t)n_w * sp.tail * 2 * ld),
+                &len, &ns);
+  *slice_len = len;
+  *slices = ns;
   return TDX_OK;
 }
 
