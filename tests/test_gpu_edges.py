@@ -104,8 +104,9 @@ def test_small_cases_match_the_oracle(tdx, ctx, crystal, case):
 def test_whole_last_block_as_tail_rows(tdx, ctx, crystal, variant):
     """A basis of whole 16-row blocks whose last block would make a column
     tile of its own runs that block as 16 tail rows (N_G = 80: five blocks,
-    4 + 1 for the 2 x 4 tile of variant 0, 2 + 2 + 1 for the 4 x 2 tile of
-    variant 2; the default 2 x 9 tile covers all five in one).  chi0 in the
+    4 + 1 for the 4 x 4 tile of variant 0, 2 + 2 + 1 for the 4 x 2 tile of
+    variant 2, so both take the tail rows; the default 2 x 9 tile covers all
+    five in one).  chi0 in the
     grid and persistent forms against the oracle on q2 of the crystal."""
     import torch
     w0, st, ost, _, _, _ = crystal
