@@ -145,3 +145,29 @@ def test_whole_last_block_as_tail_rows(tdx, ctx, crystal, variant):
         err = np.max(np.abs(c - ref)) / np.max(np.abs(ref))
         _say(f"  {name}: {err:.2e}")
         assert err < 1e-4
+
+
+def test_slicing_query_matches_the_launch(tdx, ctx, crystal):
+    """The host query tdx_chi0_bf16x3_slicing returns the slice length the
+    launch takes by itself: fixing the context's slice length to it gives
+    bitwise the chi0 of the automatic choice (another length would change
+    the rounding order of the FP32 runs and the FP64 slice reduction)."""
+    import torch
+    w, st, _, basis, _, gb = crystal
+    n_g = len(basis)
+    tr = tdx.transitions(ctx, st, w.qs[0], w.f_trans_thr)
+    om = torch.as_tensor(w.omega_grid(0), device="cuda")
+    P = tdx.pair_density(ctx, st, w.qs[0], tr, gb, "bf16x3")
+    auto = tdx.chi0(ctx, tr, P, n_g, "bf16x3", om, w.eta, st.chi0_pref)
+    v, sl = tdx.chi0_get_config(ctx, n_g)
+    v = 9 if v < 0 else v  # the default tile
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    length, ns = tdx.chi0_bf16x3_slicing(n_cu, v, len(tr), n_g, om.shape[0], sl)
+    _say(f"slicing query: {len(tr)} transitions, N_G {n_g}, {om.shape[0]} frequencies, "
+         f"{n_cu} CUs -> {ns} slices of {length}")
+    tdx.chi0_set_slice_length(ctx, length)
+    try:
+        fixed = tdx.chi0(ctx, tr, P, n_g, "bf16x3", om, w.eta, st.chi0_pref)
+    finally:
+        tdx.chi0_set_slice_length(ctx, 0)
+    assert torch.equal(auto, fixed)
