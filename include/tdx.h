@@ -282,7 +282,12 @@ int tdx_pair_density_async(tdx_ctx *ctx, const tdx_states *st, const int qj[3],
  * chi0_pref field; another value scales the result).  The weights are
  * formed in FP64 in-kernel; the products run in `prec` (see TDX_PREC_*).
  * omega: device [n_w] FP64.  chi0: device complex128 [n_w][n_g][n_g].
- * The sum over t is split into fixed chunks reduced in a fixed order. */
+ * The sum over t is split into fixed chunks reduced in a fixed order, so a
+ * call is bitwise reproducible on one device; the split-BF16 slice count
+ * depends on the list's shape and the device's CU count
+ * (tdx_chi0_bf16x3_slicing), and a length fixed with
+ * tdx_chi0_set_slice_length makes the rounding order the same on every
+ * device. */
 int tdx_chi0(tdx_ctx *ctx, const tdx_translist *tl, int64_t n_trans,
              const void *P, int n_g, int prec, const double *omega, int n_w,
              double eta, double pref, double *chi0, tdx_stream stream);
